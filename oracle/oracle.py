@@ -1,0 +1,190 @@
+"""Python face of the C oracle (``eg_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: this module is the oracle.  Only ``tests/``, the
+smoke entry point and the benchmark's CPU-baseline leg may import it.  It does
+not import the GPU library and the GPU library does not import it.
+
+``extremum_graph`` returns the whole extremum graph of a float32 array
+(C order, ``shape[0]`` slowest) as a dict of numpy arrays:
+
+* ``ptr``         steepest-ascent target of every vertex (itself at maxima)
+* ``beta``        number of upper-link components of every vertex (Table 1)
+* ``labels``      maximum reached from every vertex (its descending manifold)
+* ``maxima``      ascending ids with beta == 0
+* ``saddles``     ascending ids with beta >= 2
+* ``saddle_beta`` beta of each saddle
+* ``arc_offsets`` / ``arc_maxima``  CSR: the sorted distinct maxima reached
+  from the reps (highest vertex of each upper-link component) of each saddle
+
+``minima=True`` computes the minimum graph (the same steps under the reversed
+order).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+_I64P = ctypes.POINTER(ctypes.c_int64)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_build.LIB):
+        _build.build()
+    _lib = _bind(ctypes.CDLL(_build.LIB))
+    return _lib
+
+
+def use_library(path):
+    """Point this module at another build of ``eg_oracle.c`` (the mutation
+    tests compile deliberately broken copies); ``None`` restores the default.
+    Returns the previous library handle."""
+    global _lib
+    prev = _lib
+    _lib = None if path is None else _bind(ctypes.CDLL(path))
+    return prev
+
+
+def _bind(lib):
+    vp = ctypes.c_void_p
+    lib.ego_num_threads.restype = ctypes.c_int
+    lib.ego_neighbours.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int64, vp]
+    lib.ego_neighbours.restype = ctypes.c_int
+    lib.ego_vertex.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int64, vp, vp]
+    lib.ego_vertex.restype = ctypes.c_int
+    lib.ego_label_of.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int64]
+    lib.ego_label_of.restype = ctypes.c_int64
+    lib.ego_classify.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, vp]
+    lib.ego_classify.restype = ctypes.c_int
+    lib.ego_labels.argtypes = [vp, ctypes.c_int64, vp]
+    lib.ego_labels.restype = ctypes.c_int
+    lib.ego_arcs.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, vp, ctypes.c_int64,
+                             vp, vp, ctypes.c_int64, vp]
+    lib.ego_arcs.restype = ctypes.c_int
+    return lib
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _prep(f):
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    if f.ndim < 1:
+        raise OracleError("need at least one axis")
+    dims = np.asarray(f.shape, dtype=np.int64)
+    return f, dims
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def num_threads() -> int:
+    return int(_load().ego_num_threads())
+
+
+def neighbours(shape, v: int) -> np.ndarray:
+    """Neighbour ids of vertex ``v`` (Alg. 1 applied to every offset)."""
+    lib = _load()
+    dims = np.asarray(shape, dtype=np.int64)
+    dummy = np.zeros(1, dtype=np.float32)
+    out = np.zeros(600, dtype=np.int64)
+    k = lib.ego_neighbours(_p(dummy), len(shape), _p(dims), int(v), _p(out))
+    if k < 0:
+        raise OracleError("bad vertex")
+    return np.sort(out[:k])
+
+
+def vertex(f, v: int, minima: bool = False):
+    """(ptr, beta, reps) of one vertex; reps ascending."""
+    lib = _load()
+    f, dims = _prep(f)
+    p = np.zeros(1, dtype=np.int64)
+    reps = np.zeros(600, dtype=np.int64)
+    b = lib.ego_vertex(_p(f), f.ndim, _p(dims), int(minima), int(v), _p(p), _p(reps))
+    if b < 0:
+        raise OracleError("bad vertex")
+    return int(p[0]), int(b), reps[:b].copy()
+
+
+def label_of(f, v: int, minima: bool = False) -> int:
+    lib = _load()
+    f, dims = _prep(f)
+    r = lib.ego_label_of(_p(f), f.ndim, _p(dims), int(minima), int(v))
+    if r < 0:
+        raise OracleError("bad vertex")
+    return int(r)
+
+
+def classify(f, minima: bool = False):
+    """Per-vertex (ptr, beta) as int32 arrays of f.size."""
+    lib = _load()
+    f, dims = _prep(f)
+    n = f.size
+    if n >= 2 ** 31:
+        raise OracleError("too many vertices")
+    ptr = np.empty(n, dtype=np.int32)
+    beta = np.empty(n, dtype=np.int32)
+    st = lib.ego_classify(_p(f), f.ndim, _p(dims), int(minima), _p(ptr), _p(beta))
+    if st == 4:
+        raise OracleError("NaN in field")
+    if st != 0:
+        raise OracleError(f"oracle status {st}")
+    return ptr, beta
+
+
+def labels_from_ptr(ptr: np.ndarray) -> np.ndarray:
+    lib = _load()
+    ptr = np.ascontiguousarray(ptr, dtype=np.int32)
+    lab = np.empty_like(ptr)
+    st = lib.ego_labels(_p(ptr), ptr.size, _p(lab))
+    if st != 0:
+        raise OracleError(f"oracle status {st}")
+    return lab
+
+
+def arcs(f, labels: np.ndarray, saddles: np.ndarray, minima: bool = False):
+    lib = _load()
+    f, dims = _prep(f)
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    saddles = np.ascontiguousarray(saddles, dtype=np.int32)
+    offsets = np.zeros(saddles.size + 1, dtype=np.int32)
+    cap = max(16, 3 * saddles.size)
+    while True:
+        am = np.empty(cap, dtype=np.int32)
+        n_arc = np.zeros(1, dtype=np.int64)
+        st = lib.ego_arcs(_p(f), f.ndim, _p(dims), int(minima), _p(labels), _p(saddles),
+                          saddles.size, _p(offsets), _p(am), cap, _p(n_arc))
+        if st == 5:
+            cap = int(n_arc[0])
+            continue
+        if st != 0:
+            raise OracleError(f"oracle status {st}")
+        return offsets, am[: int(n_arc[0])].copy()
+
+
+def extremum_graph(f, minima: bool = False) -> dict:
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    ptr, beta = classify(f, minima)
+    labels = labels_from_ptr(ptr)
+    maxima = np.flatnonzero(beta == 0).astype(np.int32)
+    saddles = np.flatnonzero(beta >= 2).astype(np.int32)
+    offsets, arc_maxima = arcs(f, labels, saddles, minima)
+    return {
+        "ptr": ptr,
+        "beta": beta,
+        "labels": labels,
+        "maxima": maxima,
+        "saddles": saddles,
+        "saddle_beta": beta[saddles].astype(np.int32),
+        "arc_offsets": offsets,
+        "arc_maxima": arc_maxima,
+    }
