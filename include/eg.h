@@ -1,0 +1,155 @@
+/*
+ * eg.h -- C ABI of the MI355X extremum-graph library (libeg_hip.so).
+ *
+ * Computes the extremum graph of a piecewise-linear scalar field sampled on an
+ * n-dimensional grid (n = 1..5), following Ande, Subhash and Natarajan,
+ * "TACHYON: Efficient Shared Memory Parallel Computation of Extremum Graphs":
+ *
+ *   - grid vertices are the integer points of the box dims[0] x ... x dims[n-1],
+ *     stored in row-major (C) order: dims[0] is the slowest axis and the linear
+ *     index of a vertex is its array index (Sec. 3.2, Sec. 4);
+ *   - the grid is split by the Freudenthal tessellation: two vertices are
+ *     adjacent iff their coordinate difference is nonzero with every component
+ *     in {0,1}, or every component in {0,-1} (Alg. 1), giving 2(2^n - 1)
+ *     neighbours; vertices outside the box are absent (the link is truncated);
+ *   - ties are broken by simulated perturbation (Sec. 3.3): u is below v iff
+ *     f[u] < f[v], or f[u] == f[v] and u < v.  IEEE comparison (-0 == +0);
+ *     infinities are ordered normally; NaN is an error;
+ *   - a vertex is a maximum iff its upper link is empty and an (n-1)-saddle iff
+ *     its upper link has at least two connected components (Table 1);
+ *   - the steepest-ascent pointer of a vertex is the highest vertex of its
+ *     upper link, or the vertex itself at a maximum (Sec. 3.3);
+ *   - the label of a vertex is the maximum at the end of its steepest-ascent
+ *     path: the descending manifold containing it (Sec. 2, Alg. 2);
+ *   - for each saddle s and each upper-link component, the path from the
+ *     component's highest vertex ends at a maximum m; the arcs (s, m) form a
+ *     set (Sec. 2, Sec. 3.4 Alg. 2, UpperLinkRep).
+ *
+ * With EG_MINIMA the same is computed for the reversed order (u below v iff v
+ * is below u in the order above): the minimum graph, whose "maxima" are the
+ * minima of f and whose saddles are its 1-saddles (Sec. 2, Sec. 5).
+ *
+ * Conventions shared by every entry point:
+ *   - every buffer named "device" is HIP device memory owned by the caller;
+ *     the library never allocates, frees or synchronises; all work is queued
+ *     on the caller's stream (a hipStream_t passed as void*, NULL = default);
+ *   - argument errors are detected on the host and returned synchronously,
+ *     before anything is queued;
+ *   - data-dependent conditions (NaN in the field, an output buffer that is
+ *     too small) are written to the device header (EG_H_* slots) together
+ *     with the counts that a retry needs; read it after synchronising.
+ */
+#ifndef EG_H
+#define EG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum eg_status {
+    EG_OK = 0,
+    EG_ERR_ARG = 1,       /* host: bad ndim, dims, flags, or a NULL buffer */
+    EG_ERR_TOO_LARGE = 2, /* host: N >= 2^31 vertices, or a capacity >= 2^31 */
+    EG_ERR_WORKSPACE = 3, /* host: workspace NULL, misaligned or smaller than eg_workspace_bytes */
+    EG_ERR_NAN = 4,       /* device header: the field holds a NaN (outputs undefined) */
+    EG_ERR_CAPACITY = 5,  /* device header: an output capacity was too small; counts are the required sizes */
+    EG_ERR_HIP = 6        /* host: a HIP launch failed */
+} eg_status;
+
+/* eg_out.flags */
+#define EG_MINIMA 0x1u /* build the minimum graph instead of the maximum graph */
+
+#define EG_MAX_NDIM 5
+
+/* Slots of the device header (int32 each, EG_H_SLOTS in total). */
+#define EG_H_STATUS 0 /* eg_status of the device-side work */
+#define EG_H_NMAX 1   /* number of maxima (required size of maxima[]) */
+#define EG_H_NSAD 2   /* number of saddles (required size of saddles[], saddle_beta[]) */
+#define EG_H_NARC 3   /* number of arcs (required size of arc_maxima[]); -1 if unknown */
+#define EG_H_NPAIRS 4 /* number of (saddle, component) pairs (required cap_pairs) */
+#define EG_H_PASSES 5 /* pointer-jumping passes that did work */
+#define EG_H_SLOTS 8
+
+/*
+ * Output description for one field.  All pointers are device pointers.
+ *
+ *   labels       [N]            label (vertex id of the maximum) of every vertex
+ *   ptr          [N] or NULL    steepest-ascent pointer of every vertex (optional)
+ *   maxima       [cap_max]      ascending vertex ids of the maxima
+ *   saddles      [cap_sad]      ascending vertex ids of the saddles
+ *   saddle_beta  [cap_sad] or NULL   upper-link component count of each saddle
+ *   arc_offsets  [cap_sad + 1]  CSR row offsets: saddle i owns arc_maxima[arc_offsets[i] ..
+ *                               arc_offsets[i+1]), ascending and distinct
+ *   arc_maxima   [cap_arc]      maxima ids of the arcs
+ *   cap_pairs    capacity for (saddle, upper-link component) pairs, i.e. the sum
+ *                of beta over saddles; sizes part of the workspace
+ *   workspace    device scratch of at least eg_workspace_bytes(...) bytes,
+ *                256-byte aligned; contents need not be initialised
+ *   header       [EG_H_SLOTS] int32 device; written by the library
+ */
+typedef struct eg_out {
+    uint32_t flags;
+    int32_t* labels;
+    int32_t* ptr;
+    int32_t* maxima;
+    int64_t cap_max;
+    int32_t* saddles;
+    int32_t* saddle_beta;
+    int32_t* arc_offsets;
+    int64_t cap_sad;
+    int32_t* arc_maxima;
+    int64_t cap_arc;
+    int64_t cap_pairs;
+    void* workspace;
+    size_t ws_bytes;
+    int32_t* header;
+} eg_out;
+
+/*
+ * Workspace bytes that eg_build needs for a field of the given shape and the
+ * given capacities (the cap_* fields of eg_out).  Pure, host-only.  Returns 0
+ * on invalid arguments (ndim outside [1, EG_MAX_NDIM], a dim < 1, N >= 2^31,
+ * a negative capacity).
+ */
+size_t eg_workspace_bytes(int ndim, const int64_t* dims, int64_t cap_max, int64_t cap_sad,
+                          int64_t cap_pairs);
+
+/*
+ * Extremum graph of one field (Sec. 3: classification, then path tracing).
+ *
+ *   field   device, float32[N], C order, read-only
+ *   ndim    1..EG_MAX_NDIM
+ *   dims    host, int64[ndim], each >= 1, product N < 2^31
+ *   stream  hipStream_t (as void*) on which all work is queued
+ *   out     host struct describing the caller's device buffers (see eg_out)
+ *
+ * Returns EG_OK once the work is queued; the device header then carries the
+ * final status and the counts.  On EG_ERR_CAPACITY every count in the header
+ * is the size needed, except EG_H_NARC which is -1 when the pairs overflowed
+ * (retry with cap_pairs >= EG_H_NPAIRS first).  Outputs are bit-identical for
+ * identical inputs and independent of launch configuration.
+ */
+eg_status eg_build(const float* field, int ndim, const int64_t* dims, void* stream,
+                   const eg_out* out);
+
+/* Human-readable name of a status code (static string). */
+const char* eg_status_string(int status);
+
+/*
+ * Host-only: the neighbour table the kernels use for an n-dimensional grid
+ * (Alg. 1).  Writes k = 2(2^n - 1) rows sorted so that, for any in-bounds
+ * neighbours, row order equals linear-index order: offsets[j * ndim + i] in
+ * {-1,0,1} is the coordinate difference on axis i, adjacency[j] bit l is set
+ * iff neighbours j and l are adjacent to each other (a link edge).  Returns k,
+ * or -1 for ndim outside [1, EG_MAX_NDIM].  Buffers may be NULL to query k.
+ */
+int eg_link_table(int ndim, int8_t* offsets, uint64_t* adjacency);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EG_H */

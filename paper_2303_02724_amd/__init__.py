@@ -15,10 +15,8 @@ __all__ = ["eg", "workloads"]
 
 
 def __getattr__(name):
-    if name == "eg":
-        from . import eg
-        return eg
-    if name == "workloads":
-        from . import workloads
-        return workloads
+    if name in __all__:
+        import importlib
+
+        return importlib.import_module(f"{__name__}.{name}")
     raise AttributeError(name)

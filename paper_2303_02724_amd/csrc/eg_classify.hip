@@ -1,0 +1,323 @@
+// eg_classify.hip -- per-vertex classification, labels and saddle reps.
+//
+// k_classify_generic  stages (a) and (c) of the method for any n = 1..5: one
+//   thread per vertex reads its closed neighbourhood, forms the upper-link
+//   mask (Sec. 3.3), the steepest-ascent pointer (highest upper-link vertex,
+//   Sec. 3.3) and decides maximum (empty upper link) / saddle (>= 2
+//   components, Table 1) with a bit-parallel BFS over the link edges.
+// k_jump  stage (b): pointer jumping on the label array until every entry
+//   names a maximum (the end of the walk of Alg. 2).
+// k_reps  stage (d), first half: for every saddle, the highest vertex of each
+//   upper-link component (UpperLinkRep, Sec. 3.4) and the label it reaches,
+//   emitted as sortable (saddle, maximum) keys plus one marker per saddle
+//   that carries its component count.
+#include "eg_internal.h"
+
+namespace eg {
+
+__global__ void k_init(uint32_t* __restrict__ ctr, int32_t* __restrict__ header)
+{
+    const int i = threadIdx.x;
+    if (i < C_SLOTS) ctr[i] = 0;
+    if (header && i < EG_H_SLOTS) header[i] = 0;
+}
+
+hipError_t launch_init(uint32_t* ctr, int32_t* header, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, s, ctr, header);
+    return hipGetLastError();
+}
+
+// Visit the closed neighbourhood of v in the order in which later vertices
+// win ties; fills the upper-link mask and the steepest-ascent target.
+template <int NDIM, bool MINMODE>
+__device__ __forceinline__ void scan_neighbourhood(const float* __restrict__ f, const LinkTable& t, int v,
+                                                   uint32_t bits, uint32_t uv, uint64_t& up, int& best)
+{
+    constexpr int K = 2 * ((1 << NDIM) - 1);
+    uint32_t best_u = 0;
+    best = v;
+    auto visit = [&](int j) {
+        if ((bits & t.forb[j]) == 0) {
+            const int u_id = v + t.lin[j];
+            const uint32_t u = mode_key<MINMODE>(f[u_id]);
+            const bool above = row_wins_tie<MINMODE>(j, K) ? (u >= uv) : (u > uv);
+            up |= uint64_t(above) << j;
+            if (u >= best_u) {
+                best_u = u;
+                best = u_id;
+            }
+        }
+    };
+    auto self = [&]() {
+        if (uv >= best_u) {
+            best_u = uv;
+            best = v;
+        }
+    };
+    if (!MINMODE) {
+#pragma unroll
+        for (int j = 0; j < K / 2; ++j) visit(j);
+        self();
+#pragma unroll
+        for (int j = K / 2; j < K; ++j) visit(j);
+    } else {
+#pragma unroll
+        for (int j = K - 1; j >= K / 2; --j) visit(j);
+        self();
+#pragma unroll
+        for (int j = K / 2 - 1; j >= 0; --j) visit(j);
+    }
+}
+
+template <int NDIM>
+__device__ __forceinline__ uint32_t boundary_bits(const Grid& g, int v)
+{
+    uint32_t bits = 0;
+    int rem = v;
+#pragma unroll
+    for (int i = NDIM - 1; i >= 0; --i) {
+        const int d = g.dims[i];
+        const int c = rem % d;
+        rem /= d;
+        bits |= boundary_bit(c, d, i);
+    }
+    return bits;
+}
+
+template <int NDIM, bool MINMODE>
+__global__ __launch_bounds__(256) void k_classify_generic(const float* __restrict__ f, Grid g, LinkTable t,
+                                                          int32_t* __restrict__ lab, int32_t* __restrict__ ptr,
+                                                          uint32_t* __restrict__ ctr, uint32_t* __restrict__ umax,
+                                                          uint32_t cap_max, uint32_t* __restrict__ usad,
+                                                          uint32_t cap_sad)
+{
+    constexpr int K = 2 * ((1 << NDIM) - 1);
+    __shared__ uint64_t s_adj[K];
+    for (int i = threadIdx.x; i < K; i += blockDim.x) s_adj[i] = t.adj[i];
+    __syncthreads();
+
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    bool is_max = false, is_sad = false, nan = false;
+    if (v < g.N) {
+        const uint32_t bits = boundary_bits<NDIM>(g, v);
+        const float fv = f[v];
+        nan = fv != fv;
+        const uint32_t uv = mode_key<MINMODE>(fv);
+        uint64_t up = 0;
+        int best;
+        scan_neighbourhood<NDIM, MINMODE>(f, t, v, bits, uv, up, best);
+        is_max = up == 0;
+        if (!is_max) is_sad = closure(up & (~up + 1), up, s_adj) != up;
+        lab[v] = best;
+        if (ptr) ptr[v] = best;
+    }
+    wave_append(is_max, (uint32_t)v, &ctr[C_NMAX], umax, cap_max);
+    wave_append(is_sad, (uint32_t)v, &ctr[C_NSAD], usad, cap_sad);
+    if (__ballot(nan) != 0 && __lane_id() == 0) atomicOr(&ctr[C_NAN], 1u);
+}
+
+template <int NDIM, bool MINMODE>
+static void launch_classify_t(const float* f, const Grid& g, const LinkTable& t, int32_t* lab, int32_t* ptr,
+                              const Work& w, int64_t cap_max, int64_t cap_sad, hipStream_t s)
+{
+    const int blocks = (int)((g.N + 255) / 256);
+    hipLaunchKernelGGL((k_classify_generic<NDIM, MINMODE>), dim3(blocks), dim3(256), 0, s, f, g, t, lab, ptr, w.ctr,
+                       w.umax, (uint32_t)cap_max, w.usad, (uint32_t)cap_sad);
+}
+
+hipError_t launch_classify(const float* f, const Grid& g, const LinkTable& t, bool minima, int32_t* lab,
+                           int32_t* ptr, const Work& w, int64_t cap_max, int64_t cap_sad, hipStream_t s)
+{
+#define EG_CASE(N)                                                                  \
+    case N:                                                                         \
+        if (minima)                                                                 \
+            launch_classify_t<N, true>(f, g, t, lab, ptr, w, cap_max, cap_sad, s);  \
+        else                                                                        \
+            launch_classify_t<N, false>(f, g, t, lab, ptr, w, cap_max, cap_sad, s); \
+        break;
+    switch (g.ndim) {
+        EG_CASE(1)
+        EG_CASE(2)
+        EG_CASE(3)
+        EG_CASE(4)
+        EG_CASE(5)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef EG_CASE
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ labels
+
+// One pass of pointer jumping.  lab[v] always names a vertex on v's
+// steepest-ascent path, and maxima are exactly the fixed points, so entries
+// may be updated in place while other threads read them: any value read is a
+// valid later point of the same path.  Each pass follows at most kJumpHops
+// pointers per vertex; a pass that stops short raises its flag and the next
+// pass runs.  After pass p every entry has advanced kJumpHops^p steps or
+// reached its maximum, so kJumpPasses passes cover any path in a grid of
+// fewer than 2^31 vertices.
+__global__ __launch_bounds__(256) void k_jump(int32_t* lab, int32_t N, uint32_t* __restrict__ ctr, int pass)
+{
+    if (pass > 0 && __hip_atomic_load(&ctr[C_JUMP + pass - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        return;
+    bool notdone = false;
+    const int stride = gridDim.x * blockDim.x;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < N; v += stride) {
+        int l = lab[v];
+        int m = lab[l];
+        if (m == l) continue;
+        int h = 0;
+        do {
+            l = m;
+            m = lab[l];
+            ++h;
+        } while (m != l && h < kJumpHops);
+        lab[v] = l;
+        notdone |= (m != l);
+    }
+    if (__ballot(notdone) != 0 && __lane_id() == 0) atomicOr(&ctr[C_JUMP + pass], 1u);
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctr[C_PASSES], 1u);
+}
+
+hipError_t launch_jump(int32_t* lab, int32_t N, uint32_t* ctr, hipStream_t s)
+{
+    const int64_t want = (N + 255) / 256;
+    const int blocks = (int)(want < 65536 ? (want > 0 ? want : 1) : 65536);
+    for (int p = 0; p < kJumpPasses; ++p) {
+        hipLaunchKernelGGL(k_jump, dim3(blocks), dim3(256), 0, s, lab, N, ctr, p);
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ saddle reps
+
+__device__ __forceinline__ uint64_t make_key(uint32_t s, uint32_t low, uint32_t marker, int b)
+{
+    return (uint64_t(s) << (b + 1)) | (uint64_t(marker) << b) | uint64_t(low);
+}
+
+template <int NDIM, bool MINMODE>
+__global__ __launch_bounds__(256) void k_reps(const float* __restrict__ f, Grid g, LinkTable t,
+                                              const int32_t* __restrict__ lab, const uint32_t* __restrict__ usad,
+                                              uint32_t* __restrict__ ctr, uint32_t cap_sad,
+                                              uint64_t* __restrict__ keys, uint32_t cap_keys, int b)
+{
+    constexpr int K = 2 * ((1 << NDIM) - 1);
+    __shared__ uint64_t s_adj[K];
+    __shared__ int32_t s_lin[K];
+    for (int i = threadIdx.x; i < K; i += blockDim.x) {
+        s_adj[i] = t.adj[i];
+        s_lin[i] = t.lin[i];
+    }
+    __syncthreads();
+    const uint32_t nraw = __hip_atomic_load(&ctr[C_NSAD], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t n = nraw < cap_sad ? nraw : cap_sad;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int v = (int)usad[i];
+        const uint32_t bits = boundary_bits<NDIM>(g, v);
+        const uint32_t uv = mode_key<MINMODE>(f[v]);
+        uint64_t up = 0;
+        int best;
+        scan_neighbourhood<NDIM, MINMODE>(f, t, v, bits, uv, up, best);
+        int beta = 0;
+        for (uint64_t rem = up; rem;) {
+            rem &= ~closure(rem & (~rem + 1), rem, s_adj);
+            ++beta;
+        }
+        const uint32_t base = atomicAdd(&ctr[C_NKEYS], (uint32_t)(beta + 1));
+        uint32_t q = base;
+        for (uint64_t rem = up; rem;) {
+            const uint64_t c = closure(rem & (~rem + 1), rem, s_adj);
+            rem &= ~c;
+            // highest vertex of the component: scan it in tie-winning order
+            uint32_t best_u = 0;
+            int rep = v;
+            for (uint64_t x = c; x;) {
+                int j;
+                if (!MINMODE) {
+                    j = __ffsll((unsigned long long)x) - 1;
+                } else {
+                    j = 63 - __clzll((long long)x);
+                }
+                x &= ~(uint64_t(1) << j);
+                const int u_id = v + s_lin[j];
+                const uint32_t u = mode_key<MINMODE>(f[u_id]);
+                if (u >= best_u) {
+                    best_u = u;
+                    rep = u_id;
+                }
+            }
+            if (q < cap_keys) keys[q] = make_key((uint32_t)v, (uint32_t)lab[rep], 0u, b);
+            ++q;
+        }
+        if (q < cap_keys) keys[q] = make_key((uint32_t)v, (uint32_t)beta, 1u, b);
+    }
+}
+
+template <int NDIM, bool MINMODE>
+static void launch_reps_t(const float* f, const Grid& g, const LinkTable& t, const int32_t* lab, const Work& w,
+                          int64_t cap_sad, int bits, hipStream_t s)
+{
+    int64_t want = (cap_sad + 255) / 256;
+    const int blocks = (int)(want < 4096 ? (want > 0 ? want : 1) : 4096);
+    hipLaunchKernelGGL((k_reps<NDIM, MINMODE>), dim3(blocks), dim3(256), 0, s, f, g, t, lab, w.usad, w.ctr,
+                       (uint32_t)cap_sad, w.keysA, (uint32_t)w.cap_keys, bits);
+}
+
+hipError_t launch_reps(const float* f, const Grid& g, const LinkTable& t, bool minima, const int32_t* lab,
+                       const Work& w, int64_t cap_sad, int bits, hipStream_t s)
+{
+#define EG_CASE(N)                                                            \
+    case N:                                                                   \
+        if (minima)                                                           \
+            launch_reps_t<N, true>(f, g, t, lab, w, cap_sad, bits, s);        \
+        else                                                                  \
+            launch_reps_t<N, false>(f, g, t, lab, w, cap_sad, bits, s);       \
+        break;
+    switch (g.ndim) {
+        EG_CASE(1)
+        EG_CASE(2)
+        EG_CASE(3)
+        EG_CASE(4)
+        EG_CASE(5)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef EG_CASE
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ finalize
+
+__global__ void k_finalize(const uint32_t* __restrict__ ctr, int32_t* __restrict__ header, int64_t cap_max,
+                           int64_t cap_sad, int64_t cap_keys, int64_t cap_arc)
+{
+    if (threadIdx.x != 0) return;
+    const int64_t nmax = ctr[C_NMAX], nsad = ctr[C_NSAD], nkeys = ctr[C_NKEYS], narc = ctr[C_NARC];
+    const bool sad_over = nsad > cap_sad;
+    const bool keys_over = nkeys > cap_keys;
+    int status = EG_OK;
+    if (ctr[C_NAN])
+        status = EG_ERR_NAN;
+    else if (nmax > cap_max || sad_over || keys_over || narc > cap_arc)
+        status = EG_ERR_CAPACITY;
+    header[EG_H_STATUS] = status;
+    header[EG_H_NMAX] = (int32_t)nmax;
+    header[EG_H_NSAD] = (int32_t)nsad;
+    header[EG_H_NARC] = (sad_over || keys_over) ? -1 : (int32_t)narc;
+    header[EG_H_NPAIRS] = sad_over ? -1 : (int32_t)(nkeys - nsad);
+    header[EG_H_PASSES] = (int32_t)ctr[C_PASSES];
+}
+
+hipError_t launch_finalize(const Work& w, const eg_out& o, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, w.ctr, o.header, o.cap_max, o.cap_sad, w.cap_keys,
+                       o.cap_arc);
+    return hipGetLastError();
+}
+
+}  // namespace eg

@@ -1,0 +1,166 @@
+// eg_internal.h -- shared definitions of the HIP extremum-graph library.
+//
+// Vertex order.  The simulated-perturbation order of Sec. 3.3 (u below v iff
+// f[u] < f[v], or f[u] == f[v] and u < v) is evaluated with a 32-bit
+// order-preserving integer image of the float (order_key): after -0 is mapped
+// to +0, x < y as floats iff key(x) < key(y) as unsigned integers.  Ties
+// between equal keys are decided by linear index.  For the minimum graph the
+// order is reversed, which equals using ~key with the tie-break reversed.
+//
+// Neighbour rows.  The 2(2^n - 1) Freudenthal neighbours (Alg. 1) are stored
+// as rows sorted lexicographically by coordinate offset: the {0,-1}^n rows
+// first, then the {0,1}^n rows.  For any in-bounds neighbours this row order is
+// the order of their linear indices, and the vertex itself sits between the
+// two halves.  So a scan of the closed neighbourhood in row order visits
+// vertices in increasing index order, and "later wins ties" is a single >=.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "eg.h"
+
+namespace eg {
+
+constexpr int kMaxNb = 62;          // 2(2^5 - 1)
+constexpr int kJumpHops = 64;       // hops per pointer-jumping pass
+constexpr int kJumpPasses = 6;      // 64^6 > 2^31: enough for any chain
+constexpr int kSortBlocks = 256;    // grid of the radix-sort kernels
+constexpr int kSortThreads = 256;
+constexpr int kRadixBits = 8;
+
+// counter slots in the workspace (uint32 each)
+enum : int {
+    C_NAN = 0,
+    C_NMAX = 1,
+    C_NSAD = 2,
+    C_NKEYS = 3,
+    C_NARC = 4,
+    C_NSADF = 5,
+    C_PASSES = 6,
+    C_JUMP = 8,   // kJumpPasses "not converged" flags
+    C_SLOTS = 64,
+};
+
+// Neighbour table for one grid, passed by value as a kernel argument.
+struct LinkTable {
+    int32_t k;                 // number of rows, 2(2^n - 1)
+    int32_t lin[kMaxNb];       // linear index offset of row j
+    uint32_t forb[kMaxNb];     // boundary bits that rule row j out (see boundary_bits)
+    uint64_t adj[kMaxNb];      // bit l set iff rows j and l are adjacent (link edge)
+};
+
+struct Grid {
+    int32_t ndim;
+    int32_t N;
+    int32_t dims[EG_MAX_NDIM];
+};
+
+// Carved workspace.
+struct Work {
+    uint32_t* ctr;    // [C_SLOTS]
+    uint32_t* umax;   // [cap_max] maxima in discovery order
+    uint32_t* usad;   // [cap_sad] saddles in discovery order
+    uint64_t* keysA;  // [cap_keys]
+    uint64_t* keysB;  // [cap_keys]
+    uint32_t* hist;   // [256 * kSortBlocks + 2 * kSortBlocks + 64]
+    int64_t cap_keys;
+    size_t bytes;
+};
+
+// Host: table rows for ndim (Alg. 1), independent of dims.  Returns k.
+int make_rows(int ndim, int8_t (*off)[EG_MAX_NDIM], uint64_t* adj);
+// Host: full kernel table for a grid.
+void make_table(const Grid& g, LinkTable* t);
+// Host: carve (or size, when base == nullptr) the workspace.
+Work carve(void* base, int64_t cap_max, int64_t cap_sad, int64_t cap_pairs);
+// Bits needed to hold any vertex id of a grid with N vertices.
+inline int id_bits(int64_t N)
+{
+    int b = 1;
+    while ((int64_t(1) << b) < N) ++b;
+    return b;
+}
+
+// ------------------------------------------------------------------ device
+
+__device__ __forceinline__ uint32_t order_key(float x)
+{
+    uint32_t b = __float_as_uint(x);
+    b = (b == 0x80000000u) ? 0u : b;
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+template <bool MINMODE>
+__device__ __forceinline__ uint32_t mode_key(float x)
+{
+    uint32_t k = order_key(x);
+    return MINMODE ? ~k : k;
+}
+
+// Boundary bits of a vertex: bit 2i set if coordinate i is 0, bit 2i+1 set if
+// it is dims[i]-1.  Row j exists iff (bits & forb[j]) == 0.
+__device__ __forceinline__ uint32_t boundary_bit(int c, int d, int axis)
+{
+    return (uint32_t(c == 0) << (2 * axis)) | (uint32_t(c == d - 1) << (2 * axis + 1));
+}
+
+// Whether row j beats an equal key (it lies later in visiting order).  In the
+// maximum graph later = larger index = the {0,1} half; in the minimum graph
+// the roles swap.
+template <bool MINMODE>
+__device__ __forceinline__ bool row_wins_tie(int j, int k)
+{
+    return (j >= k / 2) != MINMODE;
+}
+
+// Wave-aggregated append of `val` to list[counter++] for lanes with pred.
+// Must be called by all lanes of the wave together.
+__device__ __forceinline__ void wave_append(bool pred, uint32_t val, uint32_t* counter, uint32_t* list,
+                                            uint32_t cap)
+{
+    uint64_t m = __ballot(pred);
+    if (m == 0) return;
+    const int lane = __lane_id();
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+    base = __shfl(base, leader);
+    if (pred) {
+        uint32_t pos = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+        if (pos < cap) list[pos] = val;
+    }
+}
+
+// Component of `seed` inside `mask` (BFS over link edges, bit-parallel).
+__device__ __forceinline__ uint64_t closure(uint64_t seed, uint64_t mask, const uint64_t* adj)
+{
+    uint64_t comp = seed, frontier = seed;
+    while (frontier) {
+        int j = __ffsll((unsigned long long)frontier) - 1;
+        frontier &= frontier - 1;
+        uint64_t nb = adj[j] & mask & ~comp;
+        comp |= nb;
+        frontier |= nb;
+    }
+    return comp;
+}
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_init(uint32_t* ctr, int32_t* header, hipStream_t s);
+hipError_t launch_classify(const float* f, const Grid& g, const LinkTable& t, bool minima, int32_t* lab,
+                           int32_t* ptr, const Work& w, int64_t cap_max, int64_t cap_sad, hipStream_t s);
+hipError_t launch_jump(int32_t* lab, int32_t N, uint32_t* ctr, hipStream_t s);
+hipError_t launch_reps(const float* f, const Grid& g, const LinkTable& t, bool minima, const int32_t* lab,
+                       const Work& w, int64_t cap_sad, int bits, hipStream_t s);
+// Sort keys[0 .. min(*count, cap)) over bits [0, nbits).  Returns in *sorted
+// the buffer holding the result (one of a, b); with out32 != nullptr the last
+// pass writes the low 32 bits there instead.
+hipError_t launch_sort(uint64_t* a, uint64_t* b, const uint32_t* count, int64_t cap, int nbits, uint32_t* hist,
+                       int32_t* out32, uint64_t** sorted, hipStream_t s);
+hipError_t launch_load_maxima(const Work& w, int64_t cap_max, hipStream_t s);
+hipError_t launch_csr(const uint64_t* keys, const Work& w, int bits, const eg_out& o, hipStream_t s);
+hipError_t launch_finalize(const Work& w, const eg_out& o, hipStream_t s);
+
+}  // namespace eg

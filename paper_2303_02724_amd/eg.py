@@ -1,0 +1,258 @@
+"""Thin Python binding of ``libeg_hip.so`` (the C ABI in ``include/eg.h``).
+
+Argument marshalling only: PyTorch provides device memory and the stream;
+every step of the computation runs in the library's HIP kernels.  There is
+no CPU path: if the library is missing or no HIP device is present, the
+calls raise.
+
+    res = eg.build(field)                # field: float32 CUDA tensor, n = 1..5 axes
+    res.maxima, res.saddles, res.arc_offsets, res.arc_maxima, res.labels
+
+``Builder`` keeps the buffers of one shape allocated so that repeated calls
+(benchmarks, serving) allocate nothing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field as dc_field
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libeg_hip.so")
+
+EG_OK, EG_ERR_ARG, EG_ERR_TOO_LARGE, EG_ERR_WORKSPACE, EG_ERR_NAN, EG_ERR_CAPACITY, EG_ERR_HIP = range(7)
+EG_MINIMA = 0x1
+EG_MAX_NDIM = 5
+H_STATUS, H_NMAX, H_NSAD, H_NARC, H_NPAIRS, H_PASSES = range(6)
+H_SLOTS = 8
+
+
+class EGError(RuntimeError):
+    def __init__(self, status: int, msg: str = ""):
+        self.status = status
+        super().__init__(f"eg status {status} ({status_string(status)}) {msg}".strip())
+
+
+class eg_out(ctypes.Structure):
+    _fields_ = [
+        ("flags", ctypes.c_uint32),
+        ("labels", ctypes.c_void_p),
+        ("ptr", ctypes.c_void_p),
+        ("maxima", ctypes.c_void_p),
+        ("cap_max", ctypes.c_int64),
+        ("saddles", ctypes.c_void_p),
+        ("saddle_beta", ctypes.c_void_p),
+        ("arc_offsets", ctypes.c_void_p),
+        ("cap_sad", ctypes.c_int64),
+        ("arc_maxima", ctypes.c_void_p),
+        ("cap_arc", ctypes.c_int64),
+        ("cap_pairs", ctypes.c_int64),
+        ("workspace", ctypes.c_void_p),
+        ("ws_bytes", ctypes.c_size_t),
+        ("header", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                           "(run `python -c 'import __graft_entry__ as g; g.build()'`)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
+    L.eg_workspace_bytes.argtypes = [ctypes.c_int, i64p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
+    L.eg_workspace_bytes.restype = ctypes.c_size_t
+    L.eg_build.argtypes = [vp, ctypes.c_int, i64p, vp, ctypes.POINTER(eg_out)]
+    L.eg_build.restype = ctypes.c_int
+    L.eg_status_string.argtypes = [ctypes.c_int]
+    L.eg_status_string.restype = ctypes.c_char_p
+    L.eg_link_table.argtypes = [ctypes.c_int, vp, vp]
+    L.eg_link_table.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def status_string(status: int) -> str:
+    try:
+        return lib().eg_status_string(int(status)).decode()
+    except RuntimeError:
+        return "?"
+
+
+def _dims(shape):
+    arr = (ctypes.c_int64 * len(shape))(*[int(s) for s in shape])
+    return arr
+
+
+def workspace_bytes(shape, cap_max: int, cap_sad: int, cap_pairs: int) -> int:
+    return int(lib().eg_workspace_bytes(len(shape), _dims(shape), cap_max, cap_sad, cap_pairs))
+
+
+def link_table(ndim: int):
+    """Host-only neighbour table of the library: (offsets[k, ndim], adjacency[k])."""
+    import numpy as np
+
+    k = lib().eg_link_table(ndim, None, None)
+    if k < 0:
+        raise EGError(EG_ERR_ARG, f"ndim={ndim}")
+    off = np.zeros((k, ndim), dtype=np.int8)
+    adj = np.zeros(k, dtype=np.uint64)
+    lib().eg_link_table(ndim, off.ctypes.data_as(ctypes.c_void_p), adj.ctypes.data_as(ctypes.c_void_p))
+    return off, adj
+
+
+def default_caps(n: int, ndim: int) -> dict:
+    """Starting capacities; the library reports exact needs if they are short."""
+    sad = min(n, max(4096, n // (8 if ndim <= 3 else 4)))
+    return {"cap_max": min(n, max(4096, n // 16)), "cap_sad": sad,
+            "cap_pairs": 3 * sad, "cap_arc": 3 * sad}
+
+
+@dataclass
+class EGResult:
+    labels: torch.Tensor
+    maxima: torch.Tensor
+    saddles: torch.Tensor
+    saddle_beta: torch.Tensor
+    arc_offsets: torch.Tensor
+    arc_maxima: torch.Tensor
+    ptr: torch.Tensor | None
+    passes: int
+    counts: dict = dc_field(default_factory=dict)
+
+
+class Builder:
+    """Device buffers for repeated extremum-graph builds of one grid shape.
+
+    ``launch(field)`` queues the work on the current stream and returns at
+    once; ``finish()`` synchronises, reads the device header and returns an
+    ``EGResult`` of views into the buffers (valid until the next launch).
+    """
+
+    def __init__(self, shape, minima: bool = False, want_ptr: bool = False, device=None, **caps):
+        self.shape = tuple(int(s) for s in shape)
+        if not 1 <= len(self.shape) <= EG_MAX_NDIM:
+            raise EGError(EG_ERR_ARG, f"ndim={len(self.shape)}")
+        self.n = 1
+        for s in self.shape:
+            self.n *= s
+        self.minima = minima
+        self.want_ptr = want_ptr
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        c = default_caps(self.n, len(self.shape))
+        c.update({k: int(v) for k, v in caps.items() if v is not None})
+        self._alloc(c)
+
+    def _alloc(self, caps):
+        dev = self.device
+        self.caps = dict(caps)
+        i32 = dict(dtype=torch.int32, device=dev)
+        self.labels = torch.empty(self.n, **i32)
+        self.ptr = torch.empty(self.n, **i32) if self.want_ptr else None
+        self.maxima = torch.empty(max(1, caps["cap_max"]), **i32)
+        self.saddles = torch.empty(max(1, caps["cap_sad"]), **i32)
+        self.beta = torch.empty(max(1, caps["cap_sad"]), **i32)
+        self.offsets = torch.empty(caps["cap_sad"] + 1, **i32)
+        self.arcs = torch.empty(max(1, caps["cap_arc"]), **i32)
+        self.header = torch.zeros(H_SLOTS, **i32)
+        ws = workspace_bytes(self.shape, caps["cap_max"], caps["cap_sad"], caps["cap_pairs"])
+        if ws == 0:
+            raise EGError(EG_ERR_ARG, f"workspace query failed for {self.shape} {caps}")
+        self.ws = torch.empty(ws + 256, dtype=torch.uint8, device=dev)
+        base = self.ws.data_ptr()
+        aligned = (base + 255) & ~255
+        o = eg_out()
+        o.flags = EG_MINIMA if self.minima else 0
+        o.labels = self.labels.data_ptr()
+        o.ptr = self.ptr.data_ptr() if self.ptr is not None else None
+        o.maxima = self.maxima.data_ptr()
+        o.cap_max = caps["cap_max"]
+        o.saddles = self.saddles.data_ptr()
+        o.saddle_beta = self.beta.data_ptr()
+        o.arc_offsets = self.offsets.data_ptr()
+        o.cap_sad = caps["cap_sad"]
+        o.arc_maxima = self.arcs.data_ptr()
+        o.cap_arc = caps["cap_arc"]
+        o.cap_pairs = caps["cap_pairs"]
+        o.workspace = aligned
+        o.ws_bytes = ws
+        o.header = self.header.data_ptr()
+        self.out = o
+        self._dims = _dims(self.shape)
+
+    def launch(self, field: torch.Tensor, stream=None):
+        if field.dtype != torch.float32 or not field.is_cuda or not field.is_contiguous():
+            raise EGError(EG_ERR_ARG, "field must be a contiguous float32 device tensor")
+        if field.numel() != self.n:
+            raise EGError(EG_ERR_ARG, f"field has {field.numel()} values, builder expects {self.n}")
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        st = lib().eg_build(ctypes.c_void_p(field.data_ptr()), len(self.shape), self._dims,
+                            ctypes.c_void_p(s.cuda_stream), ctypes.byref(self.out))
+        if st != EG_OK:
+            raise EGError(st)
+        self._stream = s
+
+    def header_values(self):
+        return [int(x) for x in self.header.cpu().tolist()]
+
+    def finish(self, check: bool = True) -> EGResult:
+        self._stream.synchronize()
+        h = self.header_values()
+        if check and h[H_STATUS] != EG_OK:
+            raise EGError(h[H_STATUS], f"header={h}")
+        nmax, nsad, narc = h[H_NMAX], h[H_NSAD], h[H_NARC]
+        return EGResult(
+            labels=self.labels.view(self.shape),
+            maxima=self.maxima[:nmax],
+            saddles=self.saddles[:nsad],
+            saddle_beta=self.beta[:nsad],
+            arc_offsets=self.offsets[:nsad + 1],
+            arc_maxima=self.arcs[:max(narc, 0)],
+            ptr=self.ptr.view(self.shape) if self.ptr is not None else None,
+            passes=h[H_PASSES],
+            counts={"maxima": nmax, "saddles": nsad, "arcs": narc, "pairs": h[H_NPAIRS]},
+        )
+
+    def grow(self, h):
+        """Reallocate with capacities large enough for the header's counts."""
+        c = dict(self.caps)
+        if h[H_NMAX] > c["cap_max"]:
+            c["cap_max"] = h[H_NMAX]
+        if h[H_NSAD] > c["cap_sad"]:
+            c["cap_sad"] = h[H_NSAD]
+        if h[H_NPAIRS] > c["cap_pairs"]:
+            c["cap_pairs"] = h[H_NPAIRS]
+        if h[H_NARC] > c["cap_arc"]:
+            c["cap_arc"] = h[H_NARC]
+        if h[H_NSAD] > self.caps["cap_sad"] and h[H_NPAIRS] < 0:
+            c["cap_pairs"] = max(c["cap_pairs"], 4 * c["cap_sad"])
+        if h[H_NARC] < 0:
+            c["cap_arc"] = max(c["cap_arc"], c["cap_pairs"])
+        self._alloc(c)
+
+    def run(self, field: torch.Tensor, max_retries: int = 4) -> EGResult:
+        """launch + finish, growing the buffers while the library reports a
+        capacity shortfall."""
+        for _ in range(max_retries + 1):
+            self.launch(field)
+            self._stream.synchronize()
+            h = self.header_values()
+            if h[H_STATUS] == EG_ERR_CAPACITY:
+                self.grow(h)
+                continue
+            return self.finish()
+        raise EGError(EG_ERR_CAPACITY, "capacity retries exhausted")
+
+
+def build(field: torch.Tensor, minima: bool = False, want_ptr: bool = False, **caps) -> EGResult:
+    """Extremum graph of ``field`` (float32 device tensor, 1..5 axes)."""
+    b = Builder(field.shape, minima=minima, want_ptr=want_ptr, device=field.device, **caps)
+    return b.run(field.contiguous())

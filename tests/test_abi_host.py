@@ -1,0 +1,137 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+that include/eg.h declares, sizes workspaces, rejects bad arguments before
+touching the device, and its neighbour table follows Alg. 1."""
+import ctypes
+import itertools
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2303_02724_amd import eg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?[\w\s\*]*?\b(eg_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_function():
+    names = _declared_functions()
+    assert "eg_build" in names and "eg_workspace_bytes" in names
+    L = eg.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_workspace_bytes():
+    assert eg.workspace_bytes((64, 64), 10, 10, 10) > 0
+    assert eg.workspace_bytes((64, 64), 10, 10, 10) <= eg.workspace_bytes((64, 64), 1000, 1000, 1000)
+    L = eg.lib()
+    bad = [((), 1, 1, 1), ((0, 4), 1, 1, 1), ((2,) * 6, 1, 1, 1), ((1 << 16, 1 << 16), 1, 1, 1),
+           ((4, 4), -1, 1, 1)]
+    for shape, a, b, c in bad:
+        dims = (ctypes.c_int64 * max(1, len(shape)))(*shape)
+        assert L.eg_workspace_bytes(len(shape), dims, a, b, c) == 0, shape
+
+
+def test_build_rejects_bad_arguments_on_host():
+    L = eg.lib()
+    dims = (ctypes.c_int64 * 2)(8, 8)
+    o = eg.eg_out()
+    # NULL field
+    assert L.eg_build(None, 2, dims, None, ctypes.byref(o)) == eg.EG_ERR_ARG
+    fake = ctypes.c_void_p(0x1000)
+    assert L.eg_build(fake, 0, dims, None, ctypes.byref(o)) == eg.EG_ERR_ARG
+    assert L.eg_build(fake, 6, dims, None, ctypes.byref(o)) == eg.EG_ERR_ARG
+    big = (ctypes.c_int64 * 2)(1 << 16, 1 << 16)
+    assert L.eg_build(fake, 2, big, None, ctypes.byref(o)) == eg.EG_ERR_TOO_LARGE
+    zero = (ctypes.c_int64 * 2)(0, 8)
+    assert L.eg_build(fake, 2, zero, None, ctypes.byref(o)) == eg.EG_ERR_ARG
+    # missing output buffers
+    assert L.eg_build(fake, 2, dims, None, ctypes.byref(o)) == eg.EG_ERR_ARG
+    # buffers present but no workspace
+    o.labels = o.header = o.arc_offsets = o.maxima = o.saddles = o.arc_maxima = 0x2000
+    o.cap_max = o.cap_sad = o.cap_arc = o.cap_pairs = 4
+    assert L.eg_build(fake, 2, dims, None, ctypes.byref(o)) == eg.EG_ERR_WORKSPACE
+    o.workspace = 0x3001  # misaligned
+    o.ws_bytes = 1 << 30
+    assert L.eg_build(fake, 2, dims, None, ctypes.byref(o)) == eg.EG_ERR_WORKSPACE
+    o.workspace = 0x3000
+    o.ws_bytes = 16  # too small
+    assert L.eg_build(fake, 2, dims, None, ctypes.byref(o)) == eg.EG_ERR_WORKSPACE
+    o.ws_bytes = 1 << 30
+    o.flags = 0x10  # unknown flag
+    assert L.eg_build(fake, 2, dims, None, ctypes.byref(o)) == eg.EG_ERR_ARG
+    o.flags = 0
+    o.cap_sad = 1 << 31
+    assert L.eg_build(fake, 2, dims, None, ctypes.byref(o)) == eg.EG_ERR_TOO_LARGE
+    assert eg.status_string(eg.EG_ERR_NAN) == "field contains NaN"
+
+
+def _alg1(d):
+    s = set(int(x) for x in d)
+    return any(x != 0 for x in d) and (s <= {0, 1} or s <= {0, -1})
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_link_table_follows_alg1(n):
+    off, adj = eg.link_table(n)
+    k = 2 * (2 ** n - 1)
+    assert off.shape == (k, n)
+    # exactly the Alg. 1 offsets, each once
+    want = {d for d in itertools.product((-1, 0, 1), repeat=n) if _alg1(d)}
+    assert {tuple(int(x) for x in r) for r in off} == want
+    # rows in linear-index order for any grid: lexicographic
+    rows = [tuple(int(x) for x in r) for r in off]
+    assert rows == sorted(rows)
+    # the {0,-1} half first
+    assert all(min(r) < 0 for r in rows[: k // 2]) and all(max(r) > 0 for r in rows[k // 2:])
+    # adjacency masks: symmetric and equal to Alg. 1 on offset differences
+    for j in range(k):
+        for l in range(k):
+            bit = (int(adj[j]) >> l) & 1
+            assert bit == int(_alg1(np.array(rows[j]) - np.array(rows[l]))), (j, l)
+
+
+def test_link_table_fvectors_and_3d_histogram():
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "link_counts.json")))
+    for n in range(2, 6):
+        off, adj = eg.link_table(n)
+        k = len(off)
+        nb = [{l for l in range(k) if (int(adj[j]) >> l) & 1} for j in range(k)]
+        counts, level = [k], [(j,) for j in range(k)]
+        while True:
+            level = [c + (l,) for c in level for l in nb[c[-1]] if l > c[-1] and all(l in nb[x] for x in c)]
+            if not level:
+                break
+            counts.append(len(level))
+        assert counts == gold["fvector"][str(n)]
+    # components of every subset of the 3D link, from the library's masks
+    off, adj = eg.link_table(3)
+    hist = {}
+    for m in range(1 << 14):
+        rem, beta = m, 0
+        while rem:
+            comp = rem & -rem
+            while True:
+                grow = comp
+                for j in range(14):
+                    if (comp >> j) & 1:
+                        grow |= int(adj[j]) & rem
+                if grow == comp:
+                    break
+                comp = grow
+            rem &= ~comp
+            beta += 1
+        hist[str(beta)] = hist.get(str(beta), 0) + 1
+    assert hist == gold["beta_histogram_3d"]

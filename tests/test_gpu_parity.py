@@ -1,0 +1,112 @@
+"""GPU parity: the HIP path (through the C ABI) equals the CPU oracle,
+element by element, on seeded inputs.  Integer and ordering work only, so
+the bar is bit-exact for every output."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2303_02724_amd import workloads as W
+from tests.gpu_util import KEYS, assert_same, gpu_graph
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [(1,), (2,), (37,), (1, 1), (5, 1), (1, 7), (6, 7), (33, 65), (3, 1, 4), (5, 4, 3), (17, 9, 70),
+         (3, 3, 2, 3), (6, 5, 7, 4), (2, 2, 2, 2, 2), (3, 4, 3, 2, 3), (5, 6, 4, 5, 3)]
+
+
+@pytest.mark.parametrize("shape", SMALL, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("kind", ["uniform", "ties", "normal"])
+def test_small_grids(shape, kind):
+    for seed in range(2):
+        f = W.random_field(shape, 100 + seed, kind)
+        for minima in (False, True):
+            ctx = f"shape={shape} kind={kind} seed={seed} minima={minima}"
+            print(ctx, flush=True)
+            g = gpu_graph(f, minima)
+            o = O.extremum_graph(f, minima)
+            assert_same(g, o, KEYS + ["ptr"], ctx)
+
+
+@pytest.mark.parametrize("minima", [False, True])
+def test_config0_2d_256(minima):
+    f = W.field_2d_256()
+    assert_same(gpu_graph(f, minima), O.extremum_graph(f, minima), KEYS + ["ptr"], f"2d256 minima={minima}")
+
+
+@pytest.mark.parametrize("shape,corr", [((64, 64, 64), 4.0), ((40, 72, 96), 3.0)])
+def test_grf_3d(shape, corr):
+    f = W.gaussian_random_field(shape, 5, corr_len=corr, workers=4)
+    for minima in (False, True):
+        assert_same(gpu_graph(f, minima), O.extremum_graph(f, minima), KEYS + ["ptr"], f"grf {shape}")
+
+
+def test_gaussian_mixture_5d():
+    f = W.gaussian_mixture((12, 11, 10, 9, 8), 2, n_gauss=16, noise=1e-4)
+    assert_same(gpu_graph(f), O.extremum_graph(f), KEYS + ["ptr"], "5d")
+
+
+def test_gaussian_mixture_4d():
+    f = W.gaussian_mixture((14, 13, 12, 11), 6, n_gauss=8, noise=1e-3)
+    for minima in (False, True):
+        assert_same(gpu_graph(f, minima), O.extremum_graph(f, minima), KEYS + ["ptr"], "4d")
+
+
+@pytest.mark.parametrize("shape", [(300,), (40, 50), (9, 10, 11), (4, 5, 6, 7), (3, 4, 5, 4, 3)])
+def test_constant_and_ramp(shape):
+    const = np.full(shape, 1.5, np.float32)
+    assert_same(gpu_graph(const), O.extremum_graph(const), KEYS + ["ptr"], "const")
+    assert_same(gpu_graph(const, True), O.extremum_graph(const, True), KEYS + ["ptr"], "const min")
+    n = len(shape)
+    ramp = np.indices(shape).sum(0).astype(np.float32)  # many ties, long paths
+    assert_same(gpu_graph(ramp), O.extremum_graph(ramp), KEYS + ["ptr"], "ramp")
+
+
+def test_long_paths_need_several_jump_passes():
+    # a single monotone serpentine-free ramp: the path from vertex 0 is N-1 steps
+    f = np.arange(200000, dtype=np.float32)
+    g = gpu_graph(f)
+    assert np.all(g["labels"] == f.size - 1)
+    assert g["passes"] >= 3
+
+
+def test_signed_zero_and_infinities():
+    rng = np.random.default_rng(3)
+    f = rng.choice(np.array([0.0, -0.0, np.inf, -np.inf, 1.0, -1.0], np.float32), size=(30, 31))
+    for minima in (False, True):
+        assert_same(gpu_graph(f, minima), O.extremum_graph(f, minima), KEYS + ["ptr"], "zeros/inf")
+
+
+def test_nan_reported():
+    from paper_2303_02724_amd import eg
+    f = W.random_field((20, 20), 1)
+    f[3, 4] = np.nan
+    with pytest.raises(eg.EGError) as ei:
+        gpu_graph(f)
+    assert ei.value.status == eg.EG_ERR_NAN
+
+
+def test_capacity_overflow_then_retry():
+    import torch
+    from paper_2303_02724_amd import eg
+    f = W.random_field((40, 30, 20), 8, "uniform")
+    t = torch.from_numpy(f).cuda()
+    b = eg.Builder(f.shape, cap_max=3, cap_sad=5, cap_pairs=7, cap_arc=2)
+    b.launch(t)
+    h = b.header_values() if b._stream.synchronize() is None else None
+    assert h[eg.H_STATUS] == eg.EG_ERR_CAPACITY
+    o = O.extremum_graph(f)
+    assert h[eg.H_NMAX] == o["maxima"].size
+    assert h[eg.H_NSAD] == o["saddles"].size
+    r = b.run(t)
+    got = {"labels": r.labels.reshape(-1).cpu().numpy(), "maxima": r.maxima.cpu().numpy(),
+           "saddles": r.saddles.cpu().numpy(), "saddle_beta": r.saddle_beta.cpu().numpy(),
+           "arc_offsets": r.arc_offsets.cpu().numpy(), "arc_maxima": r.arc_maxima.cpu().numpy()}
+    assert_same(got, o, KEYS, "after retry")
+
+
+def test_repeat_runs_are_identical():
+    f = W.gaussian_random_field((48, 48, 48), 9, corr_len=3.0, workers=4)
+    a = gpu_graph(f)
+    for _ in range(3):
+        b = gpu_graph(f)
+        assert_same(b, a, KEYS + ["ptr"], "repeat")
