@@ -1,0 +1,255 @@
+#!/usr/bin/env python
+"""Extremum-graph benchmark on one MI355X.
+
+A step is one pass of the whole hot path (eg_build: classification,
+pointer-jumping labels, saddle reps, arc sort / de-duplication, CSR) over one
+field that is already resident in HBM.  Default workload: the 512^3 float32
+Gaussian random field (seed 1, correlation length 8 voxels), maxima graph.
+
+    python bench.py [--steps K] [--warmup W] [--workload grf512|2d256|5d32]
+
+Prints one JSON line.  Besides the contract fields it carries
+  roofline      the dominant kernel against the HBM peak (algorithmic bytes /
+                its average duration, timed with HIP events on the launch stream)
+  cpu_baseline  the CPU oracle timed on a bounded slab of the same field
+  stages_ms     per-stage times (classify / label / arcs), HIP events
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "vertices/s + HBM GB/s for extremum graph (512³ f32); batched p99 latency"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per vertex: classify reads f and writes the pointer;
+# the whole path reads f, writes pointers, reads them and writes labels
+CLASSIFY_BYTES_PER_VERTEX = 8
+PATH_BYTES_PER_VERTEX = 16
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="grf512", choices=["grf512", "2d256", "5d32"])
+    ap.add_argument("--side", type=int, default=None, help="override the grid side (smoke runs)")
+    ap.add_argument("--minima", action="store_true", help="minimum graph instead of maximum graph")
+    ap.add_argument("--stage-reps", type=int, default=20, help="repetitions for the per-stage timings")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-planes", type=int, default=None,
+                    help="slab thickness (slowest axis) for the CPU oracle baseline")
+    ap.add_argument("--profile-stage", default=None, choices=["classify", "label", "arcs"],
+                    help="after the bench, run only this stage --stage-reps times (for counter runs)")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    d = os.path.join(ROOT, "paper_2303_02724_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources (otherwise None)."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(p):
+        return None
+    vals = {}
+    with open(p) as fh:
+        for line in fh:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def make_field(args):
+    from paper_2303_02724_amd import workloads as W
+
+    if args.workload == "grf512":
+        side = args.side or 512
+        f = W.field_3d_grf(side, seed=1)
+        cfg = {"workload": f"grf3d_{side}", "shape": [side] * 3, "seed": 1, "corr_len_voxels": 8,
+               "field": "Gaussian random field, mean 0, std 1"}
+    elif args.workload == "2d256":
+        side = args.side or 256
+        f = W.gaussian_mixture((side, side), 0, n_gauss=8, noise=1e-3)
+        cfg = {"workload": f"gauss2d_{side}", "shape": [side] * 2, "seed": 0, "gaussians": 8, "noise": 1e-3}
+    else:
+        side = args.side or 32
+        f = W.field_5d_32(seed=2, side=side)
+        cfg = {"workload": f"gauss5d_{side}", "shape": [side] * 5, "seed": 2, "gaussians": 16, "noise": 1e-4}
+    cfg["mode"] = "minima" if args.minima else "maxima"
+    return f, cfg
+
+
+def time_stages(b, t, reps):
+    """Average ms of each stage, HIP events on the launch stream."""
+    import torch
+
+    s = torch.cuda.current_stream()
+    acc = {"classify": 0.0, "label": 0.0, "arcs": 0.0}
+    for _ in range(reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(s)
+        b.launch(t, stream=s, stage="classify")
+        ev[1].record(s)
+        b.launch(t, stream=s, stage="label")
+        ev[2].record(s)
+        b.launch(t, stream=s, stage="arcs")
+        ev[3].record(s)
+        ev[3].synchronize()
+        acc["classify"] += ev[0].elapsed_time(ev[1])
+        acc["label"] += ev[1].elapsed_time(ev[2])
+        acc["arcs"] += ev[2].elapsed_time(ev[3])
+    return {k: v / reps for k, v in acc.items()}
+
+
+def cpu_baseline(f, planes):
+    from oracle import oracle as O
+
+    sub = f[:planes] if planes else f
+    t0 = time.perf_counter()
+    g = O.extremum_graph(sub)
+    dt = time.perf_counter() - t0
+    return {
+        "value": sub.size / dt,
+        "unit": "vertices/s",
+        "cores": O.num_threads(),
+        "kind": "oracle",
+        "sample": f"oracle (classification + labels + arcs) on the first {sub.shape[0]} of {f.shape[0]} "
+                  f"slowest-axis planes, shape {list(sub.shape)}, {sub.size} vertices, {dt:.2f} s; "
+                  f"{len(g['maxima'])} maxima, {len(g['saddles'])} saddles",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2303_02724_amd import eg
+
+    t_gen = time.perf_counter()
+    f, cfg = make_field(args)
+    t_gen = time.perf_counter() - t_gen
+    N = int(f.size)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t = torch.from_numpy(f).to(dev)
+    # H2D is reported apart from the timed region (inputs are resident when it starts)
+    torch.cuda.synchronize()
+    th = time.perf_counter()
+    t2 = torch.from_numpy(f).to(dev)
+    torch.cuda.synchronize()
+    h2d_s = time.perf_counter() - th
+    del t2
+
+    b = eg.Builder(f.shape, minima=args.minima, device=dev)
+    res = b.run(t)  # sizes the buffers (untimed)
+    counts = dict(res.counts)
+    counts["jump_passes"] = res.passes
+
+    s = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        b.launch(t, stream=s)
+    torch.cuda.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(s)
+    for _ in range(args.steps):
+        b.launch(t, stream=s)
+    ev1.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    gpu_ms = ev0.elapsed_time(ev1)
+    h = b.header_values()
+    if h[eg.H_STATUS] != eg.EG_OK:
+        raise SystemExit(f"device status {h[eg.H_STATUS]} after the timed region: {h}")
+    ms_per_step = 1000.0 * wall / args.steps
+    value = N * args.steps / wall
+
+    stages = time_stages(b, t, args.stage_reps)
+    dom = max(stages, key=stages.get)
+    kernel_name = {"classify": "k_classify", "label": "k_jump", "arcs": "arcs_sort_csr"}[dom]
+    # roofline of the classification kernel (one launch per step, 8 B/vertex)
+    cls_ms = stages["classify"]
+    alg_bytes = CLASSIFY_BYTES_PER_VERTEX * N
+    achieved = alg_bytes / (cls_ms * 1e-3) / 1e9
+    traffic = recorded_traffic("k_classify", cfg["workload"])
+    roof = {"bound": "hbm", "kernel": "k_classify (stages a + c)", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes,
+            "avg_launch_ms": round(cls_ms, 4), "dominant_stage": dom, "dominant_stage_kernel": kernel_name}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "vertices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": cfg,
+        "roofline": roof,
+        "effective_GBs": round(PATH_BYTES_PER_VERTEX * N / (ms_per_step * 1e-3) / 1e9, 1),
+        "gpu_event_ms_per_step": gpu_ms / args.steps,
+        "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "counts": counts,
+        "h2d_ms": round(h2d_s * 1e3, 3),
+        "field_gen_s": round(t_gen, 2),
+    }
+    if args.profile_stage:
+        torch.cuda.synchronize()
+        if args.profile_stage != "classify":
+            b.launch(t, stream=s, stage="classify")
+        if args.profile_stage == "arcs":
+            b.launch(t, stream=s, stage="label")
+        for _ in range(args.stage_reps):
+            if args.profile_stage == "label":
+                b.launch(t, stream=s, stage="classify")
+            b.launch(t, stream=s, stage=args.profile_stage)
+        torch.cuda.synchronize()
+    if not args.no_cpu_baseline:
+        planes = args.cpu_planes
+        if planes is None:
+            planes = {"grf512": max(1, f.shape[0] // 4), "2d256": f.shape[0], "5d32": max(1, f.shape[0] // 4)}[
+                args.workload]
+        out["cpu_baseline"] = cpu_baseline(f, planes)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

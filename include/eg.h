@@ -51,7 +51,7 @@ extern "C" {
 
 typedef enum eg_status {
     EG_OK = 0,
-    EG_ERR_ARG = 1,       /* host: bad ndim, dims, flags, or a NULL buffer */
+    EG_ERR_ARG = 1,       /* host: bad ndim, dims, flags, a NULL buffer, or labels not 16-byte aligned */
     EG_ERR_TOO_LARGE = 2, /* host: N >= 2^31 vertices, or a capacity >= 2^31 */
     EG_ERR_WORKSPACE = 3, /* host: workspace NULL, misaligned or smaller than eg_workspace_bytes */
     EG_ERR_NAN = 4,       /* device header: the field holds a NaN (outputs undefined) */
@@ -76,7 +76,8 @@ typedef enum eg_status {
 /*
  * Output description for one field.  All pointers are device pointers.
  *
- *   labels       [N]            label (vertex id of the maximum) of every vertex
+ *   labels       [N]            label (vertex id of the maximum) of every vertex;
+ *                               16-byte aligned
  *   ptr          [N] or NULL    steepest-ascent pointer of every vertex (optional)
  *   maxima       [cap_max]      ascending vertex ids of the maxima
  *   saddles      [cap_sad]      ascending vertex ids of the saddles
@@ -134,6 +135,32 @@ size_t eg_workspace_bytes(int ndim, const int64_t* dims, int64_t cap_max, int64_
  */
 eg_status eg_build(const float* field, int ndim, const int64_t* dims, void* stream,
                    const eg_out* out);
+
+/*
+ * The three stages of eg_build, callable one at a time with the same
+ * arguments (eg_build = eg_classify, then eg_label, then eg_arcs, on one
+ * stream).  Each validates its arguments like eg_build.
+ *
+ * eg_classify  Sec. 3.3 / Table 1: resets the header and the workspace
+ *              counters, then for every vertex its steepest-ascent pointer
+ *              (into labels[], and ptr[] when given), the maxima (empty upper
+ *              link) and the saddle candidates (>= 2 upper-link components),
+ *              kept in the workspace.
+ * eg_label     Sec. 2 / Alg. 2 (the walk to a maximum): pointer jumping on
+ *              labels[] in place until every entry names its maximum.  Needs
+ *              eg_classify's labels[] and workspace.
+ * eg_arcs      Sec. 3.4 Alg. 2 / UpperLinkRep: the highest vertex of every
+ *              upper-link component of every saddle, its label, the de-
+ *              duplicated (saddle, maximum) arcs (device radix sort), the
+ *              ascending maxima and saddles, the CSR, and the header.  Needs
+ *              the labels and workspace of the two stages before it.
+ */
+eg_status eg_classify(const float* field, int ndim, const int64_t* dims, void* stream,
+                      const eg_out* out);
+eg_status eg_label(const float* field, int ndim, const int64_t* dims, void* stream,
+                   const eg_out* out);
+eg_status eg_arcs(const float* field, int ndim, const int64_t* dims, void* stream,
+                  const eg_out* out);
 
 /* Human-readable name of a status code (static string). */
 const char* eg_status_string(int status);

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libeg_hip.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-fconstexpr-steps=200000000",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 

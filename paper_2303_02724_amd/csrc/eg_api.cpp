@@ -53,6 +53,7 @@ eg_status check_one(const float* field, int ndim, const int64_t* dims, const eg_
     if (o->flags & ~uint32_t(EG_MINIMA)) return EG_ERR_ARG;
     if (!caps_ok(o->cap_max, o->cap_sad, o->cap_pairs, o->cap_arc)) return EG_ERR_TOO_LARGE;
     if (!o->labels || !o->header || !o->arc_offsets) return EG_ERR_ARG;
+    if (reinterpret_cast<uintptr_t>(o->labels) & 15u) return EG_ERR_ARG;
     if ((o->cap_max > 0 && !o->maxima) || (o->cap_sad > 0 && !o->saddles) || (o->cap_arc > 0 && !o->arc_maxima))
         return EG_ERR_ARG;
     const Work need = carve(nullptr, o->cap_max, o->cap_sad, o->cap_pairs);
@@ -62,29 +63,34 @@ eg_status check_one(const float* field, int ndim, const int64_t* dims, const eg_
     return EG_OK;
 }
 
-// The whole path for one field, queued on s.
-hipError_t run_one(const float* field, const Grid& g, const eg_out& o, const Work& w, hipStream_t s,
-                   bool skip_classify)
+// Stage (a) + (c): pointers, maxima and saddle candidates (resets counters).
+hipError_t stage_classify(const float* field, const Grid& g, const LinkTable& t, const eg_out& o, const Work& w,
+                          hipStream_t s)
 {
-    LinkTable t;
-    make_table(g, &t);
+    const bool minima = (o.flags & EG_MINIMA) != 0;
+    hipError_t e = launch_init(w.ctr, o.header, s);
+    if (e != hipSuccess) return e;
+    return launch_classify(field, g, t, minima, o.labels, o.ptr, w, o.cap_max, o.cap_sad, s);
+}
+
+// Stage (b): labels by pointer jumping, in place.
+hipError_t stage_label(const Grid& g, const eg_out& o, const Work& w, hipStream_t s)
+{
+    return launch_jump(o.labels, g.N, w.ctr, s);
+}
+
+// Stage (d) and the canonical outputs: ascending maxima; reps -> (saddle,
+// maximum) keys -> radix sort -> unique -> CSR; the header.
+hipError_t stage_arcs(const float* field, const Grid& g, const LinkTable& t, const eg_out& o, const Work& w,
+                      hipStream_t s)
+{
     const bool minima = (o.flags & EG_MINIMA) != 0;
     const int b = id_bits(g.N);
-    hipError_t e = hipSuccess;
-    if (!skip_classify) {
-        if ((e = launch_init(w.ctr, o.header, s)) != hipSuccess) return e;
-        // stages (a) + (c): pointers, maxima, saddle candidates
-        if ((e = launch_classify(field, g, t, minima, o.labels, o.ptr, w, o.cap_max, o.cap_sad, s)) != hipSuccess)
-            return e;
-    }
-    // stage (b): labels by pointer jumping, in place
-    if ((e = launch_jump(o.labels, g.N, w.ctr, s)) != hipSuccess) return e;
-    // ascending maxima
+    hipError_t e;
     if ((e = launch_load_maxima(w, o.cap_max, s)) != hipSuccess) return e;
     if ((e = launch_sort(w.keysA, w.keysB, &w.ctr[C_NMAX], o.cap_max, b, w.hist, o.maxima, nullptr, s)) !=
         hipSuccess)
         return e;
-    // stage (d): reps -> (saddle, maximum) keys -> sort -> unique -> CSR
     if ((e = launch_reps(field, g, t, minima, o.labels, w, o.cap_sad, b, s)) != hipSuccess) return e;
     uint64_t* sorted = nullptr;
     if ((e = launch_sort(w.keysA, w.keysB, &w.ctr[C_NKEYS], w.cap_keys, 2 * b + 1, w.hist, nullptr, &sorted, s)) !=
@@ -92,6 +98,25 @@ hipError_t run_one(const float* field, const Grid& g, const eg_out& o, const Wor
         return e;
     if ((e = launch_csr(sorted, w, b, o, s)) != hipSuccess) return e;
     return launch_finalize(w, o, s);
+}
+
+enum Stage { S_CLASSIFY = 1, S_LABEL = 2, S_ARCS = 4, S_ALL = 7 };
+
+eg_status run_stages(int stages, const float* field, int ndim, const int64_t* dims, void* stream,
+                     const eg_out* out)
+{
+    Grid g;
+    Work w;
+    const eg_status st = check_one(field, ndim, dims, out, &g, &w);
+    if (st != EG_OK) return st;
+    LinkTable t;
+    make_table(g, &t);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (stages & S_CLASSIFY) e = stage_classify(field, g, t, *out, w, s);
+    if (e == hipSuccess && (stages & S_LABEL)) e = stage_label(g, *out, w, s);
+    if (e == hipSuccess && (stages & S_ARCS)) e = stage_arcs(field, g, t, *out, w, s);
+    return e == hipSuccess ? EG_OK : EG_ERR_HIP;
 }
 
 }  // namespace
@@ -108,12 +133,22 @@ size_t eg_workspace_bytes(int ndim, const int64_t* dims, int64_t cap_max, int64_
 
 eg_status eg_build(const float* field, int ndim, const int64_t* dims, void* stream, const eg_out* out)
 {
-    Grid g;
-    Work w;
-    const eg_status st = check_one(field, ndim, dims, out, &g, &w);
-    if (st != EG_OK) return st;
-    const hipError_t e = run_one(field, g, *out, w, (hipStream_t)stream, false);
-    return e == hipSuccess ? EG_OK : EG_ERR_HIP;
+    return run_stages(S_ALL, field, ndim, dims, stream, out);
+}
+
+eg_status eg_classify(const float* field, int ndim, const int64_t* dims, void* stream, const eg_out* out)
+{
+    return run_stages(S_CLASSIFY, field, ndim, dims, stream, out);
+}
+
+eg_status eg_label(const float* field, int ndim, const int64_t* dims, void* stream, const eg_out* out)
+{
+    return run_stages(S_LABEL, field, ndim, dims, stream, out);
+}
+
+eg_status eg_arcs(const float* field, int ndim, const int64_t* dims, void* stream, const eg_out* out)
+{
+    return run_stages(S_ARCS, field, ndim, dims, stream, out);
 }
 
 const char* eg_status_string(int status)

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_classify_generic(const float* __restric
         scan_neighbourhood<NDIM, MINMODE>(f, t, v, bits, uv, up, best);
         is_max = up == 0;
         if (!is_max) is_sad = closure(up & (~up + 1), up, s_adj) != up;
-        lab[v] = best;
+        lab[v] = is_max ? v : -(best + 1);  // final label, or "same as best"
         if (ptr) ptr[v] = best;
     }
     wave_append(is_max, (uint32_t)v, &ctr[C_NMAX], umax, cap_max);
@@ -129,6 +129,7 @@ static void launch_classify_t(const float* f, const Grid& g, const LinkTable& t,
 hipError_t launch_classify(const float* f, const Grid& g, const LinkTable& t, bool minima, int32_t* lab,
                            int32_t* ptr, const Work& w, int64_t cap_max, int64_t cap_sad, hipStream_t s)
 {
+    if (g.ndim == 2 || g.ndim == 3) return launch_classify_tiled(f, g, minima, lab, ptr, w, cap_max, cap_sad, s);
 #define EG_CASE(N)                                                                  \
     case N:                                                                         \
         if (minima)                                                                 \
@@ -151,32 +152,61 @@ hipError_t launch_classify(const float* f, const Grid& g, const LinkTable& t, bo
 
 // ------------------------------------------------------------------ labels
 
-// One pass of pointer jumping.  lab[v] always names a vertex on v's
-// steepest-ascent path, and maxima are exactly the fixed points, so entries
-// may be updated in place while other threads read them: any value read is a
-// valid later point of the same path.  Each pass follows at most kJumpHops
-// pointers per vertex; a pass that stops short raises its flag and the next
-// pass runs.  After pass p every entry has advanced kJumpHops^p steps or
-// reached its maximum, so kJumpPasses passes cover any path in a grid of
+// One pass of pointer jumping over the label array.  An entry m >= 0 is final
+// (the maximum m); an entry -(e + 1) means "same label as e", where e is a
+// later vertex of the same steepest-ascent path.  Entries are updated in
+// place while other threads read them; every value ever stored is a valid
+// statement about the same path, so any value read is usable.  Each thread
+// resolves four consecutive vertices at once (one 16-byte load, four
+// independent gather chains) to keep more loads in flight.  A pass follows
+// at most kJumpHops links per vertex; a pass that stops short raises its flag
+// and the next pass runs.  After pass p every entry has advanced kJumpHops^p
+// links or become final, so kJumpPasses passes cover any path in a grid of
 // fewer than 2^31 vertices.
+__device__ __forceinline__ int follow_links(int32_t* lab, int x)
+{
+    int h = 0;
+    while (x < 0 && h < kJumpHops) {
+        x = lab[-x - 1];
+        ++h;
+    }
+    return x;
+}
+
 __global__ __launch_bounds__(256) void k_jump(int32_t* lab, int32_t N, uint32_t* __restrict__ ctr, int pass)
 {
     if (pass > 0 && __hip_atomic_load(&ctr[C_JUMP + pass - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
         return;
     bool notdone = false;
+    const int nq = N >> 2;
     const int stride = gridDim.x * blockDim.x;
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < N; v += stride) {
-        int l = lab[v];
-        int m = lab[l];
-        if (m == l) continue;
-        int h = 0;
-        do {
-            l = m;
-            m = lab[l];
+    int4* lab4 = reinterpret_cast<int4*>(lab);
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += stride) {
+        const int4 x = lab4[q];
+        if ((x.x | x.y | x.z | x.w) >= 0) continue;  // all four final
+        // first links of the four chains are independent loads
+        int y0 = x.x < 0 ? lab[-x.x - 1] : x.x;
+        int y1 = x.y < 0 ? lab[-x.y - 1] : x.y;
+        int y2 = x.z < 0 ? lab[-x.z - 1] : x.z;
+        int y3 = x.w < 0 ? lab[-x.w - 1] : x.w;
+        int h = 1;
+        while ((y0 < 0 || y1 < 0 || y2 < 0 || y3 < 0) && h < kJumpHops) {
+            if (y0 < 0) y0 = lab[-y0 - 1];
+            if (y1 < 0) y1 = lab[-y1 - 1];
+            if (y2 < 0) y2 = lab[-y2 - 1];
+            if (y3 < 0) y3 = lab[-y3 - 1];
             ++h;
-        } while (m != l && h < kJumpHops);
-        lab[v] = l;
-        notdone |= (m != l);
+        }
+        lab4[q] = make_int4(y0, y1, y2, y3);
+        notdone |= (y0 < 0) | (y1 < 0) | (y2 < 0) | (y3 < 0);
+    }
+    // the last N % 4 vertices
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < (N & 3)) {
+        const int v = (nq << 2) + t;
+        const int y = follow_links(lab, lab[v]);
+        lab[v] = y;
+        notdone |= y < 0;
     }
     if (__ballot(notdone) != 0 && __lane_id() == 0) atomicOr(&ctr[C_JUMP + pass], 1u);
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctr[C_PASSES], 1u);
@@ -184,8 +214,9 @@ __global__ __launch_bounds__(256) void k_jump(int32_t* lab, int32_t N, uint32_t*
 
 hipError_t launch_jump(int32_t* lab, int32_t N, uint32_t* ctr, hipStream_t s)
 {
-    const int64_t want = (N + 255) / 256;
-    const int blocks = (int)(want < 65536 ? (want > 0 ? want : 1) : 65536);
+    if (reinterpret_cast<uintptr_t>(lab) & 15u) return hipErrorInvalidValue;
+    const int64_t want = ((int64_t)N / 4 + 255) / 256;
+    const int blocks = (int)(want < 8192 ? (want > 0 ? want : 1) : 8192);
     for (int p = 0; p < kJumpPasses; ++p) {
         hipLaunchKernelGGL(k_jump, dim3(blocks), dim3(256), 0, s, lab, N, ctr, p);
     }

@@ -84,17 +84,24 @@ inline int id_bits(int64_t N)
 
 // ------------------------------------------------------------------ device
 
+// Keys lie in [1, 0xFFFFFFFE] in both modes (non-NaN values map into
+// [0x007FFFFF, 0xFF800000]; NaN patterns, reported as an error, are clamped),
+// so 0 is a sentinel below every vertex, used for positions outside the grid:
+// no pointer can ever leave the grid.
+// Adding +0.0 turns -0 into +0 (round to nearest) and leaves every other
+// value unchanged; the sign-dependent flip makes unsigned order equal float
+// order; the clamp keeps NaN patterns off the sentinel.
 __device__ __forceinline__ uint32_t order_key(float x)
 {
-    uint32_t b = __float_as_uint(x);
-    b = (b == 0x80000000u) ? 0u : b;
-    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+    const uint32_t b = __float_as_uint(x + 0.0f);
+    const uint32_t k = b ^ ((uint32_t)((int32_t)b >> 31) | 0x80000000u);
+    return min(max(k, 1u), 0xFFFFFFFEu);
 }
 
 template <bool MINMODE>
 __device__ __forceinline__ uint32_t mode_key(float x)
 {
-    uint32_t k = order_key(x);
+    const uint32_t k = order_key(x);
     return MINMODE ? ~k : k;
 }
 
@@ -151,6 +158,8 @@ __device__ __forceinline__ uint64_t closure(uint64_t seed, uint64_t mask, const 
 hipError_t launch_init(uint32_t* ctr, int32_t* header, hipStream_t s);
 hipError_t launch_classify(const float* f, const Grid& g, const LinkTable& t, bool minima, int32_t* lab,
                            int32_t* ptr, const Work& w, int64_t cap_max, int64_t cap_sad, hipStream_t s);
+hipError_t launch_classify_tiled(const float* f, const Grid& g, bool minima, int32_t* lab, int32_t* ptr,
+                                 const Work& w, int64_t cap_max, int64_t cap_sad, hipStream_t s);
 hipError_t launch_jump(int32_t* lab, int32_t N, uint32_t* ctr, hipStream_t s);
 hipError_t launch_reps(const float* f, const Grid& g, const LinkTable& t, bool minima, const int32_t* lab,
                        const Work& w, int64_t cap_sad, int bits, hipStream_t s);

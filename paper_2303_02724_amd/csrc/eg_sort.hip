@@ -14,14 +14,19 @@
 
 namespace eg {
 
-__device__ __forceinline__ void chunk_range(uint32_t n, uint32_t nblocks, uint32_t blk, uint32_t& lo, uint32_t& hi)
+// Blocks take contiguous runs of whole 256-key tiles; only the first
+// `active` blocks get work, so small inputs touch few histogram columns.
+__device__ __forceinline__ uint32_t chunk_range(uint32_t n, uint32_t nblocks, uint32_t blk, uint32_t& lo,
+                                                uint32_t& hi)
 {
     const uint32_t tiles = (n + 255u) / 256u;
-    const uint32_t per = (tiles + nblocks - 1u) / nblocks;
+    const uint32_t per = tiles == 0 ? 1u : (tiles + nblocks - 1u) / nblocks;
+    const uint32_t active = (tiles + per - 1u) / per;
     const uint64_t l = uint64_t(blk) * per * 256u;
     lo = (uint32_t)(l < n ? l : n);
     const uint64_t h = uint64_t(lo) + uint64_t(per) * 256u;
     hi = (uint32_t)(h < n ? h : n);
+    return active;
 }
 
 __device__ __forceinline__ uint32_t load_count(const uint32_t* count, uint32_t cap)
@@ -68,37 +73,58 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint64_t* __restrict__
     __syncthreads();
     const uint32_t n = load_count(count, cap);
     uint32_t lo, hi;
-    chunk_range(n, gridDim.x, blockIdx.x, lo, hi);
+    const uint32_t active = chunk_range(n, gridDim.x, blockIdx.x, lo, hi);
+    if (blockIdx.x >= active) return;
     for (uint32_t i = lo + tid; i < hi; i += 256) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
     __syncthreads();
-    hist[tid * gridDim.x + blockIdx.x] = h[tid];
+    hist[tid * active + blockIdx.x] = h[tid];
 }
 
-// Exclusive scan, in place, of `total` entries (a multiple of 1024) by one
-// block of 1024 threads; each thread owns a contiguous segment.
-__global__ __launch_bounds__(1024) void k_scan_1block(uint32_t* __restrict__ a, int total)
+// Exclusive scan, in place, of the 256 x active histogram (digit-major), by
+// one block of 1024 threads; chunks of 4096 pass through LDS so that global
+// accesses stay coalesced.
+__global__ __launch_bounds__(1024) void k_scan_hist(uint32_t* __restrict__ a, const uint32_t* count, uint32_t cap,
+                                                    uint32_t nblocks)
 {
+    __shared__ uint32_t buf[4096];
     __shared__ uint32_t wsum[16];
-    const int tid = threadIdx.x;
-    const int per = total / 1024;
-    uint32_t* seg = a + tid * per;
-    uint32_t s = 0;
-    for (int i = 0; i < per; ++i) s += seg[i];
-    const uint32_t inc = wave_incl_scan(s);
-    const int w = tid >> 6, lane = tid & 63;
-    if (lane == 63) wsum[w] = inc;
-    __syncthreads();
-    if (w == 0) {
-        uint32_t x = lane < 16 ? wsum[lane] : 0u;
-        x = wave_incl_scan(x);
-        if (lane < 16) wsum[lane] = x;
-    }
-    __syncthreads();
-    uint32_t run = (w > 0 ? wsum[w - 1] : 0u) + inc - s;
-    for (int i = 0; i < per; ++i) {
-        const uint32_t x = seg[i];
-        seg[i] = run;
-        run += x;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const uint32_t n = load_count(count, cap);
+    uint32_t lo, hi;
+    const uint32_t active = chunk_range(n, nblocks, 0, lo, hi);
+    const uint32_t total = 256u * active;
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < total; base += 4096) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t i = base + k * 1024 + tid;
+            buf[k * 1024 + tid] = i < total ? a[i] : 0u;
+        }
+        __syncthreads();
+        const uint32_t x0 = buf[4 * tid], x1 = buf[4 * tid + 1], x2 = buf[4 * tid + 2], x3 = buf[4 * tid + 3];
+        const uint32_t sum = x0 + x1 + x2 + x3;
+        const uint32_t inc = wave_incl_scan(sum);
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        if (w == 0) {
+            uint32_t y = lane < 16 ? wsum[lane] : 0u;
+            y = wave_incl_scan(y);
+            if (lane < 16) wsum[lane] = y;
+        }
+        __syncthreads();
+        const uint32_t ex = carry + (w > 0 ? wsum[w - 1] : 0u) + inc - sum;
+        buf[4 * tid] = ex;
+        buf[4 * tid + 1] = ex + x0;
+        buf[4 * tid + 2] = ex + x0 + x1;
+        buf[4 * tid + 3] = ex + x0 + x1 + x2;
+        carry += wsum[15];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t i = base + k * 1024 + tid;
+            if (i < total) a[i] = buf[k * 1024 + tid];
+        }
+        __syncthreads();
     }
 }
 
@@ -110,10 +136,11 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t* __restric
     __shared__ uint32_t wcnt[4][256];
     const int tid = threadIdx.x;
     const int w = tid >> 6, lane = tid & 63;
-    run[tid] = hist[tid * gridDim.x + blockIdx.x];
     const uint32_t n = load_count(count, cap);
     uint32_t lo, hi;
-    chunk_range(n, gridDim.x, blockIdx.x, lo, hi);
+    const uint32_t active = chunk_range(n, gridDim.x, blockIdx.x, lo, hi);
+    if (blockIdx.x >= active) return;
+    run[tid] = hist[tid * active + blockIdx.x];
     const uint64_t lt = (1ull << lane) - 1ull;
     for (uint32_t base = lo; base < hi; base += 256) {
 #pragma unroll
@@ -159,7 +186,8 @@ hipError_t launch_sort(uint64_t* a, uint64_t* b, const uint32_t* count, int64_t 
         const bool last = p == passes - 1;
         hipLaunchKernelGGL(k_radix_hist, dim3(kSortBlocks), dim3(kSortThreads), 0, s, src, count, (uint32_t)cap,
                            shift, hist);
-        hipLaunchKernelGGL(k_scan_1block, dim3(1), dim3(1024), 0, s, hist, 256 * kSortBlocks);
+        hipLaunchKernelGGL(k_scan_hist, dim3(1), dim3(1024), 0, s, hist, count, (uint32_t)cap,
+                           (uint32_t)kSortBlocks);
         int32_t* o32 = (last && out32) ? out32 : nullptr;
         hipLaunchKernelGGL(k_radix_scatter, dim3(kSortBlocks), dim3(kSortThreads), 0, s, src, dst, o32, count,
                            (uint32_t)cap, shift, hist);

@@ -1,65 +1,38 @@
 // eg_tables.cpp -- host-side neighbour tables and workspace layout.
 //
-// The neighbour rows come from the GridAdjacency test (Sec. 3.2, Alg. 1):
-// offset d (nonzero) is a neighbour offset iff every component of d lies in
-// {0,1} or every component lies in {0,-1}; two neighbours of the same vertex
-// are joined by a link edge iff their offsets differ by such a vector.
+// The neighbour rows come from the compile-time tables of eg_rows.h
+// (GridAdjacency, Sec. 3.2 Alg. 1); here they get the grid's linear offsets
+// and boundary bits.
 #include <algorithm>
-#include <array>
 #include <cstring>
-#include <vector>
 
 #include "eg_internal.h"
+#include "eg_rows.h"
 
 namespace eg {
 
-static bool alg1_adjacent(const int* d, int n)
+template <int NDIM>
+static int copy_rows(int8_t (*off)[EG_MAX_NDIM], uint64_t* adj)
 {
-    bool in01 = true, in0m1 = true, zero = true;
-    for (int i = 0; i < n; ++i) {
-        if (d[i] != 0) zero = false;
-        if (!(d[i] == 0 || d[i] == 1)) in01 = false;
-        if (!(d[i] == 0 || d[i] == -1)) in0m1 = false;
+    constexpr Rows<NDIM> r = make_rows_ce<NDIM>();
+    for (int j = 0; j < Rows<NDIM>::K; ++j) {
+        if (off)
+            for (int i = 0; i < EG_MAX_NDIM; ++i) off[j][i] = (int8_t)(i < NDIM ? r.d[j][i] : 0);
+        if (adj) adj[j] = r.adj[j];
     }
-    return !zero && (in01 || in0m1);
+    return Rows<NDIM>::K;
 }
 
 int make_rows(int ndim, int8_t (*off)[EG_MAX_NDIM], uint64_t* adj)
 {
-    if (ndim < 1 || ndim > EG_MAX_NDIM) return -1;
-    std::vector<std::array<int, EG_MAX_NDIM>> rows;
-    int total = 1;
-    for (int i = 0; i < ndim; ++i) total *= 3;
-    for (int t = 0; t < total; ++t) {
-        std::array<int, EG_MAX_NDIM> d{};
-        int r = t;
-        for (int i = ndim - 1; i >= 0; --i) {
-            d[i] = r % 3 - 1;
-            r /= 3;
-        }
-        if (alg1_adjacent(d.data(), ndim)) rows.push_back(d);
+    switch (ndim) {
+        case 1: return copy_rows<1>(off, adj);
+        case 2: return copy_rows<2>(off, adj);
+        case 3: return copy_rows<3>(off, adj);
+        case 4: return copy_rows<4>(off, adj);
+        case 5: return copy_rows<5>(off, adj);
+        default: return -1;
     }
-    // lexicographic, axis 0 most significant: equals linear-index order
-    std::sort(rows.begin(), rows.end(), [ndim](const auto& a, const auto& b) {
-        for (int i = 0; i < ndim; ++i)
-            if (a[i] != b[i]) return a[i] < b[i];
-        return false;
-    });
-    const int k = (int)rows.size();
-    for (int j = 0; j < k; ++j) {
-        if (off)
-            for (int i = 0; i < EG_MAX_NDIM; ++i) off[j][i] = (int8_t)(i < ndim ? rows[j][i] : 0);
-        if (adj) {
-            uint64_t m = 0;
-            for (int l = 0; l < k; ++l) {
-                int diff[EG_MAX_NDIM];
-                for (int i = 0; i < ndim; ++i) diff[i] = rows[j][i] - rows[l][i];
-                if (alg1_adjacent(diff, ndim)) m |= uint64_t(1) << l;
-            }
-            adj[j] = m;
-        }
-    }
-    return k;
 }
 
 void make_table(const Grid& g, LinkTable* t)

@@ -70,8 +70,10 @@ def lib():
     vp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
     L.eg_workspace_bytes.argtypes = [ctypes.c_int, i64p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
     L.eg_workspace_bytes.restype = ctypes.c_size_t
-    L.eg_build.argtypes = [vp, ctypes.c_int, i64p, vp, ctypes.POINTER(eg_out)]
-    L.eg_build.restype = ctypes.c_int
+    for name in ("eg_build", "eg_classify", "eg_label", "eg_arcs"):
+        fn = getattr(L, name)
+        fn.argtypes = [vp, ctypes.c_int, i64p, vp, ctypes.POINTER(eg_out)]
+        fn.restype = ctypes.c_int
     L.eg_status_string.argtypes = [ctypes.c_int]
     L.eg_status_string.restype = ctypes.c_char_p
     L.eg_link_table.argtypes = [ctypes.c_int, vp, vp]
@@ -188,14 +190,19 @@ class Builder:
         self.out = o
         self._dims = _dims(self.shape)
 
-    def launch(self, field: torch.Tensor, stream=None):
+    def launch(self, field: torch.Tensor, stream=None, stage: str = "all"):
+        """Queue the whole path (``stage="all"``, eg_build) or one stage
+        (``"classify"``, ``"label"``, ``"arcs"``) on ``stream`` (default: the
+        current stream)."""
         if field.dtype != torch.float32 or not field.is_cuda or not field.is_contiguous():
             raise EGError(EG_ERR_ARG, "field must be a contiguous float32 device tensor")
         if field.numel() != self.n:
             raise EGError(EG_ERR_ARG, f"field has {field.numel()} values, builder expects {self.n}")
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
-        st = lib().eg_build(ctypes.c_void_p(field.data_ptr()), len(self.shape), self._dims,
-                            ctypes.c_void_p(s.cuda_stream), ctypes.byref(self.out))
+        fn = {"all": lib().eg_build, "classify": lib().eg_classify, "label": lib().eg_label,
+              "arcs": lib().eg_arcs}[stage]
+        st = fn(ctypes.c_void_p(field.data_ptr()), len(self.shape), self._dims,
+                ctypes.c_void_p(s.cuda_stream), ctypes.byref(self.out))
         if st != EG_OK:
             raise EGError(st)
         self._stream = s

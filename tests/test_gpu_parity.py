@@ -76,6 +76,16 @@ def test_signed_zero_and_infinities():
         assert_same(gpu_graph(f, minima), O.extremum_graph(f, minima), KEYS + ["ptr"], "zeros/inf")
 
 
+def test_denormals_keep_their_order():
+    # subnormal values must compare exactly (no flush to zero on the GPU path)
+    rng = np.random.default_rng(5)
+    vals = np.array([1e-45, 2e-45, 1e-40, 3e-39, -1e-45, -1e-40, 0.0, -0.0], np.float32)
+    for shape in [(33, 70), (9, 17, 66)]:
+        f = rng.choice(vals, size=shape)
+        for minima in (False, True):
+            assert_same(gpu_graph(f, minima), O.extremum_graph(f, minima), KEYS + ["ptr"], f"denormals {shape}")
+
+
 def test_nan_reported():
     from paper_2303_02724_amd import eg
     f = W.random_field((20, 20), 1)
