@@ -70,7 +70,8 @@ typedef enum eg_status {
 #define EG_H_NSAD 2   /* number of saddles (required size of saddles[], saddle_beta[]) */
 #define EG_H_NARC 3   /* number of arcs (required size of arc_maxima[]); -1 if unknown */
 #define EG_H_NPAIRS 4 /* number of (saddle, component) pairs (required cap_pairs) */
-#define EG_H_PASSES 5 /* pointer-jumping passes that did work */
+#define EG_H_PASSES 5 /* per-vertex label passes that ran */
+#define EG_H_EXITS 6  /* tile exit-list entries the labels used (diagnostic) */
 #define EG_H_SLOTS 8
 
 /*
@@ -161,6 +162,40 @@ eg_status eg_label(const float* field, int ndim, const int64_t* dims, void* stre
                    const eg_out* out);
 eg_status eg_arcs(const float* field, int ndim, const int64_t* dims, void* stream,
                   const eg_out* out);
+
+/*
+ * Batches: the extremum graphs of `count` independent 2D or 3D fields in one
+ * launch sequence.  Classification runs as one persistent launch over a work
+ * list of (field, tile) items; labels, reps and the per-field CSR outputs are
+ * computed for all fields together, with one radix sort over keys that carry
+ * the field index.  Results equal eg_build's for every field.
+ *
+ * Field i is described exactly as for eg_build: fields[i] (device float32),
+ * ndims[i] (2 or 3), dims[i * EG_MAX_NDIM + 0 .. ndims[i]-1], outs[i] (its own
+ * output buffers, header and workspace of eg_workspace_bytes; cap_max >= 1).
+ * The batch also needs a batch workspace (device, 256-byte aligned, at least
+ * eg_batch_workspace_bytes) and a plan:
+ *
+ *   1. eg_batch_plan() validates everything (host only) and writes the plan
+ *      into host memory of eg_batch_plan_bytes(count) bytes;
+ *   2. the caller copies those bytes to the start of the batch workspace
+ *      (any stream-ordered or synchronous host-to-device copy);
+ *   3. eg_build_batched(host_plan, stream) queues the work.  It never
+ *      allocates or synchronises, so a plan can be replayed, e.g. from a HIP
+ *      graph, as long as the fields and buffers it names stay in place.
+ *
+ * Errors: EG_ERR_ARG for ndim outside {2, 3}, NULL pointers, cap_max < 1 or a
+ * short host plan buffer; EG_ERR_TOO_LARGE when a field is too large, the keys
+ * of the batch exceed 2^32 or the field index plus two vertex ids and two
+ * flag bits exceed 64 bits; EG_ERR_WORKSPACE for a missing, misaligned or short
+ * workspace.  Device-side conditions go to each field's header.
+ */
+size_t eg_batch_plan_bytes(int count);
+size_t eg_batch_workspace_bytes(int count, const int* ndims, const int64_t* dims, const eg_out* outs);
+eg_status eg_batch_plan(int count, const float* const* fields, const int* ndims, const int64_t* dims,
+                        const eg_out* outs, void* batch_ws, size_t batch_ws_bytes, void* host_plan,
+                        size_t host_plan_bytes);
+eg_status eg_build_batched(const void* host_plan, void* stream);
 
 /* Human-readable name of a status code (static string). */
 const char* eg_status_string(int status);

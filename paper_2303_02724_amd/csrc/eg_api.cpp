@@ -56,10 +56,10 @@ eg_status check_one(const float* field, int ndim, const int64_t* dims, const eg_
     if (reinterpret_cast<uintptr_t>(o->labels) & 15u) return EG_ERR_ARG;
     if ((o->cap_max > 0 && !o->maxima) || (o->cap_sad > 0 && !o->saddles) || (o->cap_arc > 0 && !o->arc_maxima))
         return EG_ERR_ARG;
-    const Work need = carve(nullptr, o->cap_max, o->cap_sad, o->cap_pairs);
+    const Work need = carve(nullptr, g->N, o->cap_max, o->cap_sad, o->cap_pairs);
     if (!o->workspace || (reinterpret_cast<uintptr_t>(o->workspace) & 255u) || o->ws_bytes < need.bytes)
         return EG_ERR_WORKSPACE;
-    *w = carve(o->workspace, o->cap_max, o->cap_sad, o->cap_pairs);
+    *w = carve(o->workspace, g->N, o->cap_max, o->cap_sad, o->cap_pairs);
     return EG_OK;
 }
 
@@ -76,24 +76,22 @@ hipError_t stage_classify(const float* field, const Grid& g, const LinkTable& t,
 // Stage (b): labels by pointer jumping, in place.
 hipError_t stage_label(const Grid& g, const eg_out& o, const Work& w, hipStream_t s)
 {
-    return launch_jump(o.labels, g.N, w.ctr, s);
+    return launch_labels(o.labels, g.N, w, s);
 }
 
-// Stage (d) and the canonical outputs: ascending maxima; reps -> (saddle,
-// maximum) keys -> radix sort -> unique -> CSR; the header.
+// Stage (d) and the canonical outputs: maxima and (saddle, maximum) keys
+// from the reps -> one radix sort -> ascending maxima, unique arcs, CSR; the
+// header.
 hipError_t stage_arcs(const float* field, const Grid& g, const LinkTable& t, const eg_out& o, const Work& w,
                       hipStream_t s)
 {
     const bool minima = (o.flags & EG_MINIMA) != 0;
     const int b = id_bits(g.N);
     hipError_t e;
-    if ((e = launch_load_maxima(w, o.cap_max, s)) != hipSuccess) return e;
-    if ((e = launch_sort(w.keysA, w.keysB, &w.ctr[C_NMAX], o.cap_max, b, w.hist, o.maxima, nullptr, s)) !=
-        hipSuccess)
-        return e;
+    if ((e = launch_load_maxima(w, o.cap_max, b, s)) != hipSuccess) return e;
     if ((e = launch_reps(field, g, t, minima, o.labels, w, o.cap_sad, b, s)) != hipSuccess) return e;
     uint64_t* sorted = nullptr;
-    if ((e = launch_sort(w.keysA, w.keysB, &w.ctr[C_NKEYS], w.cap_keys, 2 * b + 1, w.hist, nullptr, &sorted, s)) !=
+    if ((e = launch_sort(w.keysA, w.keysB, &w.ctr[C_NKEYS], w.cap_keys, 2 * b + 2, w.hist, &sorted, s)) !=
         hipSuccess)
         return e;
     if ((e = launch_csr(sorted, w, b, o, s)) != hipSuccess) return e;
@@ -119,16 +117,165 @@ eg_status run_stages(int stages, const float* field, int ndim, const int64_t* di
     return e == hipSuccess ? EG_OK : EG_ERR_HIP;
 }
 
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct BatchLayout {
+    size_t o_plan, o_fields, o_bctr, o_seg, o_hist, o_ka, o_kb, bytes, plan_bytes;
+    int64_t cap_keys;
+};
+
+BatchLayout batch_layout(int count, int64_t cap_keys)
+{
+    BatchLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        const size_t at = off;
+        off = align_up(off + n);
+        return at;
+    };
+    L.o_plan = take(sizeof(BatchPlan));
+    L.o_fields = take(sizeof(BatchField) * (size_t)count);
+    L.plan_bytes = off;
+    L.o_bctr = take(sizeof(uint32_t) * C_SLOTS);
+    L.o_seg = take(sizeof(uint32_t) * 3 * (size_t)(count + 1));
+    L.o_hist = take(sizeof(uint32_t) * (256 * kSortBlocks + 2 * kSortBlocks + 64));
+    L.cap_keys = cap_keys > 0 ? cap_keys : 1;
+    L.o_ka = take(sizeof(uint64_t) * (size_t)L.cap_keys);
+    L.o_kb = take(sizeof(uint64_t) * (size_t)L.cap_keys);
+    L.bytes = off;
+    return L;
+}
+
+eg_status batch_keys(int count, const int* ndims, const int64_t* dims, const eg_out* outs, int64_t* cap_keys,
+                     int* bits)
+{
+    if (count < 1 || !ndims || !dims || !outs) return EG_ERR_ARG;
+    int64_t keys = 0;
+    int b = 1;
+    for (int i = 0; i < count; ++i) {
+        Grid g;
+        if (ndims[i] != 2 && ndims[i] != 3) return EG_ERR_ARG;
+        if (!grid_from(ndims[i], dims + (size_t)i * EG_MAX_NDIM, &g))
+            return too_large_or_arg(ndims[i], dims + (size_t)i * EG_MAX_NDIM);
+        const eg_out& o = outs[i];
+        if (!caps_ok(o.cap_max, o.cap_sad, o.cap_pairs, o.cap_arc)) return EG_ERR_TOO_LARGE;
+        keys += o.cap_max + o.cap_sad + o.cap_pairs;
+        const int bi = id_bits(g.N);
+        if (bi > b) b = bi;
+    }
+    int fbits = id_bits(count);
+    if (fbits + 2 * b + 2 > 64 || keys >= (int64_t(1) << 32)) return EG_ERR_TOO_LARGE;
+    *cap_keys = keys;
+    *bits = b;
+    return EG_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t eg_batch_plan_bytes(int count)
+{
+    if (count < 1) return 0;
+    return batch_layout(count, 1).plan_bytes;
+}
+
+size_t eg_batch_workspace_bytes(int count, const int* ndims, const int64_t* dims, const eg_out* outs)
+{
+    int64_t cap_keys;
+    int b;
+    if (batch_keys(count, ndims, dims, outs, &cap_keys, &b) != EG_OK) return 0;
+    return batch_layout(count, cap_keys).bytes;
+}
+
+eg_status eg_batch_plan(int count, const float* const* fields, const int* ndims, const int64_t* dims,
+                        const eg_out* outs, void* batch_ws, size_t batch_ws_bytes, void* host_plan,
+                        size_t host_plan_bytes)
+{
+    int64_t cap_keys;
+    int b;
+    eg_status st = batch_keys(count, ndims, dims, outs, &cap_keys, &b);
+    if (st != EG_OK) return st;
+    if (!fields || !host_plan) return EG_ERR_ARG;
+    const BatchLayout L = batch_layout(count, cap_keys);
+    if (host_plan_bytes < L.plan_bytes) return EG_ERR_ARG;
+    if (!batch_ws || (reinterpret_cast<uintptr_t>(batch_ws) & 255u) || batch_ws_bytes < L.bytes)
+        return EG_ERR_WORKSPACE;
+    char* dbase = (char*)batch_ws;
+    std::memset(host_plan, 0, L.plan_bytes);
+    BatchPlan* P = (BatchPlan*)host_plan;
+    BatchField* F = (BatchField*)((char*)host_plan + L.o_fields);
+    P->count = count;
+    P->bits = b;
+    P->fbits = id_bits(count);
+    P->cap_keys = L.cap_keys;
+    P->bctr = (uint32_t*)(dbase + L.o_bctr);
+    P->seg = (uint32_t*)(dbase + L.o_seg);
+    P->hist = (uint32_t*)(dbase + L.o_hist);
+    P->keysA = (uint64_t*)(dbase + L.o_ka);
+    P->keysB = (uint64_t*)(dbase + L.o_kb);
+    P->fields = (BatchField*)(dbase + L.o_fields);
+    P->dev = (const BatchPlan*)(dbase + L.o_plan);
+    P->plan_bytes = (int64_t)L.plan_bytes;
+    int64_t tiles = 0, quads = 0, sad = 0, exits = 0, maxs = 0;
+    for (int i = 0; i < count; ++i) {
+        Grid g;
+        Work w;
+        const eg_out& o = outs[i];
+        st = check_one(fields[i], ndims[i], dims + (size_t)i * EG_MAX_NDIM, &o, &g, &w);
+        if (st != EG_OK) return st;
+        if (o.cap_max < 1) return EG_ERR_ARG;
+        const int ty = g.ndim == 3 ? kTile3Y : kTile2Y, tz = g.ndim == 3 ? kTile3Z : 1;
+        F[i].ta = tile_args(fields[i], g, o.labels, o.ptr, w, o.cap_max, o.cap_sad, ty, tz);
+        F[i].ndim = g.ndim;
+        F[i].minima = (o.flags & EG_MINIMA) ? 1 : 0;
+        F[i].N = g.N;
+        F[i].tile_base = tiles;
+        F[i].quad_base = quads;
+        F[i].sad_base = sad;
+        F[i].exit_base = exits;
+        F[i].max_base = maxs;
+        F[i].exres = w.exres;
+        F[i].header = o.header;
+        F[i].maxima = o.maxima;
+        F[i].saddles = o.saddles;
+        F[i].beta = o.saddle_beta;
+        F[i].offsets = o.arc_offsets;
+        F[i].arcs = o.arc_maxima;
+        F[i].cap_arc = (uint32_t)o.cap_arc;
+        F[i].cap_keys = (uint32_t)(o.cap_max + o.cap_sad + o.cap_pairs);
+        tiles += F[i].ta.ntiles;
+        quads += (g.N + 3) / 4;
+        sad += o.cap_sad;
+        exits += w.cap_exit;
+        maxs += o.cap_max;
+    }
+    P->total_tiles = tiles;
+    P->total_quads = quads;
+    P->total_sad = sad;
+    P->total_exit = exits;
+    P->total_max = maxs;
+    return EG_OK;
+}
+
+eg_status eg_build_batched(const void* host_plan, void* stream)
+{
+    if (!host_plan) return EG_ERR_ARG;
+    const BatchPlan& P = *(const BatchPlan*)host_plan;
+    if (P.count < 1 || !P.dev) return EG_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_batched_init(P.dev, P, s);
+    if (e == hipSuccess) e = launch_classify_batched(P.dev, P, s);
+    if (e == hipSuccess) e = launch_batched_rest(P.dev, P, s);
+    return e == hipSuccess ? EG_OK : EG_ERR_HIP;
+}
 
 size_t eg_workspace_bytes(int ndim, const int64_t* dims, int64_t cap_max, int64_t cap_sad, int64_t cap_pairs)
 {
     Grid g;
     if (!grid_from(ndim, dims, &g)) return 0;
     if (!caps_ok(cap_max, cap_sad, cap_pairs, 0)) return 0;
-    return carve(nullptr, cap_max, cap_sad, cap_pairs).bytes;
+    return carve(nullptr, g.N, cap_max, cap_sad, cap_pairs).bytes;
 }
 
 eg_status eg_build(const float* field, int ndim, const int64_t* dims, void* stream, const eg_out* out)

@@ -5,8 +5,8 @@
 //   mask (Sec. 3.3), the steepest-ascent pointer (highest upper-link vertex,
 //   Sec. 3.3) and decides maximum (empty upper link) / saddle (>= 2
 //   components, Table 1) with a bit-parallel BFS over the link edges.
-// k_jump  stage (b): pointer jumping on the label array until every entry
-//   names a maximum (the end of the walk of Alg. 2).
+// k_exit_*, k_final  stage (b): pointer jumping until every vertex names its
+//   maximum (the end of the walk of Alg. 2).
 // k_reps  stage (d), first half: for every saddle, the highest vertex of each
 //   upper-link component (UpperLinkRep, Sec. 3.4) and the label it reaches,
 //   emitted as sortable (saddle, maximum) keys plus one marker per saddle
@@ -152,31 +152,69 @@ hipError_t launch_classify(const float* f, const Grid& g, const LinkTable& t, bo
 
 // ------------------------------------------------------------------ labels
 
-// One pass of pointer jumping over the label array.  An entry m >= 0 is final
-// (the maximum m); an entry -(e + 1) means "same label as e", where e is a
-// later vertex of the same steepest-ascent path.  Entries are updated in
-// place while other threads read them; every value ever stored is a valid
-// statement about the same path, so any value read is usable.  Each thread
-// resolves four consecutive vertices at once (one 16-byte load, four
-// independent gather chains) to keep more loads in flight.  A pass follows
-// at most kJumpHops links per vertex; a pass that stops short raises its flag
-// and the next pass runs.  After pass p every entry has advanced kJumpHops^p
-// links or become final, so kJumpPasses passes cover any path in a grid of
-// fewer than 2^31 vertices.
-__device__ __forceinline__ int follow_links(int32_t* lab, int x)
+// Stage (b): labels.  After classification every vertex holds a final label
+// (its maximum) or a code for a later vertex of its steepest-ascent path: a
+// vertex id, or an entry of the exit list (the distinct vertices where paths
+// leave a tile, published once per tile).  The pass resolves the short exit
+// list first, by pointer jumping, and then every vertex with one look-up;
+// vertex-id codes (grids without tiling, or a full exit list) are resolved by
+// pointer jumping over the label array itself.
+//
+// Entries are updated in place while other threads read them.  Every value
+// ever stored says something true about the same path, so any value read is
+// usable.  A pass follows at most kJumpHops links per entry; a pass that stops
+// short raises its flag and the next pass runs.  After pass p every entry has
+// advanced kJumpHops^p links or become final, so kJumpPasses passes cover any
+// path in a grid of fewer than 2^31 vertices.
+
+__device__ __forceinline__ int next_link(const int32_t* lab, const int32_t* res, int N, int x)
 {
-    int h = 0;
-    while (x < 0 && h < kJumpHops) {
-        x = lab[-x - 1];
-        ++h;
-    }
-    return x;
+    return x >= -N ? lab[-x - 1] : res[-x - 1 - N];
 }
 
-__global__ __launch_bounds__(256) void k_jump(int32_t* lab, int32_t N, uint32_t* __restrict__ ctr, int pass)
+__device__ __forceinline__ bool gate(const uint32_t* ctr, int flag_base, int pass)
 {
-    if (pass > 0 && __hip_atomic_load(&ctr[C_JUMP + pass - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
-        return;
+    return pass == 0 ||
+           __hip_atomic_load(&ctr[flag_base + pass - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+__global__ __launch_bounds__(256) void k_exit_init(const uint32_t* __restrict__ exits, int32_t* __restrict__ res,
+                                                   const int32_t* __restrict__ lab, const uint32_t* __restrict__ ctr,
+                                                   uint32_t cap)
+{
+    const uint32_t req = __hip_atomic_load(&ctr[C_NEXIT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t n = req < cap ? req : cap;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        res[i] = lab[exits[i]];
+}
+
+__global__ __launch_bounds__(256) void k_exit_jump(int32_t* res, const int32_t* __restrict__ lab, int N,
+                                                   uint32_t* __restrict__ ctr, uint32_t cap, int pass)
+{
+    if (!gate(ctr, C_JUMP, pass)) return;
+    const uint32_t req = __hip_atomic_load(&ctr[C_NEXIT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t n = req < cap ? req : cap;
+    bool notdone = false;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int x = res[i];
+        if (x >= 0) continue;
+        int h = 0;
+        do {
+            x = next_link(lab, res, N, x);
+            ++h;
+        } while (x < 0 && h < kJumpHops);
+        res[i] = x;
+        notdone |= x < 0;
+    }
+    if (__ballot(notdone) != 0 && __lane_id() == 0) atomicOr(&ctr[C_JUMP + pass], 1u);
+}
+
+// Per-vertex pass: four consecutive vertices per thread (one 16-byte load,
+// four independent chains).
+__global__ __launch_bounds__(256) void k_final(int32_t* lab, const int32_t* __restrict__ res, int32_t N,
+                                               uint32_t* __restrict__ ctr, int pass)
+{
+    if (!gate(ctr, C_FINAL, pass)) return;
     bool notdone = false;
     const int nq = N >> 2;
     const int stride = gridDim.x * blockDim.x;
@@ -184,17 +222,16 @@ __global__ __launch_bounds__(256) void k_jump(int32_t* lab, int32_t N, uint32_t*
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += stride) {
         const int4 x = lab4[q];
         if ((x.x | x.y | x.z | x.w) >= 0) continue;  // all four final
-        // first links of the four chains are independent loads
-        int y0 = x.x < 0 ? lab[-x.x - 1] : x.x;
-        int y1 = x.y < 0 ? lab[-x.y - 1] : x.y;
-        int y2 = x.z < 0 ? lab[-x.z - 1] : x.z;
-        int y3 = x.w < 0 ? lab[-x.w - 1] : x.w;
+        int y0 = x.x < 0 ? next_link(lab, res, N, x.x) : x.x;
+        int y1 = x.y < 0 ? next_link(lab, res, N, x.y) : x.y;
+        int y2 = x.z < 0 ? next_link(lab, res, N, x.z) : x.z;
+        int y3 = x.w < 0 ? next_link(lab, res, N, x.w) : x.w;
         int h = 1;
         while ((y0 < 0 || y1 < 0 || y2 < 0 || y3 < 0) && h < kJumpHops) {
-            if (y0 < 0) y0 = lab[-y0 - 1];
-            if (y1 < 0) y1 = lab[-y1 - 1];
-            if (y2 < 0) y2 = lab[-y2 - 1];
-            if (y3 < 0) y3 = lab[-y3 - 1];
+            if (y0 < 0) y0 = next_link(lab, res, N, y0);
+            if (y1 < 0) y1 = next_link(lab, res, N, y1);
+            if (y2 < 0) y2 = next_link(lab, res, N, y2);
+            if (y3 < 0) y3 = next_link(lab, res, N, y3);
             ++h;
         }
         lab4[q] = make_int4(y0, y1, y2, y3);
@@ -204,31 +241,33 @@ __global__ __launch_bounds__(256) void k_jump(int32_t* lab, int32_t N, uint32_t*
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < (N & 3)) {
         const int v = (nq << 2) + t;
-        const int y = follow_links(lab, lab[v]);
+        int y = lab[v];
+        for (int h = 0; y < 0 && h < kJumpHops; ++h) y = next_link(lab, res, N, y);
         lab[v] = y;
         notdone |= y < 0;
     }
-    if (__ballot(notdone) != 0 && __lane_id() == 0) atomicOr(&ctr[C_JUMP + pass], 1u);
+    if (__ballot(notdone) != 0 && __lane_id() == 0) atomicOr(&ctr[C_FINAL + pass], 1u);
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctr[C_PASSES], 1u);
 }
 
-hipError_t launch_jump(int32_t* lab, int32_t N, uint32_t* ctr, hipStream_t s)
+hipError_t launch_labels(int32_t* lab, int32_t N, const Work& w, hipStream_t s)
 {
     if (reinterpret_cast<uintptr_t>(lab) & 15u) return hipErrorInvalidValue;
+    const uint32_t cap = (uint32_t)w.cap_exit;
+    const int64_t ewant = (w.cap_exit + 255) / 256;
+    const int eblocks = (int)(ewant < 2048 ? (ewant > 0 ? ewant : 1) : 2048);
+    hipLaunchKernelGGL(k_exit_init, dim3(eblocks), dim3(256), 0, s, w.exits, w.exres, lab, w.ctr, cap);
+    for (int p = 0; p < kJumpPasses; ++p)
+        hipLaunchKernelGGL(k_exit_jump, dim3(eblocks), dim3(256), 0, s, w.exres, lab, N, w.ctr, cap, p);
     const int64_t want = ((int64_t)N / 4 + 255) / 256;
     const int blocks = (int)(want < 8192 ? (want > 0 ? want : 1) : 8192);
-    for (int p = 0; p < kJumpPasses; ++p) {
-        hipLaunchKernelGGL(k_jump, dim3(blocks), dim3(256), 0, s, lab, N, ctr, p);
-    }
+    for (int p = 0; p < kJumpPasses; ++p)
+        hipLaunchKernelGGL(k_final, dim3(blocks), dim3(256), 0, s, lab, w.exres, N, w.ctr, p);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ saddle reps
 
-__device__ __forceinline__ uint64_t make_key(uint32_t s, uint32_t low, uint32_t marker, int b)
-{
-    return (uint64_t(s) << (b + 1)) | (uint64_t(marker) << b) | uint64_t(low);
-}
 
 template <int NDIM, bool MINMODE>
 __global__ __launch_bounds__(256) void k_reps(const float* __restrict__ f, Grid g, LinkTable t,
@@ -282,10 +321,10 @@ __global__ __launch_bounds__(256) void k_reps(const float* __restrict__ f, Grid 
                     rep = u_id;
                 }
             }
-            if (q < cap_keys) keys[q] = make_key((uint32_t)v, (uint32_t)lab[rep], 0u, b);
+            if (q < cap_keys) keys[q] = saddle_key((uint32_t)v, (uint32_t)lab[rep], 0u, b);
             ++q;
         }
-        if (q < cap_keys) keys[q] = make_key((uint32_t)v, (uint32_t)beta, 1u, b);
+        if (q < cap_keys) keys[q] = saddle_key((uint32_t)v, (uint32_t)beta, 1u, b);
     }
 }
 
@@ -331,6 +370,7 @@ __global__ void k_finalize(const uint32_t* __restrict__ ctr, int32_t* __restrict
     const int64_t nmax = ctr[C_NMAX], nsad = ctr[C_NSAD], nkeys = ctr[C_NKEYS], narc = ctr[C_NARC];
     const bool sad_over = nsad > cap_sad;
     const bool keys_over = nkeys > cap_keys;
+    const int64_t nmax_keys = nmax < cap_max ? nmax : cap_max;
     int status = EG_OK;
     if (ctr[C_NAN])
         status = EG_ERR_NAN;
@@ -340,8 +380,9 @@ __global__ void k_finalize(const uint32_t* __restrict__ ctr, int32_t* __restrict
     header[EG_H_NMAX] = (int32_t)nmax;
     header[EG_H_NSAD] = (int32_t)nsad;
     header[EG_H_NARC] = (sad_over || keys_over) ? -1 : (int32_t)narc;
-    header[EG_H_NPAIRS] = sad_over ? -1 : (int32_t)(nkeys - nsad);
+    header[EG_H_NPAIRS] = sad_over ? -1 : (int32_t)(nkeys - nsad - nmax_keys);
     header[EG_H_PASSES] = (int32_t)ctr[C_PASSES];
+    header[EG_H_EXITS] = (int32_t)ctr[C_NEXIT];
 }
 
 hipError_t launch_finalize(const Work& w, const eg_out& o, hipStream_t s)

@@ -104,12 +104,74 @@ __device__ __forceinline__ void double_tile_chains(int (&cur)[VPT], int32_t* s_n
     }
 }
 
+// After the tile's chains are resolved, cur[k] is a tile-local maximum (>= 0)
+// or -(h + 1) for the exit at halo position h.  The tile flags the halo
+// positions used as exits, numbers them with a block scan, appends their
+// vertex ids to the exit list (one atomic per tile) and turns every exit into
+// an exit-list code, so the label pass resolves each exit once.  A tile that
+// does not fit in the list keeps vertex-id codes.  s_words must hold
+// (HALO + 1) / 2 words of LDS that nobody else uses any more.
+template <int VPT, int HALO, class H2G>
+__device__ __forceinline__ void publish_exits(int (&cur)[VPT], uint32_t* s_words, uint32_t* s_tmp,
+                                              uint32_t* __restrict__ ctr, uint32_t* __restrict__ exits,
+                                              uint32_t cap_exit, int N, H2G h2g)
+{
+    constexpr int WORDS = (HALO + 1) / 2;
+    constexpr int SEG = (HALO + 255) / 256;
+    uint16_t* s_map = reinterpret_cast<uint16_t*>(s_words);
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    for (int i = tid; i < WORDS; i += 256) s_words[i] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < VPT; ++k)
+        if (cur[k] < 0) s_map[-cur[k] - 1] = 1;
+    __syncthreads();
+    const int lo = tid * SEG;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int i = 0; i < SEG; ++i)
+        if (lo + i < HALO) cnt += s_map[lo + i];
+    // block-wide exclusive scan of the counts
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) s_tmp[w] = inc;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int k = 0; k < w; ++k) pre += s_tmp[k];
+    const uint32_t total = s_tmp[0] + s_tmp[1] + s_tmp[2] + s_tmp[3];
+    if (tid == 0) s_tmp[4] = total ? atomicAdd(&ctr[C_NEXIT], total) : 0u;
+    __syncthreads();
+    const uint32_t base = s_tmp[4];
+    const bool ok = (uint64_t)base + total <= cap_exit;
+    uint32_t r = pre + inc - cnt;
+#pragma unroll
+    for (int i = 0; i < SEG; ++i) {
+        const int h = lo + i;
+        if (h < HALO && s_map[h]) {
+            // entries below the capacity are always written, so the list
+            // never holds garbage even when this tile does not use it
+            if (base + r < cap_exit) exits[base + r] = (uint32_t)h2g(h);
+            s_map[h] = (uint16_t)r;
+            ++r;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        if (cur[k] < 0) {
+            const int h = -cur[k] - 1;
+            cur[k] = ok ? exit_list_code(N, base + s_map[h]) : -(h2g(h) + 1);
+        }
+    }
+}
+
 template <int NDIM, bool MINMODE, int TY, int TZ>
-__global__ __launch_bounds__(256) void k_classify_tiled(const float* __restrict__ f, int X, int Y, int Z, int tiles_x,
-                                                        int tiles_y, int ntiles, int32_t* __restrict__ lab,
-                                                        int32_t* __restrict__ ptr, uint32_t* __restrict__ ctr,
-                                                        uint32_t* __restrict__ umax, uint32_t cap_max,
-                                                        uint32_t* __restrict__ usad, uint32_t cap_sad)
+__device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u, int32_t* s_nxt, uint32_t* s_conn,
+                                        uint32_t* s_tmp)
 {
     static_assert(NDIM == 2 || NDIM == 3, "tiled path is for 2D and 3D");
     static_assert(TY % 4 == 0, "four waves split the y rows");
@@ -117,22 +179,20 @@ __global__ __launch_bounds__(256) void k_classify_tiled(const float* __restrict_
     constexpr int TX = 64;
     constexpr int HX = TX + 2, HY = TY + 2, HZ = NDIM == 3 ? TZ + 2 : 1;
     constexpr int HALO = HX * HY * HZ;
-    constexpr int TILE = TX * TY * TZ;
     constexpr int YPT = TY / 4;
     constexpr int VPT = YPT * TZ;
     constexpr int ZH = NDIM == 3 ? 1 : 0;  // halo depth along z
-
-    __shared__ uint32_t s_u[HALO];
-    __shared__ int32_t s_nxt[TILE];
-    __shared__ uint32_t s_conn[NDIM == 3 ? 512 : 1];
+    const float* __restrict__ f = a.f;
+    const int X = a.X, Y = a.Y, Z = a.Z;
+    int32_t* __restrict__ lab = a.lab;
+    int32_t* __restrict__ ptr = a.ptr;
+    uint32_t* __restrict__ ctr = a.ctr;
 
     const int tid = threadIdx.x, lx = tid & 63, wv = tid >> 6;
-    int b = blockIdx.x;
-    if ((ntiles & 7) == 0) b = (b & 7) * (ntiles >> 3) + (b >> 3);
-    const int tx = b % tiles_x;
-    const int rr = b / tiles_x;
-    const int ty = rr % tiles_y;
-    const int tz = rr / tiles_y;
+    const int tx = b % a.tiles_x;
+    const int rr = b / a.tiles_x;
+    const int ty = rr % a.tiles_y;
+    const int tz = rr / a.tiles_y;
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
     const int SY = X;
     const int SZ = X * Y;
@@ -180,7 +240,7 @@ __global__ __launch_bounds__(256) void k_classify_tiled(const float* __restrict_
         const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
         const bool in = gx < X && gy < Y && gz < Z;
         const int li = (lz * TY + ly) * TX + lx;
-        int n = -1;
+        int n = li;  // vertices outside the grid stay put and are never written
         bool is_max = false, is_sad = false;
         int v = 0;
         if (in) {
@@ -231,19 +291,24 @@ __global__ __launch_bounds__(256) void k_classify_tiled(const float* __restrict_
                 const int lz2 = lz + dz, ly2 = ly + dy, lx2 = lx + dx;
                 const bool inside = (unsigned)lz2 < (unsigned)TZ && (unsigned)ly2 < (unsigned)TY &&
                                     (unsigned)lx2 < (unsigned)TX;
-                n = inside ? (lz2 * TY + ly2) * TX + lx2 : -(pv + 1);
+                n = inside ? (lz2 * TY + ly2) * TX + lx2 : -(c + (dz * HY + dy) * HX + dx + 1);
             }
             if (ptr) ptr[v] = pv;
         }
         nxt[k] = n;
         s_nxt[li] = n;
-        wave_append(is_max, (uint32_t)v, &ctr[C_NMAX], umax, cap_max);
-        wave_append(is_sad, (uint32_t)v, &ctr[C_NSAD], usad, cap_sad);
+        wave_append(is_max, (uint32_t)v, &ctr[C_NMAX], a.umax, a.cap_max);
+        wave_append(is_sad, (uint32_t)v, &ctr[C_NSAD], a.usad, a.cap_sad);
     }
     if (__ballot(nan) != 0 && __lane_id() == 0) atomicOr(&ctr[C_NAN], 1u);
     __syncthreads();
 
     double_tile_chains<VPT>(nxt, s_nxt, [&](int k) { return ((k / YPT) * TY + wv + 4 * (k % YPT)) * TX + lx; });
+    const int N = X * Y * Z;
+    publish_exits<VPT, HALO>(nxt, s_u, s_tmp, ctr, a.exits, a.cap_exit, N, [&](int h) {
+        const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+        return (z0 + hz - ZH) * SZ + (y0 + hy - 1) * SY + x0 + hx - 1;
+    });
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
         const int ly = wv + 4 * (k % YPT);
@@ -271,11 +336,7 @@ struct Win {
 };
 
 template <bool MINMODE, int TY, int TZ>
-__global__ __launch_bounds__(256) void k_classify3d(const float* __restrict__ f, int X, int Y, int Z, int tiles_x,
-                                                    int tiles_y, int ntiles, int32_t* __restrict__ lab,
-                                                    int32_t* __restrict__ ptr, uint32_t* __restrict__ ctr,
-                                                    uint32_t* __restrict__ umax, uint32_t cap_max,
-                                                    uint32_t* __restrict__ usad, uint32_t cap_sad)
+__device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, uint32_t* s_conn, uint32_t* s_tmp)
 {
     constexpr int K = 14;
     constexpr int TX = 64;
@@ -286,18 +347,18 @@ __global__ __launch_bounds__(256) void k_classify3d(const float* __restrict__ f,
     constexpr int VPT = YPT * TZ;
     static_assert(TILE <= HALO, "the chains reuse the halo's LDS");
     static_assert(TY % 4 == 0, "four waves split the y rows");
-
-    __shared__ uint32_t s_u[HALO];
-    __shared__ uint32_t s_conn[512];
+    const float* __restrict__ f = a.f;
+    const int X = a.X, Y = a.Y, Z = a.Z;
+    int32_t* __restrict__ lab = a.lab;
+    int32_t* __restrict__ ptr = a.ptr;
+    uint32_t* __restrict__ ctr = a.ctr;
     int32_t* s_nxt = reinterpret_cast<int32_t*>(s_u);
 
     const int tid = threadIdx.x, lx = tid & 63, wv = tid >> 6;
-    int b = blockIdx.x;
-    if ((ntiles & 7) == 0) b = (b & 7) * (ntiles >> 3) + (b >> 3);
-    const int tx = b % tiles_x;
-    const int rr = b / tiles_x;
-    const int ty = rr % tiles_y;
-    const int tz = rr / tiles_y;
+    const int tx = b % a.tiles_x;
+    const int rr = b / a.tiles_x;
+    const int ty = rr % a.tiles_y;
+    const int tz = rr / a.tiles_y;
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
     const int SY = X;
     const int SZ = X * Y;
@@ -396,7 +457,7 @@ __global__ __launch_bounds__(256) void k_classify3d(const float* __restrict__ f,
             const bool is_max = in && up == 0;
             const bool is_sad = in && up != 0 && !((s_conn[up >> 5] >> (up & 31)) & 1u);
             const int v = gz * SZ + gy * SY + gx;
-            int n = -1;
+            int n = (lz * TY + ly) * TX + lx;  // vertices outside the grid stay put
             if (in) {
                 int pv = v;
                 if (best_j == K) {
@@ -409,13 +470,14 @@ __global__ __launch_bounds__(256) void k_classify3d(const float* __restrict__ f,
                     const int lz2 = lz + dz, ly2 = ly + dy, lx2 = lx + dx;
                     const bool inside = (unsigned)lz2 < (unsigned)TZ && (unsigned)ly2 < (unsigned)TY &&
                                         (unsigned)lx2 < (unsigned)TX;
-                    n = inside ? (lz2 * TY + ly2) * TX + lx2 : -(pv + 1);
+                    const int hpos = ((lz + 1 + dz) * HY + ly + 1 + dy) * HX + lx + 1 + dx;
+                    n = inside ? (lz2 * TY + ly2) * TX + lx2 : -(hpos + 1);
                 }
                 if (ptr) ptr[v] = pv;
             }
             nxt[c * TZ + lz] = n;
-            wave_append(is_max, (uint32_t)v, &ctr[C_NMAX], umax, cap_max);
-            wave_append(is_sad, (uint32_t)v, &ctr[C_NSAD], usad, cap_sad);
+            wave_append(is_max, (uint32_t)v, &ctr[C_NMAX], a.umax, a.cap_max);
+            wave_append(is_sad, (uint32_t)v, &ctr[C_NSAD], a.usad, a.cap_sad);
         }
     }
     if (__ballot(nan) != 0 && __lane_id() == 0) atomicOr(&ctr[C_NAN], 1u);
@@ -429,6 +491,10 @@ __global__ __launch_bounds__(256) void k_classify3d(const float* __restrict__ f,
     // successors (a maximum is its own successor), entries < 0 are
     // -(id + 1) of the first vertex outside the tile
     double_tile_chains<VPT>(nxt, s_nxt, [&](int k) { return ((k % TZ) * TY + wv + 4 * (k / TZ)) * TX + lx; });
+    publish_exits<VPT, HALO>(nxt, s_u, s_tmp, ctr, a.exits, a.cap_exit, X * Y * Z, [&](int h) {
+        const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+        return (z0 + hz - 1) * SZ + (y0 + hy - 1) * SY + x0 + hx - 1;
+    });
 #pragma unroll
     for (int c = 0; c < YPT; ++c) {
         const int ly = wv + 4 * c;
@@ -442,41 +508,131 @@ __global__ __launch_bounds__(256) void k_classify3d(const float* __restrict__ f,
     }
 }
 
-template <bool MINMODE, int TY, int TZ>
-static hipError_t launch_3d_t(const float* f, const Grid& g, int32_t* lab, int32_t* ptr, const Work& w,
-                              int64_t cap_max, int64_t cap_sad, hipStream_t s)
+// Tiles of one XCD are consecutive in memory: workgroups are dispatched to
+// the eight XCDs round-robin, so block b takes tile (b % 8) * (T / 8) + b / 8.
+__device__ __forceinline__ int xcd_tile(int b, int ntiles)
 {
-    const int X = g.dims[2], Y = g.dims[1], Z = g.dims[0];
-    const int tiles_x = (X + 63) / 64, tiles_y = (Y + TY - 1) / TY, tiles_z = (Z + TZ - 1) / TZ;
-    const int64_t ntiles = (int64_t)tiles_x * tiles_y * tiles_z;
-    hipLaunchKernelGGL((k_classify3d<MINMODE, TY, TZ>), dim3((unsigned)ntiles), dim3(256), 0, s, f, X, Y, Z,
-                       tiles_x, tiles_y, (int)ntiles, lab, ptr, w.ctr, w.umax, (uint32_t)cap_max, w.usad,
-                       (uint32_t)cap_sad);
-    return hipGetLastError();
+    return (ntiles & 7) == 0 ? (b & 7) * (ntiles >> 3) + (b >> 3) : b;
 }
 
-template <int NDIM, bool MINMODE, int TY, int TZ>
-static hipError_t launch_tiled_t(const float* f, const Grid& g, int32_t* lab, int32_t* ptr, const Work& w,
-                                 int64_t cap_max, int64_t cap_sad, hipStream_t s)
+template <bool MINMODE, int TY, int TZ>
+__global__ __launch_bounds__(256) void k_classify3d(TileArgs a)
 {
-    const int X = g.dims[NDIM - 1], Y = g.dims[NDIM - 2], Z = NDIM == 3 ? g.dims[0] : 1;
-    const int tiles_x = (X + 63) / 64, tiles_y = (Y + TY - 1) / TY, tiles_z = (Z + TZ - 1) / TZ;
-    const int64_t ntiles = (int64_t)tiles_x * tiles_y * tiles_z;
-    hipLaunchKernelGGL((k_classify_tiled<NDIM, MINMODE, TY, TZ>), dim3((unsigned)ntiles), dim3(256), 0, s, f, X, Y,
-                       Z, tiles_x, tiles_y, (int)ntiles, lab, ptr, w.ctr, w.umax, (uint32_t)cap_max, w.usad,
-                       (uint32_t)cap_sad);
+    constexpr int HALO = 66 * (TY + 2) * (TZ + 2);
+    __shared__ uint32_t s_u[HALO];
+    __shared__ uint32_t s_conn[512];
+    __shared__ uint32_t s_tmp[8];
+    tile3d<MINMODE, TY, TZ>(a, xcd_tile(blockIdx.x, a.ntiles), s_u, s_conn, s_tmp);
+}
+
+template <bool MINMODE, int TY>
+__global__ __launch_bounds__(256) void k_classify2d(TileArgs a)
+{
+    __shared__ uint32_t s_u[66 * (TY + 2)];
+    __shared__ int32_t s_nxt[64 * TY];
+    __shared__ uint32_t s_tmp[8];
+    tile_nd<2, MINMODE, TY, 1>(a, xcd_tile(blockIdx.x, a.ntiles), s_u, s_nxt, nullptr, s_tmp);
+}
+
+TileArgs tile_args(const float* f, const Grid& g, int32_t* lab, int32_t* ptr, const Work& w, int64_t cap_max,
+                   int64_t cap_sad, int ty, int tz)
+{
+    TileArgs a{};
+    a.f = f;
+    a.lab = lab;
+    a.ptr = ptr;
+    a.ctr = w.ctr;
+    a.umax = w.umax;
+    a.usad = w.usad;
+    a.exits = w.exits;
+    a.X = g.dims[g.ndim - 1];
+    a.Y = g.dims[g.ndim - 2];
+    a.Z = g.ndim == 3 ? g.dims[0] : 1;
+    a.tiles_x = (a.X + 63) / 64;
+    a.tiles_y = (a.Y + ty - 1) / ty;
+    const int tiles_z = (a.Z + tz - 1) / tz;
+    a.ntiles = a.tiles_x * a.tiles_y * tiles_z;
+    a.cap_max = (uint32_t)cap_max;
+    a.cap_sad = (uint32_t)cap_sad;
+    a.cap_exit = (uint32_t)w.cap_exit;
+    return a;
+}
+
+// Persistent classification of a batch: a fixed grid walks the work list of
+// (field, tile) items of all fields; each item runs the 2D or 3D tile code of
+// its field.  The LDS of the largest tile type is shared by both.
+__device__ __forceinline__ int find_field(const BatchField* fs, int count, int64_t item, int64_t BatchField::*base)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (fs[mid].*base <= item)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_classify_batched(const BatchPlan* __restrict__ plan)
+{
+    constexpr int HALO3 = 66 * (kTile3Y + 2) * (kTile3Z + 2);
+    constexpr int HALO2 = 66 * (kTile2Y + 2);
+    static_assert(HALO2 + 64 * kTile2Y <= HALO3, "2D tile fits in the 3D tile's LDS");
+    __shared__ uint32_t s_u[HALO3];
+    __shared__ uint32_t s_conn[512];
+    __shared__ uint32_t s_tmp[8];
+    const int count = plan->count;
+    const int64_t total = plan->total_tiles;
+    const BatchField* fs = plan->fields;
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        const int f = __builtin_amdgcn_readfirstlane(find_field(fs, count, item, &BatchField::tile_base));
+        const int tile = (int)(item - fs[f].tile_base);
+        const TileArgs a = fs[f].ta;
+        const int ndim = fs[f].ndim, minima = fs[f].minima;
+        __syncthreads();  // the previous item's LDS reads are done
+        if (ndim == 3) {
+            if (minima)
+                tile3d<true, kTile3Y, kTile3Z>(a, tile, s_u, s_conn, s_tmp);
+            else
+                tile3d<false, kTile3Y, kTile3Z>(a, tile, s_u, s_conn, s_tmp);
+        } else {
+            int32_t* s_nxt = reinterpret_cast<int32_t*>(s_u + HALO2);
+            if (minima)
+                tile_nd<2, true, kTile2Y, 1>(a, tile, s_u, s_nxt, nullptr, s_tmp);
+            else
+                tile_nd<2, false, kTile2Y, 1>(a, tile, s_u, s_nxt, nullptr, s_tmp);
+        }
+    }
+}
+
+hipError_t launch_classify_batched(const BatchPlan* dplan, const BatchPlan& hplan, hipStream_t s)
+{
+    // five 28 KB workgroups fit a CU; 256 CUs
+    const int64_t grid = hplan.total_tiles < 1280 ? hplan.total_tiles : 1280;
+    hipLaunchKernelGGL(k_classify_batched, dim3((unsigned)(grid > 0 ? grid : 1)), dim3(256), 0, s, dplan);
     return hipGetLastError();
 }
 
 hipError_t launch_classify_tiled(const float* f, const Grid& g, bool minima, int32_t* lab, int32_t* ptr,
                                  const Work& w, int64_t cap_max, int64_t cap_sad, hipStream_t s)
 {
-    if (g.ndim == 3)
-        return minima ? launch_3d_t<true, 8, 8>(f, g, lab, ptr, w, cap_max, cap_sad, s)
-                      : launch_3d_t<false, 8, 8>(f, g, lab, ptr, w, cap_max, cap_sad, s);
-    if (g.ndim == 2)
-        return minima ? launch_tiled_t<2, true, 32, 1>(f, g, lab, ptr, w, cap_max, cap_sad, s)
-                      : launch_tiled_t<2, false, 32, 1>(f, g, lab, ptr, w, cap_max, cap_sad, s);
+    if (g.ndim == 3) {
+        const TileArgs a = tile_args(f, g, lab, ptr, w, cap_max, cap_sad, kTile3Y, kTile3Z);
+        if (minima)
+            hipLaunchKernelGGL((k_classify3d<true, kTile3Y, kTile3Z>), dim3(a.ntiles), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_classify3d<false, kTile3Y, kTile3Z>), dim3(a.ntiles), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+    if (g.ndim == 2) {
+        const TileArgs a = tile_args(f, g, lab, ptr, w, cap_max, cap_sad, kTile2Y, 1);
+        if (minima)
+            hipLaunchKernelGGL((k_classify2d<true, kTile2Y>), dim3(a.ntiles), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_classify2d<false, kTile2Y>), dim3(a.ntiles), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     return hipErrorInvalidValue;
 }
 

@@ -28,6 +28,8 @@ constexpr int kJumpPasses = 6;      // 64^6 > 2^31: enough for any chain
 constexpr int kSortBlocks = 256;    // grid of the radix-sort kernels
 constexpr int kSortThreads = 256;
 constexpr int kRadixBits = 8;
+constexpr int kTile3Y = 8, kTile3Z = 8;  // 3D tile: 64 x 8 x 8 vertices
+constexpr int kTile2Y = 32;             // 2D tile: 64 x 32 vertices
 
 // counter slots in the workspace (uint32 each)
 enum : int {
@@ -38,7 +40,9 @@ enum : int {
     C_NARC = 4,
     C_NSADF = 5,
     C_PASSES = 6,
-    C_JUMP = 8,   // kJumpPasses "not converged" flags
+    C_NEXIT = 7,  // exit-list entries requested by the tiles
+    C_JUMP = 8,   // kJumpPasses "not converged" flags of the exit-list passes
+    C_FINAL = 16, // kJumpPasses "not converged" flags of the per-vertex passes
     C_SLOTS = 64,
 };
 
@@ -64,16 +68,67 @@ struct Work {
     uint64_t* keysA;  // [cap_keys]
     uint64_t* keysB;  // [cap_keys]
     uint32_t* hist;   // [256 * kSortBlocks + 2 * kSortBlocks + 64]
+    uint32_t* exits;  // [cap_exit] exit vertices published by the tiles
+    int32_t* exres;   // [cap_exit] their labels while being resolved
     int64_t cap_keys;
+    int64_t cap_exit;
     size_t bytes;
+};
+
+// Everything a classification tile needs to know about its field.
+struct TileArgs {
+    const float* f;
+    int32_t* lab;
+    int32_t* ptr;
+    uint32_t* ctr;
+    uint32_t* umax;
+    uint32_t* usad;
+    uint32_t* exits;
+    int32_t X, Y, Z, tiles_x, tiles_y, ntiles;
+    uint32_t cap_max, cap_sad, cap_exit;
+};
+
+// One field of a batch (device-resident plan, built on the host).
+struct BatchField {
+    TileArgs ta;
+    int32_t ndim, minima, N, pad0;
+    int64_t tile_base;   // exclusive prefix over fields of tiles
+    int64_t quad_base;   // ... of label quads, ceil(N / 4)
+    int64_t sad_base;    // ... of saddle capacities
+    int64_t exit_base;   // ... of exit-list capacities
+    int64_t max_base;    // ... of maxima capacities
+    int32_t* exres;
+    int32_t* header;
+    int32_t* maxima;
+    int32_t* saddles;
+    int32_t* beta;
+    int32_t* offsets;
+    int32_t* arcs;
+    uint32_t cap_arc, cap_keys;
+};
+
+struct BatchPlan {
+    int32_t count, bits, fbits, pad0;
+    int64_t total_tiles, total_quads, total_sad, total_exit, total_max, cap_keys;
+    uint32_t* bctr;       // [C_SLOTS] batch counters
+    uint64_t* keysA;      // [cap_keys]
+    uint64_t* keysB;
+    uint32_t* hist;       // [256 * kSortBlocks + 2 * kSortBlocks + 64]
+    uint32_t* seg;        // [3 * (count + 1)]: per field, first key index, arc rank, saddle rank
+    BatchField* fields;   // device address of fields[] (right after this header)
+    const BatchPlan* dev; // device address of this plan (start of the batch workspace)
+    int64_t plan_bytes;
 };
 
 // Host: table rows for ndim (Alg. 1), independent of dims.  Returns k.
 int make_rows(int ndim, int8_t (*off)[EG_MAX_NDIM], uint64_t* adj);
 // Host: full kernel table for a grid.
 void make_table(const Grid& g, LinkTable* t);
-// Host: carve (or size, when base == nullptr) the workspace.
-Work carve(void* base, int64_t cap_max, int64_t cap_sad, int64_t cap_pairs);
+// Host: carve (or size, when base == nullptr) the workspace of a grid with N
+// vertices.
+Work carve(void* base, int64_t N, int64_t cap_max, int64_t cap_sad, int64_t cap_pairs);
+// Exit-list capacity for a grid of N vertices (label codes need N + cap < 2^31).
+int64_t exit_capacity(int64_t N);
 // Bits needed to hold any vertex id of a grid with N vertices.
 inline int id_bits(int64_t N)
 {
@@ -160,16 +215,41 @@ hipError_t launch_classify(const float* f, const Grid& g, const LinkTable& t, bo
                            int32_t* ptr, const Work& w, int64_t cap_max, int64_t cap_sad, hipStream_t s);
 hipError_t launch_classify_tiled(const float* f, const Grid& g, bool minima, int32_t* lab, int32_t* ptr,
                                  const Work& w, int64_t cap_max, int64_t cap_sad, hipStream_t s);
-hipError_t launch_jump(int32_t* lab, int32_t N, uint32_t* ctr, hipStream_t s);
+TileArgs tile_args(const float* f, const Grid& g, int32_t* lab, int32_t* ptr, const Work& w, int64_t cap_max,
+                   int64_t cap_sad, int ty, int tz);
+hipError_t launch_classify_batched(const BatchPlan* dplan, const BatchPlan& hplan, hipStream_t s);
+hipError_t launch_batched_rest(const BatchPlan* dplan, const BatchPlan& hplan, hipStream_t s);
+
+// Sort keys of stage (d), b = id_bits(N), 2b + 2 bits in all:
+//   bit 2b+1      0 for a maximum entry, 1 for a saddle entry (maxima sort first)
+//   bits b+1..2b  the vertex (the maximum, or the saddle)
+//   bit b         marker: 1 on the one entry per saddle that closes its row
+//   bits 0..b-1   the maximum an arc reaches, or the marker's component count
+__device__ __forceinline__ uint64_t max_key(uint32_t m, int b) { return uint64_t(m) << (b + 1); }
+__device__ __forceinline__ uint64_t saddle_key(uint32_t s, uint32_t low, uint32_t marker, int b)
+{
+    return (uint64_t(1) << (2 * b + 1)) | (uint64_t(s) << (b + 1)) | (uint64_t(marker) << b) | uint64_t(low);
+}
+
+// Label codes between classification and the label pass (int32):
+//   x >= 0            final: the maximum x
+//   -N <= x <= -1     "same label as vertex -x-1" (a later vertex of the path)
+//   x < -N            "same label as exit-list entry -x-1-N"
+__device__ __forceinline__ int exit_list_code(int N, uint32_t idx) { return -(N + 1 + (int)idx); }
+hipError_t launch_labels(int32_t* lab, int32_t N, const Work& w, hipStream_t s);
 hipError_t launch_reps(const float* f, const Grid& g, const LinkTable& t, bool minima, const int32_t* lab,
                        const Work& w, int64_t cap_sad, int bits, hipStream_t s);
 // Sort keys[0 .. min(*count, cap)) over bits [0, nbits).  Returns in *sorted
-// the buffer holding the result (one of a, b); with out32 != nullptr the last
-// pass writes the low 32 bits there instead.
+// the buffer holding the result (one of a, b).
 hipError_t launch_sort(uint64_t* a, uint64_t* b, const uint32_t* count, int64_t cap, int nbits, uint32_t* hist,
-                       int32_t* out32, uint64_t** sorted, hipStream_t s);
-hipError_t launch_load_maxima(const Work& w, int64_t cap_max, hipStream_t s);
+                       uint64_t** sorted, hipStream_t s);
+hipError_t launch_load_maxima(const Work& w, int64_t cap_max, int bits, hipStream_t s);
 hipError_t launch_csr(const uint64_t* keys, const Work& w, int bits, const eg_out& o, hipStream_t s);
+// Per-block arc and marker counts of sorted keys and their scan; totals into
+// ctr[C_NARC], ctr[C_NSADF]; block bases at hist + 256 * kSortBlocks.
+hipError_t launch_csr_counts(const uint64_t* keys, const uint32_t* count, int64_t cap, int bits, uint32_t* hist,
+                             uint32_t* ctr, hipStream_t s);
+hipError_t launch_batched_init(const BatchPlan* dplan, const BatchPlan& hplan, hipStream_t s);
 hipError_t launch_finalize(const Work& w, const eg_out& o, hipStream_t s);
 
 }  // namespace eg

@@ -46,19 +46,23 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
     return x;
 }
 
-__global__ __launch_bounds__(256) void k_load_maxima(const uint32_t* __restrict__ umax,
-                                                     const uint32_t* __restrict__ ctr, uint32_t cap_max,
-                                                     uint64_t* __restrict__ keys)
+// The maxima become the first keys; the saddle entries are appended after
+// them (the key counter starts at the number of maxima).
+__global__ __launch_bounds__(256) void k_load_maxima(const uint32_t* __restrict__ umax, uint32_t* __restrict__ ctr,
+                                                     uint32_t cap_max, uint64_t* __restrict__ keys, int b)
 {
     const uint32_t n = load_count(&ctr[C_NMAX], cap_max);
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) keys[i] = umax[i];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        keys[i] = max_key(umax[i], b);
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctr[C_NKEYS], n);
 }
 
-hipError_t launch_load_maxima(const Work& w, int64_t cap_max, hipStream_t s)
+hipError_t launch_load_maxima(const Work& w, int64_t cap_max, int bits, hipStream_t s)
 {
     int64_t want = (cap_max + 255) / 256;
     const int blocks = (int)(want < 1024 ? (want > 0 ? want : 1) : 1024);
-    hipLaunchKernelGGL(k_load_maxima, dim3(blocks), dim3(256), 0, s, w.umax, w.ctr, (uint32_t)cap_max, w.keysA);
+    hipLaunchKernelGGL(k_load_maxima, dim3(blocks), dim3(256), 0, s, w.umax, w.ctr, (uint32_t)cap_max, w.keysA,
+                       bits);
     return hipGetLastError();
 }
 
@@ -129,8 +133,8 @@ __global__ __launch_bounds__(1024) void k_scan_hist(uint32_t* __restrict__ a, co
 }
 
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
-                                                       int32_t* __restrict__ out32, const uint32_t* count,
-                                                       uint32_t cap, int shift, const uint32_t* __restrict__ hist)
+                                                       const uint32_t* count, uint32_t cap, int shift,
+                                                       const uint32_t* __restrict__ hist)
 {
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[4][256];
@@ -163,11 +167,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t* __restric
         if (valid) {
             uint32_t pre = run[d];
             for (int k = 0; k < w; ++k) pre += wcnt[k][d];
-            const uint32_t dest = pre + rank;
-            if (out32)
-                out32[dest] = (int32_t)(uint32_t)key;
-            else
-                out[dest] = key;
+            out[pre + rank] = key;
         }
         __syncthreads();
         run[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
@@ -176,26 +176,22 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t* __restric
 }
 
 hipError_t launch_sort(uint64_t* a, uint64_t* b, const uint32_t* count, int64_t cap, int nbits, uint32_t* hist,
-                       int32_t* out32, uint64_t** sorted, hipStream_t s)
+                       uint64_t** sorted, hipStream_t s)
 {
     const int passes = (nbits + kRadixBits - 1) / kRadixBits;
     uint64_t* src = a;
     uint64_t* dst = b;
     for (int p = 0; p < passes; ++p) {
         const int shift = p * kRadixBits;
-        const bool last = p == passes - 1;
         hipLaunchKernelGGL(k_radix_hist, dim3(kSortBlocks), dim3(kSortThreads), 0, s, src, count, (uint32_t)cap,
                            shift, hist);
         hipLaunchKernelGGL(k_scan_hist, dim3(1), dim3(1024), 0, s, hist, count, (uint32_t)cap,
                            (uint32_t)kSortBlocks);
-        int32_t* o32 = (last && out32) ? out32 : nullptr;
-        hipLaunchKernelGGL(k_radix_scatter, dim3(kSortBlocks), dim3(kSortThreads), 0, s, src, dst, o32, count,
+        hipLaunchKernelGGL(k_radix_scatter, dim3(kSortBlocks), dim3(kSortThreads), 0, s, src, dst, count,
                            (uint32_t)cap, shift, hist);
-        if (!o32) {
-            uint64_t* t = src;
-            src = dst;
-            dst = t;
-        }
+        uint64_t* t = src;
+        src = dst;
+        dst = t;
     }
     if (sorted) *sorted = src;
     return hipGetLastError();
@@ -204,17 +200,19 @@ hipError_t launch_sort(uint64_t* a, uint64_t* b, const uint32_t* count, int64_t 
 // ------------------------------------------------------------------ CSR
 
 struct KeyFlags {
-    bool arc;     // first copy of a (saddle, maximum) key
-    bool marker;  // end-of-saddle marker
+    bool maximum;  // a maximum entry (they sort first, so their rank is their index)
+    bool arc;      // first copy of a (saddle, maximum) key
+    bool marker;   // end-of-saddle marker
 };
 
 __device__ __forceinline__ KeyFlags key_flags(const uint64_t* keys, uint32_t i, uint32_t n, int b)
 {
-    KeyFlags r{false, false};
+    KeyFlags r{false, false, false};
     if (i < n) {
         const uint64_t k = keys[i];
-        r.marker = (k >> b) & 1ull;
-        r.arc = !r.marker && (i == 0 || keys[i - 1] != k);
+        r.maximum = !((k >> (2 * b + 1)) & 1ull);
+        r.marker = !r.maximum && ((k >> b) & 1ull);
+        r.arc = !r.maximum && !r.marker && (i == 0 || keys[i - 1] != k);
     }
     return r;
 }
@@ -283,7 +281,8 @@ __global__ __launch_bounds__(256) void k_csr_write(const uint64_t* __restrict__ 
                                                    uint32_t cap, int b, const uint32_t* __restrict__ bsum,
                                                    int32_t* __restrict__ saddles, int32_t* __restrict__ beta,
                                                    int32_t* __restrict__ offsets, uint32_t cap_sad,
-                                                   int32_t* __restrict__ arc_maxima, uint32_t cap_arc)
+                                                   int32_t* __restrict__ arc_maxima, uint32_t cap_arc,
+                                                   int32_t* __restrict__ maxima, uint32_t cap_max)
 {
     __shared__ uint32_t tmp[4];
     const uint32_t n = load_count(count, cap);
@@ -298,7 +297,9 @@ __global__ __launch_bounds__(256) void k_csr_write(const uint64_t* __restrict__ 
         uint32_t ta, ts;
         const uint32_t ra = block_rank(fl.arc, tmp, ta);
         const uint32_t rs = block_rank(fl.marker, tmp, ts);
-        if (fl.arc || fl.marker) {
+        if (fl.maximum) {
+            if (i < cap_max) maxima[i] = (int32_t)(uint32_t)(keys[i] >> (b + 1));
+        } else if (fl.arc || fl.marker) {
             const uint64_t k = keys[i];
             const uint32_t low = (uint32_t)(k & lowmask);
             if (fl.arc) {
@@ -307,7 +308,7 @@ __global__ __launch_bounds__(256) void k_csr_write(const uint64_t* __restrict__ 
             } else {
                 const uint32_t sp = sbase + rs;
                 if (sp < cap_sad) {
-                    saddles[sp] = (int32_t)(k >> (b + 1));
+                    saddles[sp] = (int32_t)((k >> (b + 1)) & lowmask);
                     if (beta) beta[sp] = (int32_t)low;
                     offsets[sp + 1] = (int32_t)(abase + ra);
                 }
@@ -318,16 +319,24 @@ __global__ __launch_bounds__(256) void k_csr_write(const uint64_t* __restrict__ 
     }
 }
 
+hipError_t launch_csr_counts(const uint64_t* keys, const uint32_t* count, int64_t cap, int bits, uint32_t* hist,
+                             uint32_t* ctr, hipStream_t s)
+{
+    uint32_t* bsum = hist + 256 * kSortBlocks;
+    hipLaunchKernelGGL(k_csr_count, dim3(kSortBlocks), dim3(256), 0, s, keys, count, (uint32_t)cap, bits, bsum);
+    hipLaunchKernelGGL(k_csr_scan, dim3(1), dim3(256), 0, s, bsum, kSortBlocks, ctr);
+    return hipGetLastError();
+}
+
 hipError_t launch_csr(const uint64_t* keys, const Work& w, int bits, const eg_out& o, hipStream_t s)
 {
     uint32_t* bsum = w.hist + 256 * kSortBlocks;
     const uint32_t* count = &w.ctr[C_NKEYS];
-    hipLaunchKernelGGL(k_csr_count, dim3(kSortBlocks), dim3(256), 0, s, keys, count, (uint32_t)w.cap_keys, bits,
-                       bsum);
-    hipLaunchKernelGGL(k_csr_scan, dim3(1), dim3(256), 0, s, bsum, kSortBlocks, w.ctr);
+    hipError_t e = launch_csr_counts(keys, count, w.cap_keys, bits, w.hist, w.ctr, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_csr_write, dim3(kSortBlocks), dim3(256), 0, s, keys, count, (uint32_t)w.cap_keys, bits,
                        bsum, o.saddles, o.saddle_beta, o.arc_offsets, (uint32_t)o.cap_sad, o.arc_maxima,
-                       (uint32_t)o.cap_arc);
+                       (uint32_t)o.cap_arc, o.maxima, (uint32_t)o.cap_max);
     return hipGetLastError();
 }
 

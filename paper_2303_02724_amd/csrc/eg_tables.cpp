@@ -64,11 +64,21 @@ void make_table(const Grid& g, LinkTable* t)
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-Work carve(void* base, int64_t cap_max, int64_t cap_sad, int64_t cap_pairs)
+int64_t exit_capacity(int64_t N)
+{
+    // tiles publish the distinct vertices where paths leave them; smooth
+    // fields need far fewer than N/16 entries, and an overflowing tile falls
+    // back to per-vertex codes, so this only bounds memory, not correctness
+    int64_t cap = std::max<int64_t>(N / 16, 4096);
+    const int64_t room = (int64_t(1) << 31) - 1 - N;
+    return std::max<int64_t>(0, std::min(cap, room));
+}
+
+Work carve(void* base, int64_t N, int64_t cap_max, int64_t cap_sad, int64_t cap_pairs)
 {
     Work w{};
-    w.cap_keys = std::max<int64_t>(cap_pairs + cap_sad, cap_max);
-    w.cap_keys = std::max<int64_t>(w.cap_keys, 1);
+    w.cap_exit = exit_capacity(N);
+    w.cap_keys = std::max<int64_t>(cap_pairs + cap_sad + cap_max, 1);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t at = off;
@@ -81,6 +91,8 @@ Work carve(void* base, int64_t cap_max, int64_t cap_sad, int64_t cap_pairs)
     size_t o_ka = take(sizeof(uint64_t) * (size_t)w.cap_keys);
     size_t o_kb = take(sizeof(uint64_t) * (size_t)w.cap_keys);
     size_t o_h = take(sizeof(uint32_t) * (256 * kSortBlocks + 2 * kSortBlocks + 64));
+    size_t o_ex = take(sizeof(uint32_t) * (size_t)std::max<int64_t>(w.cap_exit, 1));
+    size_t o_er = take(sizeof(int32_t) * (size_t)std::max<int64_t>(w.cap_exit, 1));
     w.bytes = off;
     if (base) {
         char* p = (char*)base;
@@ -90,6 +102,8 @@ Work carve(void* base, int64_t cap_max, int64_t cap_sad, int64_t cap_pairs)
         w.keysA = (uint64_t*)(p + o_ka);
         w.keysB = (uint64_t*)(p + o_kb);
         w.hist = (uint32_t*)(p + o_h);
+        w.exits = (uint32_t*)(p + o_ex);
+        w.exres = (int32_t*)(p + o_er);
     }
     return w;
 }

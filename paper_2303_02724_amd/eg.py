@@ -74,6 +74,14 @@ def lib():
         fn = getattr(L, name)
         fn.argtypes = [vp, ctypes.c_int, i64p, vp, ctypes.POINTER(eg_out)]
         fn.restype = ctypes.c_int
+    L.eg_batch_plan_bytes.argtypes = [ctypes.c_int]
+    L.eg_batch_plan_bytes.restype = ctypes.c_size_t
+    L.eg_batch_workspace_bytes.argtypes = [ctypes.c_int, vp, vp, vp]
+    L.eg_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.eg_batch_plan.argtypes = [ctypes.c_int, vp, vp, vp, vp, vp, ctypes.c_size_t, vp, ctypes.c_size_t]
+    L.eg_batch_plan.restype = ctypes.c_int
+    L.eg_build_batched.argtypes = [vp, vp]
+    L.eg_build_batched.restype = ctypes.c_int
     L.eg_status_string.argtypes = [ctypes.c_int]
     L.eg_status_string.restype = ctypes.c_char_p
     L.eg_link_table.argtypes = [ctypes.c_int, vp, vp]
@@ -257,6 +265,126 @@ class Builder:
                 continue
             return self.finish()
         raise EGError(EG_ERR_CAPACITY, "capacity retries exhausted")
+
+
+class BatchBuilder:
+    """Extremum graphs of many 2D/3D fields with one batched launch sequence.
+
+    ``builders`` are per-field ``Builder`` objects (they own each field's
+    output buffers and workspace); ``plan(fields)`` validates the batch,
+    writes the plan on the host and copies it into the batch workspace on the
+    current stream; ``launch()`` queues ``eg_build_batched``; ``finish()``
+    synchronises and returns one ``EGResult`` per field.  A plan stays valid
+    while the same field tensors and buffers are used, so repeated launches
+    (benchmarks, HIP graph replays) need no new plan.
+    """
+
+    def __init__(self, shapes, minima=False, device=None, caps=None):
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        caps = caps or [None] * len(shapes)
+        mins = minima if isinstance(minima, (list, tuple)) else [minima] * len(shapes)
+        self.builders = [Builder(sh, minima=mn, device=self.device, **(c or {}))
+                         for sh, mn, c in zip(shapes, mins, caps)]
+        self._plan_host = None
+        self._fields = None
+        self._ws = None
+
+    @classmethod
+    def from_builders(cls, builders, device=None, reuse=None):
+        """A batch over existing per-field builders; ``reuse`` lends its batch
+        workspace and pinned plan buffer (it must not be in flight)."""
+        bb = cls.__new__(cls)
+        bb.device = torch.device(device) if device is not None else builders[0].device
+        bb.builders = list(builders)
+        bb._plan_host = None
+        bb._fields = None
+        bb._ws = reuse._ws if reuse is not None else None
+        bb._pinned = getattr(reuse, "_pinned", None) if reuse is not None else None
+        return bb
+
+    @property
+    def count(self):
+        return len(self.builders)
+
+    def _arrays(self):
+        n = self.count
+        ndims = (ctypes.c_int * n)(*[len(b.shape) for b in self.builders])
+        dims = (ctypes.c_int64 * (n * EG_MAX_NDIM))()
+        for i, b in enumerate(self.builders):
+            for j, d in enumerate(b.shape):
+                dims[i * EG_MAX_NDIM + j] = d
+        outs = (eg_out * n)(*[b.out for b in self.builders])
+        return ndims, dims, outs
+
+    def plan(self, fields, stream=None):
+        if len(fields) != self.count:
+            raise EGError(EG_ERR_ARG, "one field per builder")
+        for f, b in zip(fields, self.builders):
+            if f.dtype != torch.float32 or not f.is_cuda or not f.is_contiguous() or f.numel() != b.n:
+                raise EGError(EG_ERR_ARG, "fields must be contiguous float32 device tensors of the builders' shapes")
+        L = lib()
+        ndims, dims, outs = self._arrays()
+        wsb = int(L.eg_batch_workspace_bytes(self.count, ndims, dims, outs))
+        if wsb == 0:
+            raise EGError(EG_ERR_ARG, "batch workspace query failed")
+        if self._ws is None or self._ws.numel() < wsb + 256:
+            self._ws = torch.empty(wsb + 256, dtype=torch.uint8, device=self.device)
+        base = (self._ws.data_ptr() + 255) & ~255
+        pb = int(L.eg_batch_plan_bytes(self.count))
+        pinned = getattr(self, "_pinned", None)
+        if pinned is None or pinned.numel() < pb:
+            pinned = torch.empty(max(pb, 1 << 16), dtype=torch.uint8).pin_memory()
+            self._pinned = pinned
+        host = pinned[:pb]
+        fptrs = (ctypes.c_void_p * self.count)(*[f.data_ptr() for f in fields])
+        st = L.eg_batch_plan(self.count, fptrs, ndims, dims, outs, ctypes.c_void_p(base), wsb,
+                             ctypes.c_void_p(host.data_ptr()), pb)
+        if st != EG_OK:
+            raise EGError(st, "eg_batch_plan")
+        off = base - self._ws.data_ptr()
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with torch.cuda.stream(s):
+            self._ws[off:off + pb].copy_(host, non_blocking=True)
+        self._plan_host = host
+        self._fields = list(fields)
+        self._stream = s
+        return self
+
+    def launch(self, stream=None):
+        if self._plan_host is None:
+            raise EGError(EG_ERR_ARG, "plan() first")
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        st = lib().eg_build_batched(ctypes.c_void_p(self._plan_host.data_ptr()), ctypes.c_void_p(s.cuda_stream))
+        if st != EG_OK:
+            raise EGError(st, "eg_build_batched")
+        self._stream = s
+        for b in self.builders:
+            b._stream = s
+
+    def finish(self, check: bool = True):
+        self._stream.synchronize()
+        return [b.finish(check=check) for b in self.builders]
+
+    def run(self, fields, max_retries: int = 4):
+        """plan + launch + finish, growing per-field buffers on capacity errors."""
+        for _ in range(max_retries + 1):
+            self.plan(fields)
+            self.launch()
+            self._stream.synchronize()
+            heads = [b.header_values() for b in self.builders]
+            short = [i for i, h in enumerate(heads) if h[H_STATUS] == EG_ERR_CAPACITY]
+            if short:
+                for i in short:
+                    self.builders[i].grow(heads[i])
+                continue
+            return self.finish()
+        raise EGError(EG_ERR_CAPACITY, "capacity retries exhausted")
+
+
+def build_batched(fields, minima=False, **kw):
+    """Extremum graphs of a list of 2D/3D float32 device tensors in one batch."""
+    bb = BatchBuilder([f.shape for f in fields], minima=minima, device=fields[0].device, **kw)
+    return bb.run([f.contiguous() for f in fields])
 
 
 def build(field: torch.Tensor, minima: bool = False, want_ptr: bool = False, **caps) -> EGResult:

@@ -120,3 +120,68 @@ def test_repeat_runs_are_identical():
     for _ in range(3):
         b = gpu_graph(f)
         assert_same(b, a, KEYS + ["ptr"], "repeat")
+
+
+def _result_np(r):
+    return {"labels": r.labels.reshape(-1).cpu().numpy(), "maxima": r.maxima.cpu().numpy(),
+            "saddles": r.saddles.cpu().numpy(), "saddle_beta": r.saddle_beta.cpu().numpy(),
+            "arc_offsets": r.arc_offsets.cpu().numpy(), "arc_maxima": r.arc_maxima.cpu().numpy()}
+
+
+def test_batched_equals_oracle_mixed_shapes_and_modes():
+    import torch
+    from paper_2303_02724_amd import eg
+    shapes = [(64, 64), (1, 1), (5, 70), (33, 129, 17), (40, 30, 20), (130, 70), (3, 2, 1), (70, 9, 65)]
+    fields = [W.gaussian_mixture(sh, 300 + i, n_gauss=4, noise=1e-3) if len(sh) == 2 else
+              W.random_field(sh, 300 + i, "ties" if i % 2 else "uniform") for i, sh in enumerate(shapes)]
+    mins = [i % 3 == 1 for i in range(len(shapes))]
+    ts = [torch.from_numpy(f).cuda() for f in fields]
+    bb = eg.BatchBuilder([f.shape for f in fields], minima=mins)
+    res = bb.run(ts)
+    for f, m, r in zip(fields, mins, res):
+        assert_same(_result_np(r), O.extremum_graph(f, m), KEYS, f"batched {f.shape} minima={m}")
+
+
+def test_batched_replay_and_capacity_retry():
+    import torch
+    from paper_2303_02724_amd import eg
+    specs = W.batched_specs(count=12, side2=(40, 300), side3=(16, 48))
+    fields = [W.batched_field(sp) for sp in specs]
+    ts = [torch.from_numpy(f).cuda() for f in fields]
+    # tiny capacities force a capacity report and a retry with grown buffers
+    caps = [{"cap_max": 1, "cap_sad": 1, "cap_pairs": 1, "cap_arc": 1} for _ in fields]
+    bb = eg.BatchBuilder([f.shape for f in fields], caps=caps)
+    res = bb.run(ts)
+    want = [O.extremum_graph(f) for f in fields]
+    for f, r, o in zip(fields, res, want):
+        assert_same(_result_np(r), o, KEYS, f"batched retry {f.shape}")
+    # replay the same plan twice more: identical results
+    for _ in range(2):
+        bb.launch()
+        again = bb.finish()
+        for f, r, o in zip(fields, again, want):
+            assert_same(_result_np(r), o, KEYS, f"batched replay {f.shape}")
+
+
+def test_serving_mix_equals_alone():
+    """Continuous batching: every request's result in the mix equals the same
+    field built alone (exact), and admission never exceeds the budget."""
+    import torch
+    from paper_2303_02724_amd import eg, serving
+    specs = W.batched_specs(count=6, side2=(40, 400), side3=(16, 64), meta_seed=11)
+    fields = [torch.from_numpy(W.batched_field(sp)).cuda() for sp in specs]
+    alone = [_result_np(eg.build(t)) for t in fields]
+    rng = np.random.default_rng(1)
+    t, reqs = 0.0, []
+    for _ in range(60):
+        t += rng.exponential(1 / 2000.0)
+        reqs.append((t, int(rng.integers(0, len(fields)))))
+    got = {}
+    budget = 3 * max(serving.footprint(eg.Builder(tuple(f.shape))) for f in fields)
+    srv = serving.Server(hbm_budget=budget, max_slots=8, max_batch=4, lanes=2)
+    st = srv.run(reqs, fields, on_done=lambda ri, b: got.__setitem__(ri, _result_np(b.finish())))
+    assert len(got) == len(reqs)
+    assert st.peak_bytes <= budget
+    assert st.batches < len(reqs)  # requests were batched
+    for ri, (_, fi) in enumerate(reqs):
+        assert_same(got[ri], alone[fi], KEYS, f"request {ri} field {fi}")
