@@ -108,7 +108,20 @@ typedef struct eg_out {
     void* workspace;
     size_t ws_bytes;
     int32_t* header;
+    uint32_t tuning; /* launch configuration (EG_TUNE_*), 0 = defaults; never changes results */
 } eg_out;
+
+/*
+ * eg_out.tuning: launch choices an autotuner may vary.  Every choice gives
+ * bit-identical results.
+ *   EG_TUNE_TILE3(v)  3D tile: 0 = 64x8x8, 1 = 64x4x16, 2 = 64x8x4
+ *   EG_TUNE_TILE2(v)  2D tile: 0 = 64x32, 1 = 64x16
+ *   EG_TUNE_HOPS(h)   links followed per label pass: 0 = 64; 16, 32, 64 or 128
+ * Other values are EG_ERR_ARG.  A batch uses outs[0].tuning for every field.
+ */
+#define EG_TUNE_TILE3(v) ((uint32_t)(v) & 0xFu)
+#define EG_TUNE_TILE2(v) (((uint32_t)(v) & 0xFu) << 4)
+#define EG_TUNE_HOPS(h) (((uint32_t)(h) & 0xFFu) << 8)
 
 /*
  * Workspace bytes that eg_build needs for a field of the given shape and the

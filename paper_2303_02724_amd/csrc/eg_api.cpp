@@ -1,6 +1,7 @@
 // eg_api.cpp -- the C ABI: argument checks, workspace carving and the kernel
 // sequence on the caller's stream.  Nothing here allocates or synchronises.
 #include <cstring>
+#include <vector>
 
 #include "eg_internal.h"
 
@@ -45,10 +46,12 @@ eg_status too_large_or_arg(int ndim, const int64_t* dims)
     return N > (long double)kMaxIndex ? EG_ERR_TOO_LARGE : EG_ERR_ARG;
 }
 
-// Validate one field's arguments; fill g and t.
+// Validate one field's arguments; fill g and w.
 eg_status check_one(const float* field, int ndim, const int64_t* dims, const eg_out* o, Grid* g, Work* w)
 {
     if (!o || !field) return EG_ERR_ARG;
+    Tuning tu;
+    if (!decode_tuning(o->tuning, &tu)) return EG_ERR_ARG;
     if (!grid_from(ndim, dims, g)) return too_large_or_arg(ndim, dims);
     if (o->flags & ~uint32_t(EG_MINIMA)) return EG_ERR_ARG;
     if (!caps_ok(o->cap_max, o->cap_sad, o->cap_pairs, o->cap_arc)) return EG_ERR_TOO_LARGE;
@@ -65,18 +68,18 @@ eg_status check_one(const float* field, int ndim, const int64_t* dims, const eg_
 
 // Stage (a) + (c): pointers, maxima and saddle candidates (resets counters).
 hipError_t stage_classify(const float* field, const Grid& g, const LinkTable& t, const eg_out& o, const Work& w,
-                          hipStream_t s)
+                          const Tuning& tu, hipStream_t s)
 {
     const bool minima = (o.flags & EG_MINIMA) != 0;
     hipError_t e = launch_init(w.ctr, o.header, s);
     if (e != hipSuccess) return e;
-    return launch_classify(field, g, t, minima, o.labels, o.ptr, w, o.cap_max, o.cap_sad, s);
+    return launch_classify(field, g, t, minima, o.labels, o.ptr, w, o.cap_max, o.cap_sad, tu, s);
 }
 
 // Stage (b): labels by pointer jumping, in place.
-hipError_t stage_label(const Grid& g, const eg_out& o, const Work& w, hipStream_t s)
+hipError_t stage_label(const Grid& g, const eg_out& o, const Work& w, const Tuning& tu, hipStream_t s)
 {
-    return launch_labels(o.labels, g.N, w, s);
+    return launch_labels(g, o.labels, w, tu, s);
 }
 
 // Stage (d) and the canonical outputs: maxima and (saddle, maximum) keys
@@ -109,10 +112,12 @@ eg_status run_stages(int stages, const float* field, int ndim, const int64_t* di
     if (st != EG_OK) return st;
     LinkTable t;
     make_table(g, &t);
+    Tuning tu;
+    decode_tuning(out->tuning, &tu);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipSuccess;
-    if (stages & S_CLASSIFY) e = stage_classify(field, g, t, *out, w, s);
-    if (e == hipSuccess && (stages & S_LABEL)) e = stage_label(g, *out, w, s);
+    if (stages & S_CLASSIFY) e = stage_classify(field, g, t, *out, w, tu, s);
+    if (e == hipSuccess && (stages & S_LABEL)) e = stage_label(g, *out, w, tu, s);
     if (e == hipSuccess && (stages & S_ARCS)) e = stage_arcs(field, g, t, *out, w, s);
     return e == hipSuccess ? EG_OK : EG_ERR_HIP;
 }
@@ -206,6 +211,7 @@ eg_status eg_batch_plan(int count, const float* const* fields, const int* ndims,
     BatchPlan* P = (BatchPlan*)host_plan;
     BatchField* F = (BatchField*)((char*)host_plan + L.o_fields);
     P->count = count;
+    if (!decode_tuning(outs[0].tuning, &P->tuning)) return EG_ERR_ARG;
     P->bits = b;
     P->fbits = id_bits(count);
     P->cap_keys = L.cap_keys;
@@ -217,39 +223,63 @@ eg_status eg_batch_plan(int count, const float* const* fields, const int* ndims,
     P->fields = (BatchField*)(dbase + L.o_fields);
     P->dev = (const BatchPlan*)(dbase + L.o_plan);
     P->plan_bytes = (int64_t)L.plan_bytes;
+    // plan order: by class (2D max, 2D min, 3D max, 3D min), stable
+    std::vector<int> order;
+    order.reserve(count);
+    for (int c = 0; c < 4; ++c) {
+        P->class_field[c] = (int32_t)order.size();
+        for (int i = 0; i < count; ++i) {
+            const int ci = (ndims[i] == 3 ? 2 : 0) + ((outs[i].flags & EG_MINIMA) ? 1 : 0);
+            if (ci == c) order.push_back(i);
+        }
+    }
+    P->class_field[4] = count;
     int64_t tiles = 0, quads = 0, sad = 0, exits = 0, maxs = 0;
-    for (int i = 0; i < count; ++i) {
+    int cls = 0;
+    for (int k = 0; k < count; ++k) {
+        while (cls < 4 && P->class_field[cls + 1] <= k) {
+            P->class_tile[cls + 1] = tiles;
+            ++cls;
+        }
+        const int i = order[k];
         Grid g;
         Work w;
         const eg_out& o = outs[i];
         st = check_one(fields[i], ndims[i], dims + (size_t)i * EG_MAX_NDIM, &o, &g, &w);
         if (st != EG_OK) return st;
         if (o.cap_max < 1) return EG_ERR_ARG;
-        const int ty = g.ndim == 3 ? kTile3Y : kTile2Y, tz = g.ndim == 3 ? kTile3Z : 1;
-        F[i].ta = tile_args(fields[i], g, o.labels, o.ptr, w, o.cap_max, o.cap_sad, ty, tz);
-        F[i].ndim = g.ndim;
-        F[i].minima = (o.flags & EG_MINIMA) ? 1 : 0;
-        F[i].N = g.N;
-        F[i].tile_base = tiles;
-        F[i].quad_base = quads;
-        F[i].sad_base = sad;
-        F[i].exit_base = exits;
-        F[i].max_base = maxs;
-        F[i].exres = w.exres;
-        F[i].header = o.header;
-        F[i].maxima = o.maxima;
-        F[i].saddles = o.saddles;
-        F[i].beta = o.saddle_beta;
-        F[i].offsets = o.arc_offsets;
-        F[i].arcs = o.arc_maxima;
-        F[i].cap_arc = (uint32_t)o.cap_arc;
-        F[i].cap_keys = (uint32_t)(o.cap_max + o.cap_sad + o.cap_pairs);
-        tiles += F[i].ta.ntiles;
+        int ty, tz;
+        tile_shape(P->tuning, g.ndim, &ty, &tz);
+        BatchField& B = F[k];
+        B.ta = tile_args(fields[i], g, o.labels, o.ptr, w, o.cap_max, o.cap_sad, ty, tz);
+        B.ndim = g.ndim;
+        B.minima = (o.flags & EG_MINIMA) ? 1 : 0;
+        B.N = g.N;
+        B.tile_base = tiles;
+        B.quad_base = quads;
+        B.sad_base = sad;
+        B.exit_base = exits;
+        B.max_base = maxs;
+        B.exres = w.exres;
+        B.header = o.header;
+        B.maxima = o.maxima;
+        B.saddles = o.saddles;
+        B.beta = o.saddle_beta;
+        B.offsets = o.arc_offsets;
+        B.arcs = o.arc_maxima;
+        B.cap_arc = (uint32_t)o.cap_arc;
+        B.cap_keys = (uint32_t)(o.cap_max + o.cap_sad + o.cap_pairs);
+        tiles += B.ta.ntiles;
         quads += (g.N + 3) / 4;
         sad += o.cap_sad;
         exits += w.cap_exit;
         maxs += o.cap_max;
     }
+    while (cls < 4) {
+        P->class_tile[cls + 1] = tiles;
+        ++cls;
+    }
+    P->class_tile[0] = 0;
     P->total_tiles = tiles;
     P->total_quads = quads;
     P->total_sad = sad;

@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_bexit_jump(const BatchPlan* __restrict_
         do {
             x = next_link_b(lab, res, N, x);
             ++h;
-        } while (x < 0 && h < kJumpHops);
+        } while (x < 0 && h < plan->tuning.hops);
         res[i] = x;
         notdone |= x < 0;
     }
@@ -109,7 +109,8 @@ __global__ __launch_bounds__(256) void k_bfinal(const BatchPlan* __restrict__ pl
         int y2 = x.z < 0 ? next_link_b(lab, res, N, x.z) : x.z;
         int y3 = x.w < 0 ? next_link_b(lab, res, N, x.w) : x.w;
         int h = 1;
-        while ((y0 < 0 || y1 < 0 || y2 < 0 || y3 < 0) && h < kJumpHops) {
+        const int hops = plan->tuning.hops;
+        while ((y0 < 0 || y1 < 0 || y2 < 0 || y3 < 0) && h < hops) {
             if (y0 < 0) y0 = next_link_b(lab, res, N, y0);
             if (y1 < 0) y1 = next_link_b(lab, res, N, y1);
             if (y2 < 0) y2 = next_link_b(lab, res, N, y2);
@@ -123,7 +124,7 @@ __global__ __launch_bounds__(256) void k_bfinal(const BatchPlan* __restrict__ pl
     if (t < (N & 3)) {
         const int v = (nq << 2) + t;
         int y = lab[v];
-        for (int h = 0; y < 0 && h < kJumpHops; ++h) y = next_link_b(lab, res, N, y);
+        for (int h = 0; y < 0 && h < plan->tuning.hops; ++h) y = next_link_b(lab, res, N, y);
         lab[v] = y;
         notdone |= y < 0;
     }
@@ -237,7 +238,10 @@ __global__ __launch_bounds__(256) void k_breps(const BatchPlan* __restrict__ pla
 __device__ __forceinline__ uint32_t bchunk(uint32_t n, uint32_t nblocks, uint32_t blk, uint32_t& lo, uint32_t& hi)
 {
     const uint32_t tiles = (n + 255u) / 256u;
-    const uint32_t per = tiles == 0 ? 1u : (tiles + nblocks - 1u) / nblocks;
+    // at least kMinTilesPerBlock tiles per block: small inputs use few blocks
+    // and a short histogram
+    uint32_t per = tiles == 0 ? 1u : (tiles + nblocks - 1u) / nblocks;
+    per = per < kMinTilesPerBlock ? kMinTilesPerBlock : per;
     const uint32_t active = (tiles + per - 1u) / per;
     const uint64_t l = uint64_t(blk) * per * 256u;
     lo = (uint32_t)(l < n ? l : n);
@@ -373,8 +377,8 @@ hipError_t launch_batched_rest(const BatchPlan* dplan, const BatchPlan& hplan, h
 {
     const dim3 grid(kBatchBlocksPerField, hplan.count);
     hipLaunchKernelGGL(k_bexit_init, grid, dim3(256), 0, s, dplan);
-    for (int p = 0; p < kJumpPasses; ++p) hipLaunchKernelGGL(k_bexit_jump, grid, dim3(256), 0, s, dplan, p);
-    for (int p = 0; p < kJumpPasses; ++p) hipLaunchKernelGGL(k_bfinal, grid, dim3(256), 0, s, dplan, p);
+    for (int p = 0; p < hplan.tuning.passes; ++p) hipLaunchKernelGGL(k_bexit_jump, grid, dim3(256), 0, s, dplan, p);
+    for (int p = 0; p < hplan.tuning.passes; ++p) hipLaunchKernelGGL(k_bfinal, grid, dim3(256), 0, s, dplan, p);
     hipLaunchKernelGGL(k_bload_maxima, grid, dim3(256), 0, s, dplan);
     hipLaunchKernelGGL(k_breps, grid, dim3(256), 0, s, dplan);
     uint64_t* sorted = nullptr;

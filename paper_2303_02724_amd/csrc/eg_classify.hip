@@ -127,9 +127,11 @@ static void launch_classify_t(const float* f, const Grid& g, const LinkTable& t,
 }
 
 hipError_t launch_classify(const float* f, const Grid& g, const LinkTable& t, bool minima, int32_t* lab,
-                           int32_t* ptr, const Work& w, int64_t cap_max, int64_t cap_sad, hipStream_t s)
+                           int32_t* ptr, const Work& w, int64_t cap_max, int64_t cap_sad, const Tuning& tu,
+                           hipStream_t s)
 {
-    if (g.ndim == 2 || g.ndim == 3) return launch_classify_tiled(f, g, minima, lab, ptr, w, cap_max, cap_sad, s);
+    if (g.ndim == 2 || g.ndim == 3)
+        return launch_classify_tiled(f, g, minima, lab, ptr, w, cap_max, cap_sad, tu, s);
 #define EG_CASE(N)                                                                  \
     case N:                                                                         \
         if (minima)                                                                 \
@@ -162,10 +164,10 @@ hipError_t launch_classify(const float* f, const Grid& g, const LinkTable& t, bo
 //
 // Entries are updated in place while other threads read them.  Every value
 // ever stored says something true about the same path, so any value read is
-// usable.  A pass follows at most kJumpHops links per entry; a pass that stops
+// usable.  A pass follows at most `hops` links per entry; a pass that stops
 // short raises its flag and the next pass runs.  After pass p every entry has
-// advanced kJumpHops^p links or become final, so kJumpPasses passes cover any
-// path in a grid of fewer than 2^31 vertices.
+// advanced hops^p links or become final, so the launcher's pass count
+// (hops^passes >= 2^31) covers any path in a grid of fewer than 2^31 vertices.
 
 __device__ __forceinline__ int next_link(const int32_t* lab, const int32_t* res, int N, int x)
 {
@@ -189,7 +191,7 @@ __global__ __launch_bounds__(256) void k_exit_init(const uint32_t* __restrict__ 
 }
 
 __global__ __launch_bounds__(256) void k_exit_jump(int32_t* res, const int32_t* __restrict__ lab, int N,
-                                                   uint32_t* __restrict__ ctr, uint32_t cap, int pass)
+                                                   uint32_t* __restrict__ ctr, uint32_t cap, int pass, int hops)
 {
     if (!gate(ctr, C_JUMP, pass)) return;
     const uint32_t req = __hip_atomic_load(&ctr[C_NEXIT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -202,7 +204,7 @@ __global__ __launch_bounds__(256) void k_exit_jump(int32_t* res, const int32_t* 
         do {
             x = next_link(lab, res, N, x);
             ++h;
-        } while (x < 0 && h < kJumpHops);
+        } while (x < 0 && h < hops);
         res[i] = x;
         notdone |= x < 0;
     }
@@ -212,7 +214,7 @@ __global__ __launch_bounds__(256) void k_exit_jump(int32_t* res, const int32_t* 
 // Per-vertex pass: four consecutive vertices per thread (one 16-byte load,
 // four independent chains).
 __global__ __launch_bounds__(256) void k_final(int32_t* lab, const int32_t* __restrict__ res, int32_t N,
-                                               uint32_t* __restrict__ ctr, int pass)
+                                               uint32_t* __restrict__ ctr, int pass, int hops)
 {
     if (!gate(ctr, C_FINAL, pass)) return;
     bool notdone = false;
@@ -227,7 +229,7 @@ __global__ __launch_bounds__(256) void k_final(int32_t* lab, const int32_t* __re
         int y2 = x.z < 0 ? next_link(lab, res, N, x.z) : x.z;
         int y3 = x.w < 0 ? next_link(lab, res, N, x.w) : x.w;
         int h = 1;
-        while ((y0 < 0 || y1 < 0 || y2 < 0 || y3 < 0) && h < kJumpHops) {
+        while ((y0 < 0 || y1 < 0 || y2 < 0 || y3 < 0) && h < hops) {
             if (y0 < 0) y0 = next_link(lab, res, N, y0);
             if (y1 < 0) y1 = next_link(lab, res, N, y1);
             if (y2 < 0) y2 = next_link(lab, res, N, y2);
@@ -242,7 +244,7 @@ __global__ __launch_bounds__(256) void k_final(int32_t* lab, const int32_t* __re
     if (t < (N & 3)) {
         const int v = (nq << 2) + t;
         int y = lab[v];
-        for (int h = 0; y < 0 && h < kJumpHops; ++h) y = next_link(lab, res, N, y);
+        for (int h = 0; y < 0 && h < hops; ++h) y = next_link(lab, res, N, y);
         lab[v] = y;
         notdone |= y < 0;
     }
@@ -250,19 +252,27 @@ __global__ __launch_bounds__(256) void k_final(int32_t* lab, const int32_t* __re
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctr[C_PASSES], 1u);
 }
 
-hipError_t launch_labels(int32_t* lab, int32_t N, const Work& w, hipStream_t s)
+hipError_t launch_labels(const Grid& g, int32_t* lab, const Work& w, const Tuning& tu, hipStream_t s)
 {
+    const int32_t N = g.N;
     if (reinterpret_cast<uintptr_t>(lab) & 15u) return hipErrorInvalidValue;
     const uint32_t cap = (uint32_t)w.cap_exit;
     const int64_t ewant = (w.cap_exit + 255) / 256;
     const int eblocks = (int)(ewant < 2048 ? (ewant > 0 ? ewant : 1) : 2048);
     hipLaunchKernelGGL(k_exit_init, dim3(eblocks), dim3(256), 0, s, w.exits, w.exres, lab, w.ctr, cap);
-    for (int p = 0; p < kJumpPasses; ++p)
-        hipLaunchKernelGGL(k_exit_jump, dim3(eblocks), dim3(256), 0, s, w.exres, lab, N, w.ctr, cap, p);
+    for (int p = 0; p < tu.passes; ++p)
+        hipLaunchKernelGGL(k_exit_jump, dim3(eblocks), dim3(256), 0, s, w.exres, lab, N, w.ctr, cap, p, tu.hops);
     const int64_t want = ((int64_t)N / 4 + 255) / 256;
     const int blocks = (int)(want < 8192 ? (want > 0 ? want : 1) : 8192);
-    for (int p = 0; p < kJumpPasses; ++p)
-        hipLaunchKernelGGL(k_final, dim3(blocks), dim3(256), 0, s, lab, w.exres, N, w.ctr, p);
+    int p = 0;
+    if (g.ndim == 2 || g.ndim == 3) {
+        // pass 0 in tile order (the classification wrote exit-list codes)
+        const hipError_t e = launch_final_tiled(g, lab, w, tu, C_FINAL, s);
+        if (e != hipSuccess) return e;
+        p = 1;
+    }
+    for (; p < tu.passes; ++p)
+        hipLaunchKernelGGL(k_final, dim3(blocks), dim3(256), 0, s, lab, w.exres, N, w.ctr, p, tu.hops);
     return hipGetLastError();
 }
 

@@ -104,34 +104,22 @@ __device__ __forceinline__ void double_tile_chains(int (&cur)[VPT], int32_t* s_n
     }
 }
 
-// After the tile's chains are resolved, cur[k] is a tile-local maximum (>= 0)
-// or -(h + 1) for the exit at halo position h.  The tile flags the halo
-// positions used as exits, numbers them with a block scan, appends their
-// vertex ids to the exit list (one atomic per tile) and turns every exit into
-// an exit-list code, so the label pass resolves each exit once.  A tile that
-// does not fit in the list keeps vertex-id codes.  s_words must hold
-// (HALO + 1) / 2 words of LDS that nobody else uses any more.
-template <int VPT, int HALO, class H2G>
-__device__ __forceinline__ void publish_exits(int (&cur)[VPT], uint32_t* s_words, uint32_t* s_tmp,
-                                              uint32_t* __restrict__ ctr, uint32_t* __restrict__ exits,
-                                              uint32_t cap_exit, int N, H2G h2g)
+// Every vertex whose steepest step leaves the tile gets its own entry of the
+// exit list, which records the step's target; before the tile's chains are
+// resolved, cur[k] < 0 holds -(target + 1) for such a vertex.  One block scan
+// and one atomic per tile place the entries; cur[k] becomes the entry's code,
+// so the pointer doubling hands that code to every vertex whose path leaves
+// the tile there, and the label pass resolves each entry once.  A tile that
+// does not fit in the list keeps the vertex codes.
+template <int VPT>
+__device__ __forceinline__ void alloc_exits(int (&cur)[VPT], uint32_t* s_tmp, uint32_t* __restrict__ ctr,
+                                            uint32_t* __restrict__ exits, uint32_t cap_exit, int N)
 {
-    constexpr int WORDS = (HALO + 1) / 2;
-    constexpr int SEG = (HALO + 255) / 256;
-    uint16_t* s_map = reinterpret_cast<uint16_t*>(s_words);
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    for (int i = tid; i < WORDS; i += 256) s_words[i] = 0;
-    __syncthreads();
+    uint32_t mask = 0;
 #pragma unroll
-    for (int k = 0; k < VPT; ++k)
-        if (cur[k] < 0) s_map[-cur[k] - 1] = 1;
-    __syncthreads();
-    const int lo = tid * SEG;
-    uint32_t cnt = 0;
-#pragma unroll
-    for (int i = 0; i < SEG; ++i)
-        if (lo + i < HALO) cnt += s_map[lo + i];
-    // block-wide exclusive scan of the counts
+    for (int k = 0; k < VPT; ++k) mask |= (cur[k] < 0 ? 1u : 0u) << k;
+    const uint32_t cnt = (uint32_t)__popc(mask);
     uint32_t inc = cnt;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -143,28 +131,21 @@ __device__ __forceinline__ void publish_exits(int (&cur)[VPT], uint32_t* s_words
     uint32_t pre = 0;
     for (int k = 0; k < w; ++k) pre += s_tmp[k];
     const uint32_t total = s_tmp[0] + s_tmp[1] + s_tmp[2] + s_tmp[3];
+    __syncthreads();
     if (tid == 0) s_tmp[4] = total ? atomicAdd(&ctr[C_NEXIT], total) : 0u;
     __syncthreads();
     const uint32_t base = s_tmp[4];
     const bool ok = (uint64_t)base + total <= cap_exit;
-    uint32_t r = pre + inc - cnt;
-#pragma unroll
-    for (int i = 0; i < SEG; ++i) {
-        const int h = lo + i;
-        if (h < HALO && s_map[h]) {
-            // entries below the capacity are always written, so the list
-            // never holds garbage even when this tile does not use it
-            if (base + r < cap_exit) exits[base + r] = (uint32_t)h2g(h);
-            s_map[h] = (uint16_t)r;
-            ++r;
-        }
-    }
-    __syncthreads();
+    uint32_t r = base + pre + inc - cnt;
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
-        if (cur[k] < 0) {
-            const int h = -cur[k] - 1;
-            cur[k] = ok ? exit_list_code(N, base + s_map[h]) : -(h2g(h) + 1);
+        if ((mask >> k) & 1u) {
+            const int e = -cur[k] - 1;
+            // entries below the capacity are always written, so the list
+            // never holds garbage even when this tile cannot use it
+            if (r < cap_exit) exits[r] = (uint32_t)e;
+            if (ok) cur[k] = exit_list_code(N, r);
+            ++r;
         }
     }
 }
@@ -291,24 +272,22 @@ __device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u,
                 const int lz2 = lz + dz, ly2 = ly + dy, lx2 = lx + dx;
                 const bool inside = (unsigned)lz2 < (unsigned)TZ && (unsigned)ly2 < (unsigned)TY &&
                                     (unsigned)lx2 < (unsigned)TX;
-                n = inside ? (lz2 * TY + ly2) * TX + lx2 : -(c + (dz * HY + dy) * HX + dx + 1);
+                n = inside ? (lz2 * TY + ly2) * TX + lx2 : -(pv + 1);
             }
             if (ptr) ptr[v] = pv;
         }
         nxt[k] = n;
-        s_nxt[li] = n;
         wave_append(is_max, (uint32_t)v, &ctr[C_NMAX], a.umax, a.cap_max);
         wave_append(is_sad, (uint32_t)v, &ctr[C_NSAD], a.usad, a.cap_sad);
     }
     if (__ballot(nan) != 0 && __lane_id() == 0) atomicOr(&ctr[C_NAN], 1u);
-    __syncthreads();
-
-    double_tile_chains<VPT>(nxt, s_nxt, [&](int k) { return ((k / YPT) * TY + wv + 4 * (k % YPT)) * TX + lx; });
     const int N = X * Y * Z;
-    publish_exits<VPT, HALO>(nxt, s_u, s_tmp, ctr, a.exits, a.cap_exit, N, [&](int h) {
-        const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
-        return (z0 + hz - ZH) * SZ + (y0 + hy - 1) * SY + x0 + hx - 1;
-    });
+    alloc_exits<VPT>(nxt, s_tmp, ctr, a.exits, a.cap_exit, N);
+    auto s_idx = [&](int k) { return ((k / YPT) * TY + wv + 4 * (k % YPT)) * TX + lx; };
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) s_nxt[s_idx(k)] = nxt[k];
+    __syncthreads();
+    double_tile_chains<VPT>(nxt, s_nxt, s_idx);
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
         const int ly = wv + 4 * (k % YPT);
@@ -326,6 +305,22 @@ __device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u,
 // vertex costs 7 LDS reads instead of 15; pointer targets stay in registers
 // until the halo is no longer needed, then reuse its LDS for the tile-local
 // chains, which are resolved by pointer doubling.
+// Successor of a vertex as one 32-bit literal per neighbour row, chosen with
+// the steepest candidate:
+//   bits 0..5   faces of the tile the step crosses if the vertex lies on them
+//               (x-, x+, y-, y+, z-, z+)
+//   bits 6..16  tile-local index offset (signed, 11 bits)
+//   bit 31      the vertex itself (a maximum)
+constexpr uint32_t kSelfPack = 1u << 31;
+template <int TY, int HY, int HX>
+__device__ __forceinline__ constexpr uint32_t succ_pack(int dz, int dy, int dx)
+{
+    const int loff = (dz * TY + dy) * 64 + dx;
+    const uint32_t em = (dx < 0 ? 1u : 0u) | (dx > 0 ? 2u : 0u) | (dy < 0 ? 4u : 0u) | (dy > 0 ? 8u : 0u) |
+                        (dz < 0 ? 16u : 0u) | (dz > 0 ? 32u : 0u);
+    return em | ((uint32_t(loff) & 0x7FFu) << 6);
+}
+
 template <int NDIM_, int J>
 struct Win {
     // index of row J's (dy, dx) among the seven window positions
@@ -365,29 +360,33 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
 
     bool nan = false;
     {
-        // every row load of this wave is issued before the first one is used
+        // every load of this thread is issued before the first one is used:
+        // rows of 64 aligned values (one per lane), then the two edge columns
+        // of every row (one value per thread)
         constexpr int ROWS = HY * HZ;
         constexpr int RPW = (ROWS + 3) / 4;
+        constexpr int EDGES = 2 * ROWS;
+        static_assert(EDGES <= 256, "one edge value per thread");
         const int gx = x0 + lx;
         const bool xin = gx < X;
-        // edge columns: lane 0 -> x0 - 1, lane 1 -> x0 + 64
-        const int ex = lx == 0 ? x0 - 1 : x0 + TX;
-        const bool ein = lx < 2 && (unsigned)ex < (unsigned)X;
-        const int ehx = lx == 0 ? 0 : HX - 1;
-        float vals[RPW], evals[RPW];
-        bool vin[RPW], vein[RPW];
+        float vals[RPW];
+        bool vin[RPW];
 #pragma unroll
         for (int i = 0; i < RPW; ++i) {
             const int row = wv + 4 * i;
             const int hy = row % HY, hz = row / HY;
             const int gy = y0 + hy - 1, gz = z0 + hz - 1;
-            const bool rin = row < ROWS && (unsigned)gy < (unsigned)Y && (unsigned)gz < (unsigned)Z;
-            const int rbase = gz * SZ + gy * SY;
-            vin[i] = rin && xin;
-            vein[i] = rin && ein;
-            vals[i] = vin[i] ? f[rbase + gx] : 0.0f;
-            evals[i] = vein[i] ? f[rbase + ex] : 0.0f;
+            vin[i] = row < ROWS && xin && (unsigned)gy < (unsigned)Y && (unsigned)gz < (unsigned)Z;
+            vals[i] = vin[i] ? f[gz * SZ + gy * SY + gx] : 0.0f;
         }
+        // edge value of this thread: row tid >> 1, left (x0 - 1) or right (x0 + 64)
+        const int erow = tid >> 1;
+        const int ehy = erow % HY, ehz = erow / HY;
+        const int egx = (tid & 1) ? x0 + TX : x0 - 1;
+        const int egy = y0 + ehy - 1, egz = z0 + ehz - 1;
+        const bool ein = tid < EDGES && (unsigned)egx < (unsigned)X && (unsigned)egy < (unsigned)Y &&
+                         (unsigned)egz < (unsigned)Z;
+        const float eval = ein ? f[egz * SZ + egy * SY + egx] : 0.0f;
         const uint32_t conn_a = c_conn3.w[tid], conn_b = c_conn3.w[tid + 256];
         s_conn[tid] = conn_a;
         s_conn[tid + 256] = conn_b;
@@ -399,9 +398,9 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
                 const float val = vals[i];
                 s_u[row * HX + lx + 1] = vin[i] ? mode_key<MINMODE>(val) : 0u;
                 nan |= vin[i] && (hy >= 1 && hy <= TY && hz >= 1 && hz <= TZ) && (val != val);
-                if (lx < 2) s_u[row * HX + ehx] = vein[i] ? mode_key<MINMODE>(evals[i]) : 0u;
             }
         }
+        if (tid < EDGES) s_u[erow * HX + ((tid & 1) ? HX - 1 : 0)] = ein ? mode_key<MINMODE>(eval) : 0u;
     }
     __syncthreads();
 
@@ -411,6 +410,9 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
         const int ly = wv + 4 * c;
         const int gy = y0 + ly;
         const int gx = x0 + lx;
+        // tile faces this column lies on (see succ_pack)
+        const uint32_t bb_xy = (lx == 0 ? 1u : 0u) | (lx == TX - 1 ? 2u : 0u) | (ly == 0 ? 4u : 0u) |
+                               (ly == TY - 1 ? 8u : 0u);
         // window[p][q]: plane hz = lz + p, position q
         uint32_t win[3][7];
         auto load_plane = [&](uint32_t* w, int hz) {
@@ -432,14 +434,15 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
             const bool in = gx < X && gy < Y && gz < Z;
             const uint32_t uv = win[(lz + 1) % 3][3];
             uint32_t up = 0, best_u = 0;
-            int best_j = K;
+            // the steepest candidate so far, as a packed successor literal
+            uint32_t best_p = kSelfPack;
             static_for<0, K + 1>([&](auto step) {
                 constexpr int st = decltype(step)::value;
                 constexpr int pos = MINMODE ? K - st : st;
                 if constexpr (pos == K / 2) {
                     if (uv >= best_u) {
                         best_u = uv;
-                        best_j = K;
+                        best_p = kSelfPack;
                     }
                 } else {
                     constexpr int j = pos < K / 2 ? pos : pos - 1;
@@ -450,30 +453,26 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
                     up |= uint32_t(above) << j;
                     if (u >= best_u) {
                         best_u = u;
-                        best_j = j;
+                        best_p = succ_pack<TY, HY, HX>(WJ::dz, WJ::dy, WJ::dx);
                     }
                 }
             });
             const bool is_max = in && up == 0;
             const bool is_sad = in && up != 0 && !((s_conn[up >> 5] >> (up & 31)) & 1u);
             const int v = gz * SZ + gy * SY + gx;
-            int n = (lz * TY + ly) * TX + lx;  // vertices outside the grid stay put
+            const int li = (lz * TY + ly) * TX + lx;
+            int n = li;  // a maximum, or a vertex outside the grid, stays put
             if (in) {
-                int pv = v;
-                if (best_j == K) {
-                    n = (lz * TY + ly) * TX + lx;  // a maximum points to itself
-                } else {
-                    const int dz = (int)((Pack<3>::z >> (2 * best_j)) & 3u) - 1;
-                    const int dy = (int)((Pack<3>::y >> (2 * best_j)) & 3u) - 1;
-                    const int dx = (int)((Pack<3>::x >> (2 * best_j)) & 3u) - 1;
-                    pv = v + dz * SZ + dy * SY + dx;
-                    const int lz2 = lz + dz, ly2 = ly + dy, lx2 = lx + dx;
-                    const bool inside = (unsigned)lz2 < (unsigned)TZ && (unsigned)ly2 < (unsigned)TY &&
-                                        (unsigned)lx2 < (unsigned)TX;
-                    const int hpos = ((lz + 1 + dz) * HY + ly + 1 + dy) * HX + lx + 1 + dx;
-                    n = inside ? (lz2 * TY + ly2) * TX + lx2 : -(hpos + 1);
+                const int em = (int)(best_p & 63u);
+                const int dx = ((em >> 1) & 1) - (em & 1), dy = ((em >> 3) & 1) - ((em >> 2) & 1),
+                          dz = ((em >> 5) & 1) - ((em >> 4) & 1);
+                if (!(best_p & kSelfPack)) {
+                    // leaves the tile iff it steps across a face the vertex lies on
+                    const uint32_t faces = bb_xy | (lz == 0 ? 16u : 0u) | (lz == TZ - 1 ? 32u : 0u);
+                    const int loff = (int)(best_p << 15) >> 21;
+                    n = (faces & best_p & 63u) ? -(v + dz * SZ + dy * SY + dx + 1) : li + loff;
                 }
-                if (ptr) ptr[v] = pv;
+                if (ptr) ptr[v] = (best_p & kSelfPack) ? v : v + dz * SZ + dy * SY + dx;
             }
             nxt[c * TZ + lz] = n;
             wave_append(is_max, (uint32_t)v, &ctr[C_NMAX], a.umax, a.cap_max);
@@ -481,7 +480,7 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
         }
     }
     if (__ballot(nan) != 0 && __lane_id() == 0) atomicOr(&ctr[C_NAN], 1u);
-    __syncthreads();  // halo no longer read: its LDS now holds the chains
+    alloc_exits<VPT>(nxt, s_tmp, ctr, a.exits, a.cap_exit, X * Y * Z);  // has barriers: the halo is no longer read
 #pragma unroll
     for (int c = 0; c < YPT; ++c)
 #pragma unroll
@@ -491,10 +490,6 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
     // successors (a maximum is its own successor), entries < 0 are
     // -(id + 1) of the first vertex outside the tile
     double_tile_chains<VPT>(nxt, s_nxt, [&](int k) { return ((k % TZ) * TY + wv + 4 * (k / TZ)) * TX + lx; });
-    publish_exits<VPT, HALO>(nxt, s_u, s_tmp, ctr, a.exits, a.cap_exit, X * Y * Z, [&](int h) {
-        const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
-        return (z0 + hz - 1) * SZ + (y0 + hy - 1) * SY + x0 + hx - 1;
-    });
 #pragma unroll
     for (int c = 0; c < YPT; ++c) {
         const int ly = wv + 4 * c;
@@ -513,6 +508,58 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
 __device__ __forceinline__ int xcd_tile(int b, int ntiles)
 {
     return (ntiles & 7) == 0 ? (b & 7) * (ntiles >> 3) + (b >> 3) : b;
+}
+
+// Label pass over a tiled grid, one workgroup per tile: the exit codes of a
+// tile's vertices point into that tile's own block of the exit list, which
+// stays in cache while the tile's rows stream through.  Entries with vertex
+// codes (a tile whose exits did not fit the list) follow their path for up to
+// `hops` links and raise the pass flag if they stop short; the linear passes
+// after this one finish them.
+template <int TY, int TZ>
+__global__ __launch_bounds__(256) void k_final_tiled(TileArgs a, const int32_t* __restrict__ res, int hops,
+                                                     int flag_slot)
+{
+    constexpr int YPT = TY / 4;
+    const int X = a.X, Y = a.Y, Z = a.Z;
+    const int N = X * Y * Z;
+    const int SY = X, SZ = X * Y;
+    int32_t* lab = a.lab;
+    const int tid = threadIdx.x, lx = tid & 63, wv = tid >> 6;
+    const int b = xcd_tile(blockIdx.x, a.ntiles);
+    const int tx = b % a.tiles_x;
+    const int rr = b / a.tiles_x;
+    const int ty = rr % a.tiles_y;
+    const int tz = rr / a.tiles_y;
+    const int gx = tx * 64 + lx;
+    constexpr int VPT = YPT * TZ;
+    bool notdone = false;
+    int vid[VPT], x[VPT];
+    // every load of the thread first, then the exit-list look-ups, then the
+    // stores: loads and stores of the same array would otherwise serialise
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        const int gy = ty * TY + wv + 4 * (k / TZ), gz = tz * TZ + (k % TZ);
+        const bool in = gx < X && gy < Y && gz < Z;
+        vid[k] = in ? gz * SZ + gy * SY + gx : -1;
+        x[k] = in ? lab[vid[k]] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < VPT; ++k)
+        if (x[k] < -N) x[k] = res[-x[k] - 1 - N];
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        if (x[k] < 0) {
+            int y = x[k];
+            for (int h = 0; y < 0 && h < hops; ++h) y = y >= -N ? lab[-y - 1] : res[-y - 1 - N];
+            x[k] = y;
+            notdone |= y < 0;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < VPT; ++k)
+        if (vid[k] >= 0) lab[vid[k]] = x[k];
+    if (__ballot(notdone) != 0 && __lane_id() == 0) atomicOr(&a.ctr[flag_slot], 1u);
 }
 
 template <bool MINMODE, int TY, int TZ>
@@ -558,82 +605,136 @@ TileArgs tile_args(const float* f, const Grid& g, int32_t* lab, int32_t* ptr, co
     return a;
 }
 
-// Persistent classification of a batch: a fixed grid walks the work list of
-// (field, tile) items of all fields; each item runs the 2D or 3D tile code of
-// its field.  The LDS of the largest tile type is shared by both.
-__device__ __forceinline__ int find_field(const BatchField* fs, int count, int64_t item, int64_t BatchField::*base)
+// Classification of a batch: for each class of fields (2D/3D x maximum/
+// minimum graph) one launch covers the work list of (field, tile) items of
+// that class, one workgroup per item, which runs the tile code of its field.
+template <int NDIM, bool MINMODE, int TY, int TZ>
+__global__ __launch_bounds__(256) void k_classify_batched(const BatchPlan* __restrict__ plan, int cls)
 {
-    int lo = 0, hi = count - 1;
+    constexpr int HALO3 = 66 * (TY + 2) * (TZ + 2);
+    constexpr int HALO2 = 66 * (TY + 2);
+    constexpr int WORDS = NDIM == 3 ? HALO3 : HALO2 + 64 * TY;
+    __shared__ uint32_t s_u[WORDS];
+    __shared__ uint32_t s_conn[NDIM == 3 ? 512 : 1];
+    __shared__ uint32_t s_tmp[8];
+    const BatchField* fs = plan->fields;
+    const int f0 = plan->class_field[cls], f1 = plan->class_field[cls + 1];
+    const int64_t item = plan->class_tile[cls] + blockIdx.x;
+    // the field of this item: binary search over the class's tile bases
+    int lo = f0, hi = f1 - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (fs[mid].*base <= item)
+        if (fs[mid].tile_base <= item)
             lo = mid;
         else
             hi = mid - 1;
     }
-    return lo;
+    const int f = __builtin_amdgcn_readfirstlane(lo);
+    const int tile = (int)(item - fs[f].tile_base);
+    const TileArgs a = fs[f].ta;
+    if constexpr (NDIM == 3)
+        tile3d<MINMODE, TY, TZ>(a, tile, s_u, s_conn, s_tmp);
+    else
+        tile_nd<2, MINMODE, TY, 1>(a, tile, s_u, reinterpret_cast<int32_t*>(s_u + HALO2), nullptr, s_tmp);
 }
 
-__global__ __launch_bounds__(256) void k_classify_batched(const BatchPlan* __restrict__ plan)
+template <int NDIM, int TY, int TZ>
+static void launch_class(int c, unsigned grid, const BatchPlan* dplan, hipStream_t s)
 {
-    constexpr int HALO3 = 66 * (kTile3Y + 2) * (kTile3Z + 2);
-    constexpr int HALO2 = 66 * (kTile2Y + 2);
-    static_assert(HALO2 + 64 * kTile2Y <= HALO3, "2D tile fits in the 3D tile's LDS");
-    __shared__ uint32_t s_u[HALO3];
-    __shared__ uint32_t s_conn[512];
-    __shared__ uint32_t s_tmp[8];
-    const int count = plan->count;
-    const int64_t total = plan->total_tiles;
-    const BatchField* fs = plan->fields;
-    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-        const int f = __builtin_amdgcn_readfirstlane(find_field(fs, count, item, &BatchField::tile_base));
-        const int tile = (int)(item - fs[f].tile_base);
-        const TileArgs a = fs[f].ta;
-        const int ndim = fs[f].ndim, minima = fs[f].minima;
-        __syncthreads();  // the previous item's LDS reads are done
-        if (ndim == 3) {
-            if (minima)
-                tile3d<true, kTile3Y, kTile3Z>(a, tile, s_u, s_conn, s_tmp);
-            else
-                tile3d<false, kTile3Y, kTile3Z>(a, tile, s_u, s_conn, s_tmp);
-        } else {
-            int32_t* s_nxt = reinterpret_cast<int32_t*>(s_u + HALO2);
-            if (minima)
-                tile_nd<2, true, kTile2Y, 1>(a, tile, s_u, s_nxt, nullptr, s_tmp);
-            else
-                tile_nd<2, false, kTile2Y, 1>(a, tile, s_u, s_nxt, nullptr, s_tmp);
-        }
-    }
+    if (c & 1)
+        hipLaunchKernelGGL((k_classify_batched<NDIM, true, TY, TZ>), dim3(grid), dim3(256), 0, s, dplan, c);
+    else
+        hipLaunchKernelGGL((k_classify_batched<NDIM, false, TY, TZ>), dim3(grid), dim3(256), 0, s, dplan, c);
 }
 
 hipError_t launch_classify_batched(const BatchPlan* dplan, const BatchPlan& hplan, hipStream_t s)
 {
-    // five 28 KB workgroups fit a CU; 256 CUs
-    const int64_t grid = hplan.total_tiles < 1280 ? hplan.total_tiles : 1280;
-    hipLaunchKernelGGL(k_classify_batched, dim3((unsigned)(grid > 0 ? grid : 1)), dim3(256), 0, s, dplan);
+    for (int c = 0; c < 4; ++c) {
+        const int64_t tiles = hplan.class_tile[c + 1] - hplan.class_tile[c];
+        if (tiles <= 0) continue;
+        const unsigned grid = (unsigned)tiles;
+        const Tuning& tu = hplan.tuning;
+        if (c < 2) {
+            if (tu.tile2 == 1)
+                launch_class<2, 16, 1>(c, grid, dplan, s);
+            else
+                launch_class<2, 32, 1>(c, grid, dplan, s);
+        } else {
+            if (tu.tile3 == 1)
+                launch_class<3, 4, 16>(c, grid, dplan, s);
+            else if (tu.tile3 == 2)
+                launch_class<3, 8, 4>(c, grid, dplan, s);
+            else
+                launch_class<3, 8, 8>(c, grid, dplan, s);
+        }
+    }
+    return hipGetLastError();
+}
+
+template <int TY, int TZ>
+static void launch_3d(const TileArgs& a, bool minima, hipStream_t s)
+{
+    if (minima)
+        hipLaunchKernelGGL((k_classify3d<true, TY, TZ>), dim3(a.ntiles), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_classify3d<false, TY, TZ>), dim3(a.ntiles), dim3(256), 0, s, a);
+}
+
+template <int TY>
+static void launch_2d(const TileArgs& a, bool minima, hipStream_t s)
+{
+    if (minima)
+        hipLaunchKernelGGL((k_classify2d<true, TY>), dim3(a.ntiles), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_classify2d<false, TY>), dim3(a.ntiles), dim3(256), 0, s, a);
+}
+
+hipError_t launch_final_tiled(const Grid& g, int32_t* lab, const Work& w, const Tuning& tu, int flag_slot,
+                              hipStream_t s)
+{
+    int ty, tz;
+    tile_shape(tu, g.ndim, &ty, &tz);
+    const TileArgs a = tile_args(nullptr, g, lab, nullptr, w, 0, 0, ty, tz);
+    if (g.ndim == 3) {
+        if (tu.tile3 == 1)
+            hipLaunchKernelGGL((k_final_tiled<4, 16>), dim3(a.ntiles), dim3(256), 0, s, a, w.exres, tu.hops, flag_slot);
+        else if (tu.tile3 == 2)
+            hipLaunchKernelGGL((k_final_tiled<8, 4>), dim3(a.ntiles), dim3(256), 0, s, a, w.exres, tu.hops, flag_slot);
+        else
+            hipLaunchKernelGGL((k_final_tiled<8, 8>), dim3(a.ntiles), dim3(256), 0, s, a, w.exres, tu.hops, flag_slot);
+    } else if (g.ndim == 2) {
+        if (tu.tile2 == 1)
+            hipLaunchKernelGGL((k_final_tiled<16, 1>), dim3(a.ntiles), dim3(256), 0, s, a, w.exres, tu.hops, flag_slot);
+        else
+            hipLaunchKernelGGL((k_final_tiled<32, 1>), dim3(a.ntiles), dim3(256), 0, s, a, w.exres, tu.hops, flag_slot);
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_classify_tiled(const float* f, const Grid& g, bool minima, int32_t* lab, int32_t* ptr,
-                                 const Work& w, int64_t cap_max, int64_t cap_sad, hipStream_t s)
+                                 const Work& w, int64_t cap_max, int64_t cap_sad, const Tuning& tu, hipStream_t s)
 {
+    int ty, tz;
+    tile_shape(tu, g.ndim, &ty, &tz);
+    const TileArgs a = tile_args(f, g, lab, ptr, w, cap_max, cap_sad, ty, tz);
     if (g.ndim == 3) {
-        const TileArgs a = tile_args(f, g, lab, ptr, w, cap_max, cap_sad, kTile3Y, kTile3Z);
-        if (minima)
-            hipLaunchKernelGGL((k_classify3d<true, kTile3Y, kTile3Z>), dim3(a.ntiles), dim3(256), 0, s, a);
+        if (tu.tile3 == 1)
+            launch_3d<4, 16>(a, minima, s);
+        else if (tu.tile3 == 2)
+            launch_3d<8, 4>(a, minima, s);
         else
-            hipLaunchKernelGGL((k_classify3d<false, kTile3Y, kTile3Z>), dim3(a.ntiles), dim3(256), 0, s, a);
-        return hipGetLastError();
-    }
-    if (g.ndim == 2) {
-        const TileArgs a = tile_args(f, g, lab, ptr, w, cap_max, cap_sad, kTile2Y, 1);
-        if (minima)
-            hipLaunchKernelGGL((k_classify2d<true, kTile2Y>), dim3(a.ntiles), dim3(256), 0, s, a);
+            launch_3d<8, 8>(a, minima, s);
+    } else if (g.ndim == 2) {
+        if (tu.tile2 == 1)
+            launch_2d<16>(a, minima, s);
         else
-            hipLaunchKernelGGL((k_classify2d<false, kTile2Y>), dim3(a.ntiles), dim3(256), 0, s, a);
-        return hipGetLastError();
+            launch_2d<32>(a, minima, s);
+    } else {
+        return hipErrorInvalidValue;
     }
-    return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 }  // namespace eg

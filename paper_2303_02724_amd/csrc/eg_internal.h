@@ -23,13 +23,35 @@
 namespace eg {
 
 constexpr int kMaxNb = 62;          // 2(2^5 - 1)
-constexpr int kJumpHops = 64;       // hops per pointer-jumping pass
-constexpr int kJumpPasses = 6;      // 64^6 > 2^31: enough for any chain
+constexpr int kJumpHops = 64;       // default links per pointer-jumping pass
+constexpr int kMaxPasses = 8;       // flag slots per pass sequence
 constexpr int kSortBlocks = 256;    // grid of the radix-sort kernels
 constexpr int kSortThreads = 256;
 constexpr int kRadixBits = 8;
-constexpr int kTile3Y = 8, kTile3Z = 8;  // 3D tile: 64 x 8 x 8 vertices
-constexpr int kTile2Y = 32;             // 2D tile: 64 x 32 vertices
+constexpr uint32_t kMinTilesPerBlock = 8;  // sort/CSR: 2048 keys per block at least
+constexpr int kTile3Y = 8, kTile3Z = 8;  // default 3D tile: 64 x 8 x 8 vertices
+constexpr int kTile2Y = 32;             // default 2D tile: 64 x 32 vertices
+
+// Decoded eg_out.tuning.
+struct Tuning {
+    int tile3;  // 0: 64x8x8, 1: 64x4x16, 2: 64x8x4
+    int tile2;  // 0: 64x32, 1: 64x16
+    int hops;   // links per label pass
+    int passes; // passes that cover any path of fewer than 2^31 links
+};
+bool decode_tuning(uint32_t t, Tuning* out);
+inline void tile_shape(const Tuning& t, int ndim, int* ty, int* tz)
+{
+    if (ndim == 3) {
+        static const int ys[3] = {8, 4, 8}, zs[3] = {8, 16, 4};
+        *ty = ys[t.tile3];
+        *tz = zs[t.tile3];
+    } else {
+        static const int ys[2] = {32, 16};
+        *ty = ys[t.tile2];
+        *tz = 1;
+    }
+}
 
 // counter slots in the workspace (uint32 each)
 enum : int {
@@ -41,8 +63,8 @@ enum : int {
     C_NSADF = 5,
     C_PASSES = 6,
     C_NEXIT = 7,  // exit-list entries requested by the tiles
-    C_JUMP = 8,   // kJumpPasses "not converged" flags of the exit-list passes
-    C_FINAL = 16, // kJumpPasses "not converged" flags of the per-vertex passes
+    C_JUMP = 8,   // kMaxPasses "not converged" flags of the exit-list passes
+    C_FINAL = 16, // kMaxPasses "not converged" flags of the per-vertex passes
     C_SLOTS = 64,
 };
 
@@ -109,7 +131,14 @@ struct BatchField {
 
 struct BatchPlan {
     int32_t count, bits, fbits, pad0;
+    Tuning tuning;
     int64_t total_tiles, total_quads, total_sad, total_exit, total_max, cap_keys;
+    // fields are ordered by class (2D max, 2D min, 3D max, 3D min); class c
+    // owns fields [class_field[c], class_field[c + 1]) and tiles
+    // [class_tile[c], class_tile[c + 1])
+    int32_t class_field[5];
+    int32_t pad1;
+    int64_t class_tile[5];
     uint32_t* bctr;       // [C_SLOTS] batch counters
     uint64_t* keysA;      // [cap_keys]
     uint64_t* keysB;
@@ -212,9 +241,10 @@ __device__ __forceinline__ uint64_t closure(uint64_t seed, uint64_t mask, const 
 
 hipError_t launch_init(uint32_t* ctr, int32_t* header, hipStream_t s);
 hipError_t launch_classify(const float* f, const Grid& g, const LinkTable& t, bool minima, int32_t* lab,
-                           int32_t* ptr, const Work& w, int64_t cap_max, int64_t cap_sad, hipStream_t s);
+                           int32_t* ptr, const Work& w, int64_t cap_max, int64_t cap_sad, const Tuning& tu,
+                           hipStream_t s);
 hipError_t launch_classify_tiled(const float* f, const Grid& g, bool minima, int32_t* lab, int32_t* ptr,
-                                 const Work& w, int64_t cap_max, int64_t cap_sad, hipStream_t s);
+                                 const Work& w, int64_t cap_max, int64_t cap_sad, const Tuning& tu, hipStream_t s);
 TileArgs tile_args(const float* f, const Grid& g, int32_t* lab, int32_t* ptr, const Work& w, int64_t cap_max,
                    int64_t cap_sad, int ty, int tz);
 hipError_t launch_classify_batched(const BatchPlan* dplan, const BatchPlan& hplan, hipStream_t s);
@@ -236,7 +266,11 @@ __device__ __forceinline__ uint64_t saddle_key(uint32_t s, uint32_t low, uint32_
 //   -N <= x <= -1     "same label as vertex -x-1" (a later vertex of the path)
 //   x < -N            "same label as exit-list entry -x-1-N"
 __device__ __forceinline__ int exit_list_code(int N, uint32_t idx) { return -(N + 1 + (int)idx); }
-hipError_t launch_labels(int32_t* lab, int32_t N, const Work& w, hipStream_t s);
+hipError_t launch_labels(const Grid& g, int32_t* lab, const Work& w, const Tuning& tu, hipStream_t s);
+// Tile-ordered first per-vertex label pass (2D/3D grids); raises ctr[flag_slot]
+// if some vertex is not final yet.
+hipError_t launch_final_tiled(const Grid& g, int32_t* lab, const Work& w, const Tuning& tu, int flag_slot,
+                              hipStream_t s);
 hipError_t launch_reps(const float* f, const Grid& g, const LinkTable& t, bool minima, const int32_t* lab,
                        const Work& w, int64_t cap_sad, int bits, hipStream_t s);
 // Sort keys[0 .. min(*count, cap)) over bits [0, nbits).  Returns in *sorted

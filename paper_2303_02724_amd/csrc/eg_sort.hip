@@ -20,7 +20,10 @@ __device__ __forceinline__ uint32_t chunk_range(uint32_t n, uint32_t nblocks, ui
                                                 uint32_t& hi)
 {
     const uint32_t tiles = (n + 255u) / 256u;
-    const uint32_t per = tiles == 0 ? 1u : (tiles + nblocks - 1u) / nblocks;
+    // at least kMinTilesPerBlock tiles per block: small inputs use few blocks
+    // and a short histogram
+    uint32_t per = tiles == 0 ? 1u : (tiles + nblocks - 1u) / nblocks;
+    per = per < kMinTilesPerBlock ? kMinTilesPerBlock : per;
     const uint32_t active = (tiles + per - 1u) / per;
     const uint64_t l = uint64_t(blk) * per * 256u;
     lo = (uint32_t)(l < n ? l : n);

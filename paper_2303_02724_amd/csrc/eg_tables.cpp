@@ -64,12 +64,30 @@ void make_table(const Grid& g, LinkTable* t)
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+bool decode_tuning(uint32_t t, Tuning* out)
+{
+    Tuning u{};
+    u.tile3 = (int)(t & 0xFu);
+    u.tile2 = (int)((t >> 4) & 0xFu);
+    const int h = (int)((t >> 8) & 0xFFu);
+    if ((t >> 16) != 0 || u.tile3 > 2 || u.tile2 > 1) return false;
+    u.hops = h == 0 ? kJumpHops : h;
+    if (u.hops != 16 && u.hops != 32 && u.hops != 64 && u.hops != 128) return false;
+    int bits = 0;
+    while ((1 << bits) < u.hops) ++bits;
+    u.passes = (31 + bits - 1) / bits;  // hops^passes >= 2^31
+    if (u.passes > kMaxPasses) return false;
+    *out = u;
+    return true;
+}
+
 int64_t exit_capacity(int64_t N)
 {
-    // tiles publish the distinct vertices where paths leave them; smooth
-    // fields need far fewer than N/16 entries, and an overflowing tile falls
-    // back to per-vertex codes, so this only bounds memory, not correctness
-    int64_t cap = std::max<int64_t>(N / 16, 4096);
+    // one entry per vertex whose steepest step leaves its tile: about half
+    // of a tile's boundary layer (a quarter of all vertices for 64x8x8 tiles)
+    // on smooth fields.  An overflowing tile falls back to vertex codes, so
+    // this bounds memory, not correctness.
+    int64_t cap = std::max<int64_t>(N / 2, 4096);
     const int64_t room = (int64_t(1) << 31) - 1 - N;
     return std::max<int64_t>(0, std::min(cap, room));
 }

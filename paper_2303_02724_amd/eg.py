@@ -23,9 +23,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libeg_hip.so")
 
 EG_OK, EG_ERR_ARG, EG_ERR_TOO_LARGE, EG_ERR_WORKSPACE, EG_ERR_NAN, EG_ERR_CAPACITY, EG_ERR_HIP = range(7)
+
+
+def tuning(tile3: int = 0, tile2: int = 0, hops: int = 0) -> int:
+    """eg_out.tuning value (EG_TUNE_TILE3 | EG_TUNE_TILE2 | EG_TUNE_HOPS)."""
+    return (tile3 & 0xF) | ((tile2 & 0xF) << 4) | ((hops & 0xFF) << 8)
 EG_MINIMA = 0x1
 EG_MAX_NDIM = 5
-H_STATUS, H_NMAX, H_NSAD, H_NARC, H_NPAIRS, H_PASSES = range(6)
+H_STATUS, H_NMAX, H_NSAD, H_NARC, H_NPAIRS, H_PASSES, H_EXITS = range(7)
 H_SLOTS = 8
 
 
@@ -52,6 +57,7 @@ class eg_out(ctypes.Structure):
         ("workspace", ctypes.c_void_p),
         ("ws_bytes", ctypes.c_size_t),
         ("header", ctypes.c_void_p),
+        ("tuning", ctypes.c_uint32),
     ]
 
 
@@ -147,7 +153,7 @@ class Builder:
     ``EGResult`` of views into the buffers (valid until the next launch).
     """
 
-    def __init__(self, shape, minima: bool = False, want_ptr: bool = False, device=None, **caps):
+    def __init__(self, shape, minima: bool = False, want_ptr: bool = False, device=None, tuning: int = 0, **caps):
         self.shape = tuple(int(s) for s in shape)
         if not 1 <= len(self.shape) <= EG_MAX_NDIM:
             raise EGError(EG_ERR_ARG, f"ndim={len(self.shape)}")
@@ -156,6 +162,7 @@ class Builder:
             self.n *= s
         self.minima = minima
         self.want_ptr = want_ptr
+        self.tuning = int(tuning)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         c = default_caps(self.n, len(self.shape))
         c.update({k: int(v) for k, v in caps.items() if v is not None})
@@ -195,6 +202,7 @@ class Builder:
         o.workspace = aligned
         o.ws_bytes = ws
         o.header = self.header.data_ptr()
+        o.tuning = self.tuning
         self.out = o
         self._dims = _dims(self.shape)
 
@@ -233,7 +241,7 @@ class Builder:
             arc_maxima=self.arcs[:max(narc, 0)],
             ptr=self.ptr.view(self.shape) if self.ptr is not None else None,
             passes=h[H_PASSES],
-            counts={"maxima": nmax, "saddles": nsad, "arcs": narc, "pairs": h[H_NPAIRS]},
+            counts={"maxima": nmax, "saddles": nsad, "arcs": narc, "pairs": h[H_NPAIRS], "exits": h[H_EXITS]},
         )
 
     def grow(self, h):
@@ -279,11 +287,11 @@ class BatchBuilder:
     (benchmarks, HIP graph replays) need no new plan.
     """
 
-    def __init__(self, shapes, minima=False, device=None, caps=None):
+    def __init__(self, shapes, minima=False, device=None, caps=None, tuning: int = 0):
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         caps = caps or [None] * len(shapes)
         mins = minima if isinstance(minima, (list, tuple)) else [minima] * len(shapes)
-        self.builders = [Builder(sh, minima=mn, device=self.device, **(c or {}))
+        self.builders = [Builder(sh, minima=mn, device=self.device, tuning=tuning, **(c or {}))
                          for sh, mn, c in zip(shapes, mins, caps)]
         self._plan_host = None
         self._fields = None
@@ -387,7 +395,8 @@ def build_batched(fields, minima=False, **kw):
     return bb.run([f.contiguous() for f in fields])
 
 
-def build(field: torch.Tensor, minima: bool = False, want_ptr: bool = False, **caps) -> EGResult:
+def build(field: torch.Tensor, minima: bool = False, want_ptr: bool = False, tuning: int = 0,
+          **caps) -> EGResult:
     """Extremum graph of ``field`` (float32 device tensor, 1..5 axes)."""
-    b = Builder(field.shape, minima=minima, want_ptr=want_ptr, device=field.device, **caps)
+    b = Builder(field.shape, minima=minima, want_ptr=want_ptr, device=field.device, tuning=tuning, **caps)
     return b.run(field.contiguous())

@@ -44,6 +44,7 @@ class ServeStats:
     max_inflight: int = 0
     peak_bytes: int = 0
     rejected_for_memory: int = 0
+    regrown: int = 0
     wall_s: float = 0.0
 
     def summary(self):
@@ -64,6 +65,7 @@ class ServeStats:
             "max_inflight_batches": self.max_inflight,
             "peak_footprint_gb": self.peak_bytes / 1e9,
             "admission_waits_for_memory": self.rejected_for_memory,
+            "capacity_regrowths": self.regrown,
         }
 
 
@@ -144,8 +146,18 @@ class Server:
             for lane in self.lanes:
                 if lane.event is not None and lane.event.query():
                     end = time.perf_counter() - t0
-                    for (ri, b, arr, start) in lane.batch:
+                    for (ri, b, arr, start, fi) in lane.batch:
                         h = b.header_values()
+                        if h[eg.H_STATUS] == eg.EG_ERR_CAPACITY:
+                            # outputs did not fit: grow this request's buffers
+                            # and run it again in a later batch
+                            self.used -= footprint(b)
+                            b.grow(h)
+                            self.used += footprint(b)
+                            st.peak_bytes = max(st.peak_bytes, self.used)
+                            st.regrown += 1
+                            waiting.insert(0, (ri, b, arr, fi))
+                            continue
                         if h[eg.H_STATUS] != eg.EG_OK:
                             raise eg.EGError(h[eg.H_STATUS], f"request {ri}")
                         st.done.append(Done(ri, b.shape, arr, start, end, st.batches, b))
@@ -189,7 +201,7 @@ class Server:
                 ev = torch.cuda.Event()
                 ev.record(s)
                 lane.event = ev
-                lane.batch = [(ri, b, arr, start) for (ri, b, arr, fi) in batch]
+                lane.batch = [(ri, b, arr, start, fi) for (ri, b, arr, fi) in batch]
                 st.batches += 1
                 st.max_inflight = max(st.max_inflight, sum(l.event is not None for l in self.lanes))
                 continue

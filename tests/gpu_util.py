@@ -8,9 +8,9 @@ from paper_2303_02724_amd import eg
 KEYS = ["labels", "maxima", "saddles", "saddle_beta", "arc_offsets", "arc_maxima"]
 
 
-def gpu_graph(f: np.ndarray, minima: bool = False, want_ptr: bool = True, **caps) -> dict:
+def gpu_graph(f: np.ndarray, minima: bool = False, want_ptr: bool = True, tuning: int = 0, **caps) -> dict:
     t = torch.from_numpy(np.ascontiguousarray(f, dtype=np.float32)).to("cuda:0")
-    r = eg.build(t, minima=minima, want_ptr=want_ptr, **caps)
+    r = eg.build(t, minima=minima, want_ptr=want_ptr, tuning=tuning, **caps)
     out = {
         "labels": r.labels.reshape(-1).cpu().numpy(),
         "maxima": r.maxima.cpu().numpy(),

@@ -73,6 +73,13 @@ def test_build_rejects_bad_arguments_on_host():
     o.flags = 0x10  # unknown flag
     assert L.eg_build(fake, 2, dims, None, ctypes.byref(o)) == eg.EG_ERR_ARG
     o.flags = 0
+    o.tuning = 0x3  # no fourth 3D tile shape
+    assert L.eg_build(fake, 2, dims, None, ctypes.byref(o)) == eg.EG_ERR_ARG
+    o.tuning = 0x700  # 7 links per pass is not offered
+    assert L.eg_build(fake, 2, dims, None, ctypes.byref(o)) == eg.EG_ERR_ARG
+    o.tuning = eg.tuning(tile3=2, tile2=1, hops=128) | (1 << 20)  # unknown bits
+    assert L.eg_build(fake, 2, dims, None, ctypes.byref(o)) == eg.EG_ERR_ARG
+    o.tuning = 0
     o.cap_sad = 1 << 31
     assert L.eg_build(fake, 2, dims, None, ctypes.byref(o)) == eg.EG_ERR_TOO_LARGE
     assert eg.status_string(eg.EG_ERR_NAN) == "field contains NaN"
@@ -135,3 +142,53 @@ def test_link_table_fvectors_and_3d_histogram():
             beta += 1
         hist[str(beta)] = hist.get(str(beta), 0) + 1
     assert hist == gold["beta_histogram_3d"]
+
+
+def _fake_out(cap=4, ws=1 << 30):
+    o = eg.eg_out()
+    o.labels = o.header = o.arc_offsets = o.maxima = o.saddles = o.arc_maxima = 0x2000
+    o.cap_max = o.cap_sad = o.cap_arc = o.cap_pairs = cap
+    o.workspace = 0x100000
+    o.ws_bytes = ws
+    return o
+
+
+def test_batch_plan_validation_on_host():
+    L = eg.lib()
+    assert L.eg_batch_plan_bytes(0) == 0
+    assert L.eg_batch_plan_bytes(3) > L.eg_batch_plan_bytes(1) > 0
+    n = 2
+    ndims = (ctypes.c_int * n)(2, 3)
+    dims = (ctypes.c_int64 * (n * eg.EG_MAX_NDIM))(16, 16, 0, 0, 0, 8, 8, 8, 0, 0)
+    outs = (eg.eg_out * n)(_fake_out(), _fake_out())
+    wsb = L.eg_batch_workspace_bytes(n, ndims, dims, outs)
+    assert wsb > 0
+    pb = L.eg_batch_plan_bytes(n)
+    host = (ctypes.c_uint8 * pb)()
+    fields = (ctypes.c_void_p * n)(0x1000, 0x1000)
+    ok = L.eg_batch_plan(n, fields, ndims, dims, outs, ctypes.c_void_p(0x200000), wsb, host, pb)
+    assert ok == eg.EG_OK
+    # 4D fields are not batched
+    nd4 = (ctypes.c_int * n)(2, 4)
+    dims4 = (ctypes.c_int64 * (n * eg.EG_MAX_NDIM))(16, 16, 0, 0, 0, 4, 4, 4, 4, 0)
+    assert L.eg_batch_workspace_bytes(n, nd4, dims4, outs) == 0
+    assert L.eg_batch_plan(n, fields, nd4, dims4, outs, ctypes.c_void_p(0x200000), wsb, host, pb) == eg.EG_ERR_ARG
+    # workspace missing, misaligned, short
+    assert L.eg_batch_plan(n, fields, ndims, dims, outs, None, wsb, host, pb) == eg.EG_ERR_WORKSPACE
+    assert L.eg_batch_plan(n, fields, ndims, dims, outs, ctypes.c_void_p(0x200001), wsb, host,
+                           pb) == eg.EG_ERR_WORKSPACE
+    assert L.eg_batch_plan(n, fields, ndims, dims, outs, ctypes.c_void_p(0x200000), 64, host,
+                           pb) == eg.EG_ERR_WORKSPACE
+    # short host plan buffer
+    assert L.eg_batch_plan(n, fields, ndims, dims, outs, ctypes.c_void_p(0x200000), wsb, host, 8) == eg.EG_ERR_ARG
+    # cap_max must be at least 1 in a batch
+    outs0 = (eg.eg_out * n)(_fake_out(), _fake_out())
+    outs0[1].cap_max = 0
+    assert L.eg_batch_plan(n, fields, ndims, dims, outs0, ctypes.c_void_p(0x200000), wsb, host,
+                           pb) == eg.EG_ERR_ARG
+    # per-field workspace too small
+    outs1 = (eg.eg_out * n)(_fake_out(), _fake_out(ws=8))
+    assert L.eg_batch_plan(n, fields, ndims, dims, outs1, ctypes.c_void_p(0x200000), wsb, host,
+                           pb) == eg.EG_ERR_WORKSPACE
+    # a plan without a device workspace cannot be launched
+    assert L.eg_build_batched(None, None) == eg.EG_ERR_ARG

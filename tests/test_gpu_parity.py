@@ -176,12 +176,54 @@ def test_serving_mix_equals_alone():
     for _ in range(60):
         t += rng.exponential(1 / 2000.0)
         reqs.append((t, int(rng.integers(0, len(fields)))))
-    got = {}
-    budget = 3 * max(serving.footprint(eg.Builder(tuple(f.shape))) for f in fields)
-    srv = serving.Server(hbm_budget=budget, max_slots=8, max_batch=4, lanes=2)
-    st = srv.run(reqs, fields, on_done=lambda ri, b: got.__setitem__(ri, _result_np(b.finish())))
-    assert len(got) == len(reqs)
-    assert st.peak_bytes <= budget
-    assert st.batches < len(reqs)  # requests were batched
-    for ri, (_, fi) in enumerate(reqs):
-        assert_same(got[ri], alone[fi], KEYS, f"request {ri} field {fi}")
+    caps = {tuple(t.shape): {"cap_max": max(1, len(a["maxima"])), "cap_sad": max(1, len(a["saddles"])),
+                             "cap_pairs": max(1, int(a["saddle_beta"].sum())), "cap_arc": max(1, len(a["arc_maxima"]))}
+            for t, a in zip(fields, alone)}
+    budget = 3 * max(serving.footprint(eg.Builder(sh, **caps[sh])) for sh in caps)
+    for caps_for, exact in ((lambda sh: caps[sh], True), (lambda sh: {"cap_max": 1, "cap_sad": 1, "cap_pairs": 1,
+                                                                       "cap_arc": 1}, False)):
+        got = {}
+        srv = serving.Server(hbm_budget=budget, max_slots=8, max_batch=4, lanes=2, caps_for=caps_for)
+        st = srv.run(reqs, fields, on_done=lambda ri, b: got.__setitem__(ri, _result_np(b.finish())))
+        assert len(got) == len(reqs)
+        if exact:
+            assert st.peak_bytes <= budget  # admission respects the budget
+            assert st.regrown == 0
+        else:
+            assert st.regrown > 0  # undersized requests grew and ran again
+        assert st.batches < len(reqs)  # requests were batched
+        for ri, (_, fi) in enumerate(reqs):
+            assert_same(got[ri], alone[fi], KEYS, f"request {ri} field {fi}")
+
+
+def test_every_tuning_gives_identical_results():
+    """Launch choices (tile shapes, links per label pass) never change the
+    output: each one equals the oracle on the same field."""
+    from paper_2303_02724_amd import eg, tune
+    f3 = W.gaussian_random_field((37, 45, 130), 12, corr_len=3.0, workers=4)
+    f2 = W.gaussian_mixture((150, 200), 13, n_gauss=6, noise=1e-3)
+    for f in (f3, f2):
+        want = O.extremum_graph(f)
+        for tu in tune.candidates(f.ndim) + [eg.tuning(hops=16)]:
+            assert_same(gpu_graph(f, tuning=tu), want, KEYS + ["ptr"], f"tuning {tu:#x} {f.shape}")
+
+
+def test_batched_with_tuning():
+    import torch
+    from paper_2303_02724_amd import eg
+    specs = W.batched_specs(count=5, side2=(40, 200), side3=(16, 40), meta_seed=21)
+    fields = [W.batched_field(sp) for sp in specs]
+    ts = [torch.from_numpy(f).cuda() for f in fields]
+    bb = eg.BatchBuilder([f.shape for f in fields], tuning=eg.tuning(tile3=1, tile2=1, hops=32))
+    for f, r in zip(fields, bb.run(ts)):
+        assert_same(_result_np(r), O.extremum_graph(f), KEYS, f"batched tuned {f.shape}")
+
+
+def test_autotuner_records_a_choice(tmp_path):
+    import torch
+    from paper_2303_02724_amd import tune
+    f = torch.from_numpy(W.gaussian_random_field((48, 48, 64), 14, corr_len=3.0, workers=4)).cuda()
+    path = str(tmp_path / "tune.json")
+    res = tune.tune(f, reps=2, path=path)
+    assert res["tuning"] in res["times_ms"]
+    assert tune.best(tuple(f.shape), path=path) == res["tuning"]
