@@ -348,6 +348,9 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
     int32_t* __restrict__ ptr = a.ptr;
     uint32_t* __restrict__ ctr = a.ctr;
     int32_t* s_nxt = reinterpret_cast<int32_t*>(s_u);
+    // per row (and K = the vertex itself): packed successor and global offset
+    uint32_t* s_pack = s_tmp + 8;
+    int32_t* s_gdel = reinterpret_cast<int32_t*>(s_tmp + 8 + 16);
 
     const int tid = threadIdx.x, lx = tid & 63, wv = tid >> 6;
     const int tx = b % a.tiles_x;
@@ -357,6 +360,19 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
     const int SY = X;
     const int SZ = X * Y;
+    if (tid <= K) {
+        uint32_t pk = kSelfPack;
+        int gd = 0;
+        if (tid < K) {
+            const int dz = (int)((Pack<3>::z >> (2 * tid)) & 3u) - 1;
+            const int dy = (int)((Pack<3>::y >> (2 * tid)) & 3u) - 1;
+            const int dx = (int)((Pack<3>::x >> (2 * tid)) & 3u) - 1;
+            pk = succ_pack<TY, HY, HX>(dz, dy, dx);
+            gd = dz * SZ + dy * SY + dx;
+        }
+        s_pack[tid] = pk;
+        s_gdel[tid] = gd;
+    }
 
     bool nan = false;
     {
@@ -433,16 +449,16 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
             const int gz = z0 + lz;
             const bool in = gx < X && gy < Y && gz < Z;
             const uint32_t uv = win[(lz + 1) % 3][3];
-            uint32_t up = 0, best_u = 0;
-            // the steepest candidate so far, as a packed successor literal
-            uint32_t best_p = kSelfPack;
+            // upper-link mask in two 7-row halves (bit constants stay inline)
+            uint32_t up_lo = 0, up_hi = 0, best_u = 0;
+            int best_j = K;  // the steepest candidate so far; K is the vertex itself
             static_for<0, K + 1>([&](auto step) {
                 constexpr int st = decltype(step)::value;
                 constexpr int pos = MINMODE ? K - st : st;
                 if constexpr (pos == K / 2) {
                     if (uv >= best_u) {
                         best_u = uv;
-                        best_p = kSelfPack;
+                        best_j = K;
                     }
                 } else {
                     constexpr int j = pos < K / 2 ? pos : pos - 1;
@@ -450,29 +466,32 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
                     constexpr bool wins_tie = (j >= K / 2) != MINMODE;
                     const uint32_t u = win[(lz + WJ::plane) % 3][WJ::pos];
                     const bool above = wins_tie ? (u >= uv) : (u > uv);
-                    up |= uint32_t(above) << j;
+                    if constexpr (j < 7)
+                        up_lo |= above ? (1u << j) : 0u;
+                    else
+                        up_hi |= above ? (1u << (j - 7)) : 0u;
                     if (u >= best_u) {
                         best_u = u;
-                        best_p = succ_pack<TY, HY, HX>(WJ::dz, WJ::dy, WJ::dx);
+                        best_j = j;
                     }
                 }
             });
+            const uint32_t up = up_lo | (up_hi << 7);
             const bool is_max = in && up == 0;
             const bool is_sad = in && up != 0 && !((s_conn[up >> 5] >> (up & 31)) & 1u);
             const int v = gz * SZ + gy * SY + gx;
             const int li = (lz * TY + ly) * TX + lx;
             int n = li;  // a maximum, or a vertex outside the grid, stays put
             if (in) {
-                const int em = (int)(best_p & 63u);
-                const int dx = ((em >> 1) & 1) - (em & 1), dy = ((em >> 3) & 1) - ((em >> 2) & 1),
-                          dz = ((em >> 5) & 1) - ((em >> 4) & 1);
+                const uint32_t best_p = s_pack[best_j];
+                const int pv = v + s_gdel[best_j];
                 if (!(best_p & kSelfPack)) {
                     // leaves the tile iff it steps across a face the vertex lies on
                     const uint32_t faces = bb_xy | (lz == 0 ? 16u : 0u) | (lz == TZ - 1 ? 32u : 0u);
                     const int loff = (int)(best_p << 15) >> 21;
-                    n = (faces & best_p & 63u) ? -(v + dz * SZ + dy * SY + dx + 1) : li + loff;
+                    n = (faces & best_p & 63u) ? -(pv + 1) : li + loff;
                 }
-                if (ptr) ptr[v] = (best_p & kSelfPack) ? v : v + dz * SZ + dy * SY + dx;
+                if (ptr) ptr[v] = pv;
             }
             nxt[c * TZ + lz] = n;
             wave_append(is_max, (uint32_t)v, &ctr[C_NMAX], a.umax, a.cap_max);
@@ -568,7 +587,7 @@ __global__ __launch_bounds__(256) void k_classify3d(TileArgs a)
     constexpr int HALO = 66 * (TY + 2) * (TZ + 2);
     __shared__ uint32_t s_u[HALO];
     __shared__ uint32_t s_conn[512];
-    __shared__ uint32_t s_tmp[8];
+    __shared__ uint32_t s_tmp[40];
     tile3d<MINMODE, TY, TZ>(a, xcd_tile(blockIdx.x, a.ntiles), s_u, s_conn, s_tmp);
 }
 
@@ -616,7 +635,7 @@ __global__ __launch_bounds__(256) void k_classify_batched(const BatchPlan* __res
     constexpr int WORDS = NDIM == 3 ? HALO3 : HALO2 + 64 * TY;
     __shared__ uint32_t s_u[WORDS];
     __shared__ uint32_t s_conn[NDIM == 3 ? 512 : 1];
-    __shared__ uint32_t s_tmp[8];
+    __shared__ uint32_t s_tmp[40];
     const BatchField* fs = plan->fields;
     const int f0 = plan->class_field[cls], f1 = plan->class_field[cls + 1];
     const int64_t item = plan->class_tile[cls] + blockIdx.x;
