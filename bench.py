@@ -169,7 +169,7 @@ def run_batched(args):
     for b in bb.builders:
         h = b.header_values()
         caps.append({"cap_max": max(1, h[eg.H_NMAX]), "cap_sad": max(1, h[eg.H_NSAD]),
-                     "cap_pairs": max(1, h[eg.H_NPAIRS]), "cap_arc": max(1, h[eg.H_NARC])})
+                     "cap_arc": max(1, h[eg.H_NARC])})
     bb = eg.BatchBuilder([f.shape for f in fields], device=dev, caps=caps)
     bb.run(ts)
     s = torch.cuda.current_stream()
@@ -273,7 +273,7 @@ def run_serving(args):
     for t in ts:
         r = eg.build(t)
         caps[tuple(t.shape)] = {"cap_max": max(1, r.counts["maxima"]), "cap_sad": max(1, r.counts["saddles"]),
-                                "cap_pairs": max(1, r.counts["pairs"]), "cap_arc": max(1, r.counts["arcs"])}
+                                "cap_arc": max(1, r.counts["arcs"])}
     torch.cuda.synchronize()
     out = {}
     for name, kw in [("continuous_batching", dict(max_batch=32, lanes=3, max_slots=96)),

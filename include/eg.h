@@ -69,7 +69,7 @@ typedef enum eg_status {
 #define EG_H_NMAX 1   /* number of maxima (required size of maxima[]) */
 #define EG_H_NSAD 2   /* number of saddles (required size of saddles[], saddle_beta[]) */
 #define EG_H_NARC 3   /* number of arcs (required size of arc_maxima[]); -1 if unknown */
-#define EG_H_NPAIRS 4 /* number of (saddle, component) pairs (required cap_pairs) */
+#define EG_H_NPAIRS 4 /* number of (saddle, upper-link component) pairs, the sum of beta; -1 if unknown */
 #define EG_H_PASSES 5 /* per-vertex label passes that ran */
 #define EG_H_EXITS 6  /* tile exit-list entries the labels used (diagnostic) */
 #define EG_H_SLOTS 8
@@ -86,8 +86,6 @@ typedef enum eg_status {
  *   arc_offsets  [cap_sad + 1]  CSR row offsets: saddle i owns arc_maxima[arc_offsets[i] ..
  *                               arc_offsets[i+1]), ascending and distinct
  *   arc_maxima   [cap_arc]      maxima ids of the arcs
- *   cap_pairs    capacity for (saddle, upper-link component) pairs, i.e. the sum
- *                of beta over saddles; sizes part of the workspace
  *   workspace    device scratch of at least eg_workspace_bytes(...) bytes,
  *                256-byte aligned; contents need not be initialised
  *   header       [EG_H_SLOTS] int32 device; written by the library
@@ -104,7 +102,6 @@ typedef struct eg_out {
     int64_t cap_sad;
     int32_t* arc_maxima;
     int64_t cap_arc;
-    int64_t cap_pairs;
     void* workspace;
     size_t ws_bytes;
     int32_t* header;
@@ -125,12 +122,13 @@ typedef struct eg_out {
 
 /*
  * Workspace bytes that eg_build needs for a field of the given shape and the
- * given capacities (the cap_* fields of eg_out).  Pure, host-only.  Returns 0
- * on invalid arguments (ndim outside [1, EG_MAX_NDIM], a dim < 1, N >= 2^31,
- * a negative capacity).
+ * given saddle capacity (eg_out.cap_sad; the other capacities do not enter):
+ * about 4.25 bytes per vertex (more when the last axis is much shorter than
+ * 64) plus 8 bytes per saddle slot.  Pure,
+ * host-only.  Returns 0 on invalid arguments (ndim outside [1, EG_MAX_NDIM],
+ * a dim < 1, N >= 2^31, a capacity outside [0, 2^31)).
  */
-size_t eg_workspace_bytes(int ndim, const int64_t* dims, int64_t cap_max, int64_t cap_sad,
-                          int64_t cap_pairs);
+size_t eg_workspace_bytes(int ndim, const int64_t* dims, int64_t cap_sad);
 
 /*
  * Extremum graph of one field (Sec. 3: classification, then path tracing).
@@ -143,8 +141,9 @@ size_t eg_workspace_bytes(int ndim, const int64_t* dims, int64_t cap_max, int64_
  *
  * Returns EG_OK once the work is queued; the device header then carries the
  * final status and the counts.  On EG_ERR_CAPACITY every count in the header
- * is the size needed, except EG_H_NARC which is -1 when the pairs overflowed
- * (retry with cap_pairs >= EG_H_NPAIRS first).  Outputs are bit-identical for
+ * is the size needed, except EG_H_NARC and EG_H_NPAIRS, which are -1 when the
+ * saddles overflowed (retry with cap_sad >= EG_H_NSAD first).  Entries below
+ * each capacity are written even then.  Outputs are bit-identical for
  * identical inputs and independent of launch configuration.
  */
 eg_status eg_build(const float* field, int ndim, const int64_t* dims, void* stream,
@@ -159,15 +158,15 @@ eg_status eg_build(const float* field, int ndim, const int64_t* dims, void* stre
  *              counters, then for every vertex its steepest-ascent pointer
  *              (into labels[], and ptr[] when given), the maxima (empty upper
  *              link) and the saddle candidates (>= 2 upper-link components),
- *              kept in the workspace.
+ *              kept in the workspace as bitmasks.
  * eg_label     Sec. 2 / Alg. 2 (the walk to a maximum): pointer jumping on
  *              labels[] in place until every entry names its maximum.  Needs
  *              eg_classify's labels[] and workspace.
- * eg_arcs      Sec. 3.4 Alg. 2 / UpperLinkRep: the highest vertex of every
- *              upper-link component of every saddle, its label, the de-
- *              duplicated (saddle, maximum) arcs (device radix sort), the
- *              ascending maxima and saddles, the CSR, and the header.  Needs
- *              the labels and workspace of the two stages before it.
+ * eg_arcs      Sec. 3.4 Alg. 2 / UpperLinkRep: the ascending maxima and
+ *              saddles (compaction of the bitmasks), the highest vertex of
+ *              every upper-link component of every saddle, its label, the
+ *              distinct (saddle, maximum) arcs as a CSR, and the header.
+ *              Needs the labels and workspace of the two stages before it.
  */
 eg_status eg_classify(const float* field, int ndim, const int64_t* dims, void* stream,
                       const eg_out* out);
@@ -178,14 +177,15 @@ eg_status eg_arcs(const float* field, int ndim, const int64_t* dims, void* strea
 
 /*
  * Batches: the extremum graphs of `count` independent 2D or 3D fields in one
- * launch sequence.  Classification runs as one persistent launch over a work
- * list of (field, tile) items; labels, reps and the per-field CSR outputs are
- * computed for all fields together, with one radix sort over keys that carry
- * the field index.  Results equal eg_build's for every field.
+ * launch sequence.  Classification runs one launch per class of fields (2D or
+ * 3D, maximum or minimum graph) over a work list of (field, tile) items;
+ * labels, compaction, arcs and the per-field CSR outputs are computed for all
+ * fields together, each launch split over the fields in proportion to their
+ * size.  Results equal eg_build's for every field.
  *
  * Field i is described exactly as for eg_build: fields[i] (device float32),
  * ndims[i] (2 or 3), dims[i * EG_MAX_NDIM + 0 .. ndims[i]-1], outs[i] (its own
- * output buffers, header and workspace of eg_workspace_bytes; cap_max >= 1).
+ * output buffers, header and workspace of eg_workspace_bytes).
  * The batch also needs a batch workspace (device, 256-byte aligned, at least
  * eg_batch_workspace_bytes) and a plan:
  *
@@ -197,11 +197,10 @@ eg_status eg_arcs(const float* field, int ndim, const int64_t* dims, void* strea
  *      allocates or synchronises, so a plan can be replayed, e.g. from a HIP
  *      graph, as long as the fields and buffers it names stay in place.
  *
- * Errors: EG_ERR_ARG for ndim outside {2, 3}, NULL pointers, cap_max < 1 or a
- * short host plan buffer; EG_ERR_TOO_LARGE when a field is too large, the keys
- * of the batch exceed 2^32 or the field index plus two vertex ids and two
- * flag bits exceed 64 bits; EG_ERR_WORKSPACE for a missing, misaligned or short
- * workspace.  Device-side conditions go to each field's header.
+ * Errors: EG_ERR_ARG for ndim outside {2, 3}, NULL pointers or a short host
+ * plan buffer; EG_ERR_TOO_LARGE when a field or a capacity is too large;
+ * EG_ERR_WORKSPACE for a missing, misaligned or short workspace.  Device-side
+ * conditions go to each field's header.
  */
 size_t eg_batch_plan_bytes(int count);
 size_t eg_batch_workspace_bytes(int count, const int* ndims, const int64_t* dims, const eg_out* outs);

@@ -28,10 +28,10 @@ bool grid_from(int ndim, const int64_t* dims, Grid* g)
     return true;
 }
 
-bool caps_ok(int64_t cap_max, int64_t cap_sad, int64_t cap_pairs, int64_t cap_arc)
+bool caps_ok(int64_t cap_max, int64_t cap_sad, int64_t cap_arc)
 {
     auto ok = [](int64_t c) { return c >= 0 && c < kMaxIndex; };
-    return ok(cap_max) && ok(cap_sad) && ok(cap_pairs) && ok(cap_arc) && cap_pairs + cap_sad < kMaxIndex;
+    return ok(cap_max) && ok(cap_sad) && ok(cap_arc);
 }
 
 eg_status too_large_or_arg(int ndim, const int64_t* dims)
@@ -54,15 +54,16 @@ eg_status check_one(const float* field, int ndim, const int64_t* dims, const eg_
     if (!decode_tuning(o->tuning, &tu)) return EG_ERR_ARG;
     if (!grid_from(ndim, dims, g)) return too_large_or_arg(ndim, dims);
     if (o->flags & ~uint32_t(EG_MINIMA)) return EG_ERR_ARG;
-    if (!caps_ok(o->cap_max, o->cap_sad, o->cap_pairs, o->cap_arc)) return EG_ERR_TOO_LARGE;
+    if (!caps_ok(o->cap_max, o->cap_sad, o->cap_arc)) return EG_ERR_TOO_LARGE;
     if (!o->labels || !o->header || !o->arc_offsets) return EG_ERR_ARG;
     if (reinterpret_cast<uintptr_t>(o->labels) & 15u) return EG_ERR_ARG;
     if ((o->cap_max > 0 && !o->maxima) || (o->cap_sad > 0 && !o->saddles) || (o->cap_arc > 0 && !o->arc_maxima))
         return EG_ERR_ARG;
-    const Work need = carve(nullptr, g->N, o->cap_max, o->cap_sad, o->cap_pairs);
+    const int64_t X = g->dims[g->ndim - 1];
+    const Work need = carve(nullptr, g->N, X, o->cap_sad);
     if (!o->workspace || (reinterpret_cast<uintptr_t>(o->workspace) & 255u) || o->ws_bytes < need.bytes)
         return EG_ERR_WORKSPACE;
-    *w = carve(o->workspace, g->N, o->cap_max, o->cap_sad, o->cap_pairs);
+    *w = carve(o->workspace, g->N, X, o->cap_sad);
     return EG_OK;
 }
 
@@ -73,7 +74,7 @@ hipError_t stage_classify(const float* field, const Grid& g, const LinkTable& t,
     const bool minima = (o.flags & EG_MINIMA) != 0;
     hipError_t e = launch_init(w.ctr, o.header, s);
     if (e != hipSuccess) return e;
-    return launch_classify(field, g, t, minima, o.labels, o.ptr, w, o.cap_max, o.cap_sad, tu, s);
+    return launch_classify(field, g, t, minima, o.labels, o.ptr, w, tu, s);
 }
 
 // Stage (b): labels by pointer jumping, in place.
@@ -82,23 +83,11 @@ hipError_t stage_label(const Grid& g, const eg_out& o, const Work& w, const Tuni
     return launch_labels(g, o.labels, w, tu, s);
 }
 
-// Stage (d) and the canonical outputs: maxima and (saddle, maximum) keys
-// from the reps -> one radix sort -> ascending maxima, unique arcs, CSR; the
-// header.
-hipError_t stage_arcs(const float* field, const Grid& g, const LinkTable& t, const eg_out& o, const Work& w,
-                      hipStream_t s)
+// Stage (d) and the canonical outputs: ascending maxima and saddles, the
+// arcs of every saddle as a CSR, and the header.
+hipError_t stage_arcs(const float* field, const Grid& g, const eg_out& o, const Work& w, hipStream_t s)
 {
-    const bool minima = (o.flags & EG_MINIMA) != 0;
-    const int b = id_bits(g.N);
-    hipError_t e;
-    if ((e = launch_load_maxima(w, o.cap_max, b, s)) != hipSuccess) return e;
-    if ((e = launch_reps(field, g, t, minima, o.labels, w, o.cap_sad, b, s)) != hipSuccess) return e;
-    uint64_t* sorted = nullptr;
-    if ((e = launch_sort(w.keysA, w.keysB, &w.ctr[C_NKEYS], w.cap_keys, 2 * b + 2, w.hist, &sorted, s)) !=
-        hipSuccess)
-        return e;
-    if ((e = launch_csr(sorted, w, b, o, s)) != hipSuccess) return e;
-    return launch_finalize(w, o, s);
+    return launch_arcs(arc_args(field, g, o, w), s);
 }
 
 enum Stage { S_CLASSIFY = 1, S_LABEL = 2, S_ARCS = 4, S_ALL = 7 };
@@ -118,18 +107,17 @@ eg_status run_stages(int stages, const float* field, int ndim, const int64_t* di
     hipError_t e = hipSuccess;
     if (stages & S_CLASSIFY) e = stage_classify(field, g, t, *out, w, tu, s);
     if (e == hipSuccess && (stages & S_LABEL)) e = stage_label(g, *out, w, tu, s);
-    if (e == hipSuccess && (stages & S_ARCS)) e = stage_arcs(field, g, t, *out, w, s);
+    if (e == hipSuccess && (stages & S_ARCS)) e = stage_arcs(field, g, *out, w, s);
     return e == hipSuccess ? EG_OK : EG_ERR_HIP;
 }
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct BatchLayout {
-    size_t o_plan, o_fields, o_bctr, o_seg, o_hist, o_ka, o_kb, bytes, plan_bytes;
-    int64_t cap_keys;
+    size_t o_plan, o_fields, o_bctr, bytes, plan_bytes;
 };
 
-BatchLayout batch_layout(int count, int64_t cap_keys)
+BatchLayout batch_layout(int count)
 {
     BatchLayout L{};
     size_t off = 0;
@@ -142,36 +130,21 @@ BatchLayout batch_layout(int count, int64_t cap_keys)
     L.o_fields = take(sizeof(BatchField) * (size_t)count);
     L.plan_bytes = off;
     L.o_bctr = take(sizeof(uint32_t) * C_SLOTS);
-    L.o_seg = take(sizeof(uint32_t) * 3 * (size_t)(count + 1));
-    L.o_hist = take(sizeof(uint32_t) * (256 * kSortBlocks + 2 * kSortBlocks + 64));
-    L.cap_keys = cap_keys > 0 ? cap_keys : 1;
-    L.o_ka = take(sizeof(uint64_t) * (size_t)L.cap_keys);
-    L.o_kb = take(sizeof(uint64_t) * (size_t)L.cap_keys);
     L.bytes = off;
     return L;
 }
 
-eg_status batch_keys(int count, const int* ndims, const int64_t* dims, const eg_out* outs, int64_t* cap_keys,
-                     int* bits)
+eg_status batch_check(int count, const int* ndims, const int64_t* dims, const eg_out* outs)
 {
     if (count < 1 || !ndims || !dims || !outs) return EG_ERR_ARG;
-    int64_t keys = 0;
-    int b = 1;
     for (int i = 0; i < count; ++i) {
         Grid g;
         if (ndims[i] != 2 && ndims[i] != 3) return EG_ERR_ARG;
         if (!grid_from(ndims[i], dims + (size_t)i * EG_MAX_NDIM, &g))
             return too_large_or_arg(ndims[i], dims + (size_t)i * EG_MAX_NDIM);
         const eg_out& o = outs[i];
-        if (!caps_ok(o.cap_max, o.cap_sad, o.cap_pairs, o.cap_arc)) return EG_ERR_TOO_LARGE;
-        keys += o.cap_max + o.cap_sad + o.cap_pairs;
-        const int bi = id_bits(g.N);
-        if (bi > b) b = bi;
+        if (!caps_ok(o.cap_max, o.cap_sad, o.cap_arc)) return EG_ERR_TOO_LARGE;
     }
-    int fbits = id_bits(count);
-    if (fbits + 2 * b + 2 > 64 || keys >= (int64_t(1) << 32)) return EG_ERR_TOO_LARGE;
-    *cap_keys = keys;
-    *bits = b;
     return EG_OK;
 }
 
@@ -182,27 +155,23 @@ extern "C" {
 size_t eg_batch_plan_bytes(int count)
 {
     if (count < 1) return 0;
-    return batch_layout(count, 1).plan_bytes;
+    return batch_layout(count).plan_bytes;
 }
 
 size_t eg_batch_workspace_bytes(int count, const int* ndims, const int64_t* dims, const eg_out* outs)
 {
-    int64_t cap_keys;
-    int b;
-    if (batch_keys(count, ndims, dims, outs, &cap_keys, &b) != EG_OK) return 0;
-    return batch_layout(count, cap_keys).bytes;
+    if (batch_check(count, ndims, dims, outs) != EG_OK) return 0;
+    return batch_layout(count).bytes;
 }
 
 eg_status eg_batch_plan(int count, const float* const* fields, const int* ndims, const int64_t* dims,
                         const eg_out* outs, void* batch_ws, size_t batch_ws_bytes, void* host_plan,
                         size_t host_plan_bytes)
 {
-    int64_t cap_keys;
-    int b;
-    eg_status st = batch_keys(count, ndims, dims, outs, &cap_keys, &b);
+    eg_status st = batch_check(count, ndims, dims, outs);
     if (st != EG_OK) return st;
     if (!fields || !host_plan) return EG_ERR_ARG;
-    const BatchLayout L = batch_layout(count, cap_keys);
+    const BatchLayout L = batch_layout(count);
     if (host_plan_bytes < L.plan_bytes) return EG_ERR_ARG;
     if (!batch_ws || (reinterpret_cast<uintptr_t>(batch_ws) & 255u) || batch_ws_bytes < L.bytes)
         return EG_ERR_WORKSPACE;
@@ -212,14 +181,7 @@ eg_status eg_batch_plan(int count, const float* const* fields, const int* ndims,
     BatchField* F = (BatchField*)((char*)host_plan + L.o_fields);
     P->count = count;
     if (!decode_tuning(outs[0].tuning, &P->tuning)) return EG_ERR_ARG;
-    P->bits = b;
-    P->fbits = id_bits(count);
-    P->cap_keys = L.cap_keys;
     P->bctr = (uint32_t*)(dbase + L.o_bctr);
-    P->seg = (uint32_t*)(dbase + L.o_seg);
-    P->hist = (uint32_t*)(dbase + L.o_hist);
-    P->keysA = (uint64_t*)(dbase + L.o_ka);
-    P->keysB = (uint64_t*)(dbase + L.o_kb);
     P->fields = (BatchField*)(dbase + L.o_fields);
     P->dev = (const BatchPlan*)(dbase + L.o_plan);
     P->plan_bytes = (int64_t)L.plan_bytes;
@@ -234,7 +196,7 @@ eg_status eg_batch_plan(int count, const float* const* fields, const int* ndims,
         }
     }
     P->class_field[4] = count;
-    int64_t tiles = 0, quads = 0, sad = 0, exits = 0, maxs = 0;
+    int64_t tiles = 0, arc_blocks_total = 0;
     int cls = 0;
     for (int k = 0; k < count; ++k) {
         while (cls < 4 && P->class_field[cls + 1] <= k) {
@@ -247,33 +209,19 @@ eg_status eg_batch_plan(int count, const float* const* fields, const int* ndims,
         const eg_out& o = outs[i];
         st = check_one(fields[i], ndims[i], dims + (size_t)i * EG_MAX_NDIM, &o, &g, &w);
         if (st != EG_OK) return st;
-        if (o.cap_max < 1) return EG_ERR_ARG;
         int ty, tz;
         tile_shape(P->tuning, g.ndim, &ty, &tz);
         BatchField& B = F[k];
-        B.ta = tile_args(fields[i], g, o.labels, o.ptr, w, o.cap_max, o.cap_sad, ty, tz);
+        B.ta = tile_args(fields[i], g, o.labels, o.ptr, w, ty, tz);
+        B.arc = arc_args(fields[i], g, o, w);
         B.ndim = g.ndim;
         B.minima = (o.flags & EG_MINIMA) ? 1 : 0;
         B.N = g.N;
         B.tile_base = tiles;
-        B.quad_base = quads;
-        B.sad_base = sad;
-        B.exit_base = exits;
-        B.max_base = maxs;
+        B.arc_base = arc_blocks_total;
         B.exres = w.exres;
-        B.header = o.header;
-        B.maxima = o.maxima;
-        B.saddles = o.saddles;
-        B.beta = o.saddle_beta;
-        B.offsets = o.arc_offsets;
-        B.arcs = o.arc_maxima;
-        B.cap_arc = (uint32_t)o.cap_arc;
-        B.cap_keys = (uint32_t)(o.cap_max + o.cap_sad + o.cap_pairs);
         tiles += B.ta.ntiles;
-        quads += (g.N + 3) / 4;
-        sad += o.cap_sad;
-        exits += w.cap_exit;
-        maxs += o.cap_max;
+        arc_blocks_total += B.arc.arc_blocks;
     }
     while (cls < 4) {
         P->class_tile[cls + 1] = tiles;
@@ -281,10 +229,7 @@ eg_status eg_batch_plan(int count, const float* const* fields, const int* ndims,
     }
     P->class_tile[0] = 0;
     P->total_tiles = tiles;
-    P->total_quads = quads;
-    P->total_sad = sad;
-    P->total_exit = exits;
-    P->total_max = maxs;
+    P->total_arc_blocks = arc_blocks_total;
     return EG_OK;
 }
 
@@ -300,12 +245,12 @@ eg_status eg_build_batched(const void* host_plan, void* stream)
     return e == hipSuccess ? EG_OK : EG_ERR_HIP;
 }
 
-size_t eg_workspace_bytes(int ndim, const int64_t* dims, int64_t cap_max, int64_t cap_sad, int64_t cap_pairs)
+size_t eg_workspace_bytes(int ndim, const int64_t* dims, int64_t cap_sad)
 {
     Grid g;
     if (!grid_from(ndim, dims, &g)) return 0;
-    if (!caps_ok(cap_max, cap_sad, cap_pairs, 0)) return 0;
-    return carve(nullptr, g.N, cap_max, cap_sad, cap_pairs).bytes;
+    if (!caps_ok(0, cap_sad, 0)) return 0;
+    return carve(nullptr, g.N, g.dims[ndim - 1], cap_sad).bytes;
 }
 
 eg_status eg_build(const float* field, int ndim, const int64_t* dims, void* stream, const eg_out* out)

@@ -1,0 +1,547 @@
+// eg_arcs.hip -- stage (d) and the canonical outputs, for one field or a batch.
+//
+// Classification leaves the maxima and the saddles as two row-padded bitmasks.
+// Here:
+//   1. k_mask_count / k_scan_rows / k_mask_emit: an order-preserving
+//      compaction of each mask (block counts, their scan, then every block
+//      expands its words), so maxima[] and saddles[] come out in ascending
+//      vertex order without a sort;
+//   2. k_arc_count: for every saddle, the highest vertex of each upper-link
+//      component (UpperLinkRep, Sec. 3.4), the label it reaches, and the
+//      ascending distinct set of those labels: the saddle's arcs (arcs form
+//      a set, Sec. 2); the count and the first two arcs are kept;
+//   3. k_scan_rows / k_arc_write: the CSR offsets from a scan of the counts,
+//      then the arcs (saddles with more than two distinct arcs, rare, are
+//      recomputed rather than stored);
+//   4. k_finalize: status and counts into the header.
+// No step uses an atomic: every position comes from a scan, so results do
+// not depend on scheduling.
+//
+// Every kernel is written against a field selector: OneField (the field is
+// the kernel argument, blocks are blockIdx.x) or BatchFields (the plan lists
+// the fields; a flat grid is split over them in proportion to their size).
+#include "eg_internal.h"
+#include "eg_rows.h"
+
+namespace eg {
+
+template <int NDIM>
+struct AdjTable {
+    uint64_t adj[Rows<NDIM>::K];
+};
+template <int NDIM>
+constexpr AdjTable<NDIM> make_adj()
+{
+    constexpr Rows<NDIM> r = make_rows_ce<NDIM>();
+    AdjTable<NDIM> t{};
+    for (int j = 0; j < Rows<NDIM>::K; ++j) t.adj[j] = r.adj[j];
+    return t;
+}
+__constant__ AdjTable<1> c_adj1 = make_adj<1>();
+__constant__ AdjTable<2> c_adj2 = make_adj<2>();
+__constant__ AdjTable<3> c_adj3 = make_adj<3>();
+__constant__ AdjTable<4> c_adj4 = make_adj<4>();
+__constant__ AdjTable<5> c_adj5 = make_adj<5>();
+
+template <int NDIM>
+__device__ __forceinline__ const uint64_t* adj_table()
+{
+    if constexpr (NDIM == 1) return c_adj1.adj;
+    else if constexpr (NDIM == 2) return c_adj2.adj;
+    else if constexpr (NDIM == 3) return c_adj3.adj;
+    else if constexpr (NDIM == 4) return c_adj4.adj;
+    else return c_adj5.adj;
+}
+
+// ------------------------------------------------------------------ selectors
+
+struct OneField {
+    ArcArgs a;
+    // the field of this block, the block's index among the field's blocks and
+    // their number
+    __device__ __forceinline__ const ArcArgs& locate(uint32_t& blk, uint32_t& nb) const
+    {
+        blk = blockIdx.x;
+        nb = gridDim.x;
+        return a;
+    }
+    // kernels with one block per field
+    __device__ __forceinline__ const ArcArgs& field() const { return a; }
+};
+
+struct BatchFields {
+    const BatchPlan* plan;
+    __device__ __forceinline__ const ArcArgs& locate(uint32_t& blk, uint32_t& nb) const
+    {
+        const BatchField* fs = plan->fields;
+        const int64_t b = blockIdx.x;
+        int lo = 0, hi = plan->count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (fs[mid].arc_base <= b)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int f = __builtin_amdgcn_readfirstlane(lo);
+        blk = (uint32_t)(b - fs[f].arc_base);
+        nb = (uint32_t)fs[f].arc.arc_blocks;
+        return fs[f].arc;
+    }
+    __device__ __forceinline__ const ArcArgs& field() const { return plan->fields[blockIdx.x].arc; }
+};
+
+// ------------------------------------------------------------------ helpers
+
+// Contiguous chunk [lo, hi) of [0, n) for block blk of nb: whole rounds of
+// 256 items, so every block but the last has full rounds.
+__device__ __forceinline__ void chunk(uint32_t n, uint32_t nb, uint32_t blk, uint32_t& lo, uint32_t& hi)
+{
+    uint32_t per = (uint32_t)(((uint64_t)n + nb - 1u) / nb);
+    per = (per + 255u) & ~255u;
+    if (per == 0) per = 256u;
+    const uint64_t l = (uint64_t)blk * per;
+    lo = (uint32_t)(l < n ? l : n);
+    const uint64_t h = (uint64_t)lo + per;
+    hi = (uint32_t)(h < n ? h : n);
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
+{
+    const int lane = __lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan of x over the 256 threads of the block; total gets the sum.
+// Uses tmp[0..3]; every thread must call it.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* tmp, uint32_t& total)
+{
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const uint32_t inc = wave_incl_scan(x);
+    if (lane == 63) tmp[w] = inc;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int k = 0; k < w; ++k) pre += tmp[k];
+    total = tmp[0] + tmp[1] + tmp[2] + tmp[3];
+    __syncthreads();
+    return pre + inc - x;
+}
+
+__device__ __forceinline__ uint32_t block_sum(uint32_t x, uint32_t* tmp)
+{
+    uint32_t total;
+    block_excl_scan(x, tmp, total);
+    return total;
+}
+
+__device__ __forceinline__ uint32_t saddle_count(const ArcArgs& A)
+{
+    const uint32_t n = A.ctr[C_NSAD];
+    return n < A.cap_sad ? n : A.cap_sad;
+}
+
+// ------------------------------------------------------------------ masks
+
+template <class Sel>
+__global__ __launch_bounds__(256) void k_mask_count(Sel sel)
+{
+    __shared__ uint32_t tmp[4];
+    uint32_t blk, nb;
+    const ArcArgs& A = sel.locate(blk, nb);
+    uint32_t lo, hi;
+    chunk((uint32_t)A.words, nb, blk, lo, hi);
+    uint32_t cm = 0, cs = 0;
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) {
+        cm += (uint32_t)__popcll(A.mmask[i]);
+        cs += (uint32_t)__popcll(A.smask[i]);
+    }
+    cm = block_sum(cm, tmp);
+    cs = block_sum(cs, tmp);
+    if (threadIdx.x == 0) {
+        A.bsum[blk] = cm;
+        A.bsum[kArcBlocks + blk] = cs;
+    }
+}
+
+// Exclusive scan, in place, of rows `row` and `row + 1` of a field's block
+// counts (nb <= kArcBlocks entries each); the row totals go to the counter
+// slots.  One block of 1024 threads per field.
+template <class Sel>
+__global__ __launch_bounds__(1024) void k_scan_rows(Sel sel, int row, int slot0, int slot1)
+{
+    __shared__ uint32_t wsum[16];
+    const ArcArgs& A = sel.field();
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int nb = A.arc_blocks;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        uint32_t* a = A.bsum + (row + r) * kArcBlocks;
+        const uint32_t x = tid < nb ? a[tid] : 0u;
+        const uint32_t inc = wave_incl_scan(x);
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        if (w == 0) {
+            uint32_t y = lane < 16 ? wsum[lane] : 0u;
+            y = wave_incl_scan(y);
+            if (lane < 16) wsum[lane] = y;
+        }
+        __syncthreads();
+        const uint32_t ex = (w > 0 ? wsum[w - 1] : 0u) + inc - x;
+        if (tid < nb) a[tid] = ex;
+        if (tid == 0) A.ctr[r == 0 ? slot0 : slot1] = wsum[15];
+        __syncthreads();
+    }
+}
+
+template <class Sel>
+__global__ __launch_bounds__(256) void k_mask_emit(Sel sel)
+{
+    __shared__ uint32_t tmp[4];
+    uint32_t blk, nb;
+    const ArcArgs& A = sel.locate(blk, nb);
+    uint32_t lo, hi;
+    chunk((uint32_t)A.words, nb, blk, lo, hi);
+    uint32_t rm = A.bsum[blk], rs = A.bsum[kArcBlocks + blk];
+    const uint32_t XW = (uint32_t)A.XW, X = (uint32_t)A.X;
+    for (uint32_t base = lo; base < hi; base += 256) {
+        const uint32_t i = base + threadIdx.x;
+        uint64_t m = i < hi ? A.mmask[i] : 0ull;
+        uint64_t sd = i < hi ? A.smask[i] : 0ull;
+        uint32_t tm, ts;
+        uint32_t pm = rm + block_excl_scan((uint32_t)__popcll(m), tmp, tm);
+        uint32_t ps = rs + block_excl_scan((uint32_t)__popcll(sd), tmp, ts);
+        if (m | sd) {
+            const uint32_t row = i / XW, xw = i - row * XW;
+            const int32_t vbase = (int32_t)(row * X + xw * 64u);
+            while (m) {
+                const int b = __ffsll((unsigned long long)m) - 1;
+                m &= m - 1ull;
+                if (pm < A.cap_max) A.maxima[pm] = vbase + b;
+                ++pm;
+            }
+            while (sd) {
+                const int b = __ffsll((unsigned long long)sd) - 1;
+                sd &= sd - 1ull;
+                if (ps < A.cap_sad) A.saddles[ps] = vbase + b;
+                ++ps;
+            }
+        }
+        rm += tm;
+        rs += ts;
+    }
+}
+
+// ------------------------------------------------------------------ arcs
+
+// The arcs of saddle v (Sec. 3.4, UpperLinkRep): the upper link split into
+// its components (bit-parallel BFS over the link edges), the highest vertex of
+// each (scanned in the order in which the later of two equal vertices wins),
+// and the label of that vertex.  The distinct labels are kept ascending in
+// list[0], list[256], ... (this thread's LDS column, room for K entries).
+// Returns their number; beta gets the number of components.
+template <int NDIM, bool MINMODE>
+__device__ __forceinline__ int saddle_arcs(const ArcArgs& A, int v, const uint64_t* s_adj, uint32_t* list, int& beta)
+{
+    constexpr Rows<NDIM> R = make_rows_ce<NDIM>();
+    constexpr int K = Rows<NDIM>::K;
+    int c[NDIM], st[NDIM];
+    {
+        int rem = v, stride = 1;
+#pragma unroll
+        for (int i = NDIM - 1; i >= 0; --i) {
+            const int d = A.dims[i];
+            c[i] = rem % d;
+            rem /= d;
+            st[i] = stride;
+            stride *= d;
+        }
+    }
+    const uint32_t uv = mode_key<MINMODE>(A.f[v]);
+    uint32_t us[K];
+    int offs[K];
+    uint64_t up = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        bool in = true;
+        int off = 0;
+#pragma unroll
+        for (int i = 0; i < NDIM; ++i) {
+            const int d = R.d[j][i];
+            if (d != 0) {
+                in = in && (unsigned)(c[i] + d) < (unsigned)A.dims[i];
+                off += d * st[i];
+            }
+        }
+        offs[j] = off;
+        const uint32_t u = in ? mode_key<MINMODE>(A.f[v + off]) : 0u;  // 0: below every vertex
+        us[j] = u;
+        const bool wins_tie = (j >= K / 2) != MINMODE;
+        up |= uint64_t(wins_tie ? (u >= uv) : (u > uv)) << j;
+    }
+    int n = 0;
+    beta = 0;
+    for (uint64_t rem = up; rem;) {
+        const uint64_t comp = closure(rem & (~rem + 1), rem, s_adj);
+        rem &= ~comp;
+        ++beta;
+        uint32_t best_u = 0;
+        int best_off = 0;
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            const int j = MINMODE ? K - 1 - s : s;
+            if (((comp >> j) & 1ull) && us[j] >= best_u) {
+                best_u = us[j];
+                best_off = offs[j];
+            }
+        }
+        const uint32_t L = (uint32_t)A.lab[v + best_off];
+        int p = 0;
+        while (p < n && list[p * 256] < L) ++p;
+        if (p < n && list[p * 256] == L) continue;
+        for (int q = n; q > p; --q) list[q * 256] = list[(q - 1) * 256];
+        list[p * 256] = L;
+        ++n;
+    }
+    return n;
+}
+
+template <int NDIM>
+__device__ __forceinline__ void load_adj(uint64_t* s_adj)
+{
+    constexpr int K = Rows<NDIM>::K;
+    const uint64_t* t = adj_table<NDIM>();
+    for (int i = threadIdx.x; i < K; i += blockDim.x) s_adj[i] = t[i];
+    __syncthreads();
+}
+
+// Distinct-arc count, beta and the first two arcs of every saddle of the
+// block's chunk; the block's sums of both counts go to rows 2 and 3.
+template <int NDIM, bool MINMODE>
+__device__ __forceinline__ void arc_count_body(const ArcArgs& A, uint32_t blk, uint32_t nb, uint32_t* s_list,
+                                               uint64_t* s_adj, uint32_t* tmp)
+{
+    load_adj<NDIM>(s_adj);
+    uint32_t lo, hi;
+    chunk(saddle_count(A), nb, blk, lo, hi);
+    const int tid = threadIdx.x;
+    uint32_t sc = 0, sb = 0;
+    for (uint32_t i = lo + tid; i < hi; i += 256) {
+        int beta;
+        const int n = saddle_arcs<NDIM, MINMODE>(A, A.saddles[i], s_adj, s_list + tid, beta);
+        if (A.beta) A.beta[i] = beta;
+        A.offsets[i + 1] = n;  // the count until k_arc_write turns it into an offset
+        A.atmp[i] = make_uint2(s_list[tid], n > 1 ? s_list[256 + tid] : 0u);
+        sc += (uint32_t)n;
+        sb += (uint32_t)beta;
+    }
+    sc = block_sum(sc, tmp);
+    sb = block_sum(sb, tmp);
+    if (tid == 0) {
+        A.bsum[2 * kArcBlocks + blk] = sc;
+        A.bsum[3 * kArcBlocks + blk] = sb;
+    }
+}
+
+template <int NDIM, bool MINMODE>
+__device__ __forceinline__ void arc_write_body(const ArcArgs& A, uint32_t blk, uint32_t nb, uint32_t* s_list,
+                                               uint64_t* s_adj, uint32_t* tmp)
+{
+    load_adj<NDIM>(s_adj);
+    uint32_t lo, hi;
+    chunk(saddle_count(A), nb, blk, lo, hi);
+    const int tid = threadIdx.x;
+    if (blk == 0 && tid == 0) A.offsets[0] = 0;
+    uint32_t run = A.bsum[2 * kArcBlocks + blk];
+    for (uint32_t base = lo; base < hi; base += 256) {
+        const uint32_t i = base + tid;
+        const bool valid = i < hi;
+        const uint32_t n = valid ? (uint32_t)A.offsets[i + 1] : 0u;
+        uint32_t total;
+        const uint32_t pos = run + block_excl_scan(n, tmp, total);
+        if (valid) {
+            if (n <= 2) {
+                const uint2 t = A.atmp[i];
+                if (pos < A.cap_arc) A.arcs[pos] = (int32_t)t.x;
+                if (n == 2 && pos + 1 < A.cap_arc) A.arcs[pos + 1] = (int32_t)t.y;
+            } else {
+                int beta;
+                saddle_arcs<NDIM, MINMODE>(A, A.saddles[i], s_adj, s_list + tid, beta);
+                for (uint32_t k = 0; k < n; ++k)
+                    if (pos + k < A.cap_arc) A.arcs[pos + k] = (int32_t)s_list[k * 256 + tid];
+            }
+            A.offsets[i + 1] = (int32_t)(pos + n);
+        }
+        run += total;
+    }
+}
+
+template <int NDIM, bool MINMODE>
+__global__ __launch_bounds__(256) void k_arc_count(OneField sel)
+{
+    __shared__ uint32_t s_list[Rows<NDIM>::K * 256];
+    __shared__ uint64_t s_adj[Rows<NDIM>::K];
+    __shared__ uint32_t tmp[4];
+    uint32_t blk, nb;
+    const ArcArgs& A = sel.locate(blk, nb);
+    arc_count_body<NDIM, MINMODE>(A, blk, nb, s_list, s_adj, tmp);
+}
+
+template <int NDIM, bool MINMODE>
+__global__ __launch_bounds__(256) void k_arc_write(OneField sel)
+{
+    __shared__ uint32_t s_list[Rows<NDIM>::K * 256];
+    __shared__ uint64_t s_adj[Rows<NDIM>::K];
+    __shared__ uint32_t tmp[4];
+    uint32_t blk, nb;
+    const ArcArgs& A = sel.locate(blk, nb);
+    arc_write_body<NDIM, MINMODE>(A, blk, nb, s_list, s_adj, tmp);
+}
+
+// Batches hold 2D and 3D fields of either graph: the body is chosen per
+// field (a uniform branch).
+template <bool WRITE>
+__global__ __launch_bounds__(256) void k_arc_batched(BatchFields sel)
+{
+    __shared__ uint32_t s_list[14 * 256];
+    __shared__ uint64_t s_adj[14];
+    __shared__ uint32_t tmp[4];
+    uint32_t blk, nb;
+    const ArcArgs& A = sel.locate(blk, nb);
+    const int kind = __builtin_amdgcn_readfirstlane((A.ndim == 3 ? 2 : 0) + (A.minima ? 1 : 0));
+#define EG_BODY(ND, MM)                                                  \
+    if (WRITE)                                                           \
+        arc_write_body<ND, MM>(A, blk, nb, s_list, s_adj, tmp);          \
+    else                                                                 \
+        arc_count_body<ND, MM>(A, blk, nb, s_list, s_adj, tmp);
+    switch (kind) {
+        case 0: EG_BODY(2, false) break;
+        case 1: EG_BODY(2, true) break;
+        case 2: EG_BODY(3, false) break;
+        default: EG_BODY(3, true) break;
+    }
+#undef EG_BODY
+}
+
+// ------------------------------------------------------------------ header
+
+template <class Sel>
+__global__ void k_finalize(Sel sel)
+{
+    if (threadIdx.x != 0) return;
+    const ArcArgs& A = sel.field();
+    const uint32_t* c = A.ctr;
+    const int64_t nmax = c[C_NMAX], nsad = c[C_NSAD], narc = c[C_NARC];
+    const bool sad_over = nsad > A.cap_sad;
+    int status = EG_OK;
+    if (c[C_NAN])
+        status = EG_ERR_NAN;
+    else if (nmax > A.cap_max || sad_over || narc > A.cap_arc)
+        status = EG_ERR_CAPACITY;
+    int32_t* h = A.header;
+    h[EG_H_STATUS] = status;
+    h[EG_H_NMAX] = (int32_t)nmax;
+    h[EG_H_NSAD] = (int32_t)nsad;
+    // with saddles cut off at the capacity, the arc and pair totals cover
+    // only the first cap_sad saddles: unknown
+    h[EG_H_NARC] = sad_over ? -1 : (int32_t)narc;
+    h[EG_H_NPAIRS] = sad_over ? -1 : (int32_t)c[C_NPAIRS];
+    h[EG_H_PASSES] = (int32_t)c[C_PASSES];
+    h[EG_H_EXITS] = (int32_t)c[C_NEXIT];
+}
+
+// ------------------------------------------------------------------ launchers
+
+// Blocks per field of the stage (d) kernels: one per 32768 vertices.
+uint32_t arc_blocks(int64_t N)
+{
+    const int64_t b = (N + 32767) / 32768;
+    return (uint32_t)(b < 1 ? 1 : b > kArcBlocks ? kArcBlocks : b);
+}
+
+ArcArgs arc_args(const float* f, const Grid& g, const eg_out& o, const Work& w)
+{
+    ArcArgs a{};
+    a.f = f;
+    a.lab = o.labels;
+    a.mmask = w.mmask;
+    a.smask = w.smask;
+    a.bsum = w.bsum;
+    a.atmp = w.atmp;
+    a.ctr = w.ctr;
+    a.header = o.header;
+    a.maxima = o.maxima;
+    a.saddles = o.saddles;
+    a.beta = o.saddle_beta;
+    a.offsets = o.arc_offsets;
+    a.arcs = o.arc_maxima;
+    a.ndim = g.ndim;
+    a.minima = (o.flags & EG_MINIMA) ? 1 : 0;
+    a.N = g.N;
+    a.X = g.dims[g.ndim - 1];
+    a.XW = (a.X + 63) / 64;
+    a.words = (int32_t)w.words;
+    for (int i = 0; i < EG_MAX_NDIM; ++i) a.dims[i] = i < g.ndim ? g.dims[i] : 1;
+    a.cap_max = (uint32_t)o.cap_max;
+    a.cap_sad = (uint32_t)o.cap_sad;
+    a.cap_arc = (uint32_t)o.cap_arc;
+    a.arc_blocks = (int32_t)arc_blocks(g.N);
+    return a;
+}
+
+template <int NDIM, bool MINMODE>
+static void launch_arc_pair(const OneField& sel, uint32_t nb, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_arc_count<NDIM, MINMODE>), dim3(nb), dim3(256), 0, s, sel);
+    hipLaunchKernelGGL(k_scan_rows<OneField>, dim3(1), dim3(1024), 0, s, sel, 2, (int)C_NARC, (int)C_NPAIRS);
+    hipLaunchKernelGGL((k_arc_write<NDIM, MINMODE>), dim3(nb), dim3(256), 0, s, sel);
+}
+
+hipError_t launch_arcs(const ArcArgs& a, hipStream_t s)
+{
+    const OneField sel{a};
+    const uint32_t nb = (uint32_t)a.arc_blocks;
+    hipLaunchKernelGGL(k_mask_count<OneField>, dim3(nb), dim3(256), 0, s, sel);
+    hipLaunchKernelGGL(k_scan_rows<OneField>, dim3(1), dim3(1024), 0, s, sel, 0, (int)C_NMAX, (int)C_NSAD);
+    hipLaunchKernelGGL(k_mask_emit<OneField>, dim3(nb), dim3(256), 0, s, sel);
+#define EG_CASE(N)                                  \
+    case N:                                         \
+        if (a.minima)                               \
+            launch_arc_pair<N, true>(sel, nb, s);   \
+        else                                        \
+            launch_arc_pair<N, false>(sel, nb, s);  \
+        break;
+    switch (a.ndim) {
+        EG_CASE(1)
+        EG_CASE(2)
+        EG_CASE(3)
+        EG_CASE(4)
+        EG_CASE(5)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef EG_CASE
+    hipLaunchKernelGGL(k_finalize<OneField>, dim3(1), dim3(64), 0, s, sel);
+    return hipGetLastError();
+}
+
+hipError_t launch_arcs_batched(const BatchPlan* dplan, const BatchPlan& hplan, hipStream_t s)
+{
+    const BatchFields sel{dplan};
+    const unsigned grid = (unsigned)hplan.total_arc_blocks;
+    const unsigned count = (unsigned)hplan.count;
+    hipLaunchKernelGGL(k_mask_count<BatchFields>, dim3(grid), dim3(256), 0, s, sel);
+    hipLaunchKernelGGL(k_scan_rows<BatchFields>, dim3(count), dim3(1024), 0, s, sel, 0, (int)C_NMAX, (int)C_NSAD);
+    hipLaunchKernelGGL(k_mask_emit<BatchFields>, dim3(grid), dim3(256), 0, s, sel);
+    hipLaunchKernelGGL(k_arc_batched<false>, dim3(grid), dim3(256), 0, s, sel);
+    hipLaunchKernelGGL(k_scan_rows<BatchFields>, dim3(count), dim3(1024), 0, s, sel, 2, (int)C_NARC, (int)C_NPAIRS);
+    hipLaunchKernelGGL(k_arc_batched<true>, dim3(grid), dim3(256), 0, s, sel);
+    hipLaunchKernelGGL(k_finalize<BatchFields>, dim3(count), dim3(64), 0, s, sel);
+    return hipGetLastError();
+}
+
+}  // namespace eg

@@ -7,10 +7,6 @@
 //   components, Table 1) with a bit-parallel BFS over the link edges.
 // k_exit_*, k_final  stage (b): pointer jumping until every vertex names its
 //   maximum (the end of the walk of Alg. 2).
-// k_reps  stage (d), first half: for every saddle, the highest vertex of each
-//   upper-link component (UpperLinkRep, Sec. 3.4) and the label it reaches,
-//   emitted as sortable (saddle, maximum) keys plus one marker per saddle
-//   that carries its component count.
 #include "eg_internal.h"
 
 namespace eg {
@@ -85,12 +81,39 @@ __device__ __forceinline__ uint32_t boundary_bits(const Grid& g, int v)
     return bits;
 }
 
+__global__ __launch_bounds__(256) void k_zero_words(uint64_t* __restrict__ a, uint64_t* __restrict__ b, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        a[i] = 0;
+        b[i] = 0;
+    }
+}
+
+// OR the bits of the lanes with `pred` into the row-padded mask: lanes that
+// share a word form a run of consecutive lanes (consecutive x), and the first
+// lane of each run writes the run's bits with one atomic.  Words are shared
+// only by the runs at either end of a wave, so atomics rarely meet.
+__device__ __forceinline__ void mask_or(bool pred, int64_t word, int bit, uint64_t* __restrict__ mask)
+{
+    const uint64_t b = __ballot(pred);
+    if (b == 0) return;
+    const int lane = __lane_id();
+    const int64_t prev = __shfl_up(word, 1);
+    const bool lead = lane == 0 || prev != word;
+    const uint64_t leads = __ballot(lead);
+    const uint64_t later = lane == 63 ? 0ull : (leads >> (lane + 1)) << (lane + 1);
+    const int next = later ? __ffsll((unsigned long long)later) - 1 : 64;
+    const int len = next - lane;
+    const uint64_t run = len >= 64 ? ~0ull : ((1ull << len) - 1ull);
+    const uint64_t bits = ((b >> lane) & run) << bit;
+    if (lead && word >= 0 && bits) atomicOr((unsigned long long*)&mask[word], (unsigned long long)bits);
+}
+
 template <int NDIM, bool MINMODE>
 __global__ __launch_bounds__(256) void k_classify_generic(const float* __restrict__ f, Grid g, LinkTable t,
                                                           int32_t* __restrict__ lab, int32_t* __restrict__ ptr,
-                                                          uint32_t* __restrict__ ctr, uint32_t* __restrict__ umax,
-                                                          uint32_t cap_max, uint32_t* __restrict__ usad,
-                                                          uint32_t cap_sad)
+                                                          uint32_t* __restrict__ ctr, uint64_t* __restrict__ mmask,
+                                                          uint64_t* __restrict__ smask)
 {
     constexpr int K = 2 * ((1 << NDIM) - 1);
     __shared__ uint64_t s_adj[K];
@@ -112,32 +135,37 @@ __global__ __launch_bounds__(256) void k_classify_generic(const float* __restric
         lab[v] = is_max ? v : -(best + 1);  // final label, or "same as best"
         if (ptr) ptr[v] = best;
     }
-    wave_append(is_max, (uint32_t)v, &ctr[C_NMAX], umax, cap_max);
-    wave_append(is_sad, (uint32_t)v, &ctr[C_NSAD], usad, cap_sad);
+    // this vertex's bit in the row-padded masks (rows run along the last axis)
+    const int X = g.dims[NDIM - 1];
+    const int row = v / X, x = v - row * X;
+    const int64_t word = v < g.N ? (int64_t)row * ((X + 63) >> 6) + (x >> 6) : -1;
+    mask_or(is_max, word, x & 63, mmask);
+    mask_or(is_sad, word, x & 63, smask);
     if (__ballot(nan) != 0 && __lane_id() == 0) atomicOr(&ctr[C_NAN], 1u);
 }
 
 template <int NDIM, bool MINMODE>
 static void launch_classify_t(const float* f, const Grid& g, const LinkTable& t, int32_t* lab, int32_t* ptr,
-                              const Work& w, int64_t cap_max, int64_t cap_sad, hipStream_t s)
+                              const Work& w, hipStream_t s)
 {
+    const int64_t zwant = (w.words + 255) / 256;
+    const int zblocks = (int)(zwant < 4096 ? (zwant > 0 ? zwant : 1) : 4096);
+    hipLaunchKernelGGL(k_zero_words, dim3(zblocks), dim3(256), 0, s, w.mmask, w.smask, w.words);
     const int blocks = (int)((g.N + 255) / 256);
     hipLaunchKernelGGL((k_classify_generic<NDIM, MINMODE>), dim3(blocks), dim3(256), 0, s, f, g, t, lab, ptr, w.ctr,
-                       w.umax, (uint32_t)cap_max, w.usad, (uint32_t)cap_sad);
+                       w.mmask, w.smask);
 }
 
 hipError_t launch_classify(const float* f, const Grid& g, const LinkTable& t, bool minima, int32_t* lab,
-                           int32_t* ptr, const Work& w, int64_t cap_max, int64_t cap_sad, const Tuning& tu,
-                           hipStream_t s)
+                           int32_t* ptr, const Work& w, const Tuning& tu, hipStream_t s)
 {
-    if (g.ndim == 2 || g.ndim == 3)
-        return launch_classify_tiled(f, g, minima, lab, ptr, w, cap_max, cap_sad, tu, s);
-#define EG_CASE(N)                                                                  \
-    case N:                                                                         \
-        if (minima)                                                                 \
-            launch_classify_t<N, true>(f, g, t, lab, ptr, w, cap_max, cap_sad, s);  \
-        else                                                                        \
-            launch_classify_t<N, false>(f, g, t, lab, ptr, w, cap_max, cap_sad, s); \
+    if (g.ndim == 2 || g.ndim == 3) return launch_classify_tiled(f, g, minima, lab, ptr, w, tu, s);
+#define EG_CASE(N)                                                \
+    case N:                                                       \
+        if (minima)                                               \
+            launch_classify_t<N, true>(f, g, t, lab, ptr, w, s);  \
+        else                                                      \
+            launch_classify_t<N, false>(f, g, t, lab, ptr, w, s); \
         break;
     switch (g.ndim) {
         EG_CASE(1)
@@ -273,132 +301,6 @@ hipError_t launch_labels(const Grid& g, int32_t* lab, const Work& w, const Tunin
     }
     for (; p < tu.passes; ++p)
         hipLaunchKernelGGL(k_final, dim3(blocks), dim3(256), 0, s, lab, w.exres, N, w.ctr, p, tu.hops);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ saddle reps
-
-
-template <int NDIM, bool MINMODE>
-__global__ __launch_bounds__(256) void k_reps(const float* __restrict__ f, Grid g, LinkTable t,
-                                              const int32_t* __restrict__ lab, const uint32_t* __restrict__ usad,
-                                              uint32_t* __restrict__ ctr, uint32_t cap_sad,
-                                              uint64_t* __restrict__ keys, uint32_t cap_keys, int b)
-{
-    constexpr int K = 2 * ((1 << NDIM) - 1);
-    __shared__ uint64_t s_adj[K];
-    __shared__ int32_t s_lin[K];
-    for (int i = threadIdx.x; i < K; i += blockDim.x) {
-        s_adj[i] = t.adj[i];
-        s_lin[i] = t.lin[i];
-    }
-    __syncthreads();
-    const uint32_t nraw = __hip_atomic_load(&ctr[C_NSAD], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t n = nraw < cap_sad ? nraw : cap_sad;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const int v = (int)usad[i];
-        const uint32_t bits = boundary_bits<NDIM>(g, v);
-        const uint32_t uv = mode_key<MINMODE>(f[v]);
-        uint64_t up = 0;
-        int best;
-        scan_neighbourhood<NDIM, MINMODE>(f, t, v, bits, uv, up, best);
-        int beta = 0;
-        for (uint64_t rem = up; rem;) {
-            rem &= ~closure(rem & (~rem + 1), rem, s_adj);
-            ++beta;
-        }
-        const uint32_t base = atomicAdd(&ctr[C_NKEYS], (uint32_t)(beta + 1));
-        uint32_t q = base;
-        for (uint64_t rem = up; rem;) {
-            const uint64_t c = closure(rem & (~rem + 1), rem, s_adj);
-            rem &= ~c;
-            // highest vertex of the component: scan it in tie-winning order
-            uint32_t best_u = 0;
-            int rep = v;
-            for (uint64_t x = c; x;) {
-                int j;
-                if (!MINMODE) {
-                    j = __ffsll((unsigned long long)x) - 1;
-                } else {
-                    j = 63 - __clzll((long long)x);
-                }
-                x &= ~(uint64_t(1) << j);
-                const int u_id = v + s_lin[j];
-                const uint32_t u = mode_key<MINMODE>(f[u_id]);
-                if (u >= best_u) {
-                    best_u = u;
-                    rep = u_id;
-                }
-            }
-            if (q < cap_keys) keys[q] = saddle_key((uint32_t)v, (uint32_t)lab[rep], 0u, b);
-            ++q;
-        }
-        if (q < cap_keys) keys[q] = saddle_key((uint32_t)v, (uint32_t)beta, 1u, b);
-    }
-}
-
-template <int NDIM, bool MINMODE>
-static void launch_reps_t(const float* f, const Grid& g, const LinkTable& t, const int32_t* lab, const Work& w,
-                          int64_t cap_sad, int bits, hipStream_t s)
-{
-    int64_t want = (cap_sad + 255) / 256;
-    const int blocks = (int)(want < 4096 ? (want > 0 ? want : 1) : 4096);
-    hipLaunchKernelGGL((k_reps<NDIM, MINMODE>), dim3(blocks), dim3(256), 0, s, f, g, t, lab, w.usad, w.ctr,
-                       (uint32_t)cap_sad, w.keysA, (uint32_t)w.cap_keys, bits);
-}
-
-hipError_t launch_reps(const float* f, const Grid& g, const LinkTable& t, bool minima, const int32_t* lab,
-                       const Work& w, int64_t cap_sad, int bits, hipStream_t s)
-{
-#define EG_CASE(N)                                                            \
-    case N:                                                                   \
-        if (minima)                                                           \
-            launch_reps_t<N, true>(f, g, t, lab, w, cap_sad, bits, s);        \
-        else                                                                  \
-            launch_reps_t<N, false>(f, g, t, lab, w, cap_sad, bits, s);       \
-        break;
-    switch (g.ndim) {
-        EG_CASE(1)
-        EG_CASE(2)
-        EG_CASE(3)
-        EG_CASE(4)
-        EG_CASE(5)
-        default:
-            return hipErrorInvalidValue;
-    }
-#undef EG_CASE
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ finalize
-
-__global__ void k_finalize(const uint32_t* __restrict__ ctr, int32_t* __restrict__ header, int64_t cap_max,
-                           int64_t cap_sad, int64_t cap_keys, int64_t cap_arc)
-{
-    if (threadIdx.x != 0) return;
-    const int64_t nmax = ctr[C_NMAX], nsad = ctr[C_NSAD], nkeys = ctr[C_NKEYS], narc = ctr[C_NARC];
-    const bool sad_over = nsad > cap_sad;
-    const bool keys_over = nkeys > cap_keys;
-    const int64_t nmax_keys = nmax < cap_max ? nmax : cap_max;
-    int status = EG_OK;
-    if (ctr[C_NAN])
-        status = EG_ERR_NAN;
-    else if (nmax > cap_max || sad_over || keys_over || narc > cap_arc)
-        status = EG_ERR_CAPACITY;
-    header[EG_H_STATUS] = status;
-    header[EG_H_NMAX] = (int32_t)nmax;
-    header[EG_H_NSAD] = (int32_t)nsad;
-    header[EG_H_NARC] = (sad_over || keys_over) ? -1 : (int32_t)narc;
-    header[EG_H_NPAIRS] = sad_over ? -1 : (int32_t)(nkeys - nsad - nmax_keys);
-    header[EG_H_PASSES] = (int32_t)ctr[C_PASSES];
-    header[EG_H_EXITS] = (int32_t)ctr[C_NEXIT];
-}
-
-hipError_t launch_finalize(const Work& w, const eg_out& o, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, w.ctr, o.header, o.cap_max, o.cap_sad, w.cap_keys,
-                       o.cap_arc);
     return hipGetLastError();
 }
 

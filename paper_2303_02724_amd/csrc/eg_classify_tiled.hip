@@ -150,6 +150,27 @@ __device__ __forceinline__ void alloc_exits(int (&cur)[VPT], uint32_t* s_tmp, ui
     }
 }
 
+// Critical-vertex bitmasks: each wave handles one 64-vertex row segment of
+// the tile per step, which is exactly one mask word (tiles start at
+// multiples of 64 along x).  Step k parks its maxima word in lane k and its
+// saddle word in lane 32 + k; at the end every lane stores at most one word,
+// so the masks cost one store instruction per wave and no atomics.
+__device__ __forceinline__ void park_word(uint64_t& mine, bool pred, int lane)
+{
+    const uint64_t b = __ballot(pred);
+    if (__lane_id() == lane) mine = b;
+}
+
+__device__ __forceinline__ void store_words(const TileArgs& a, uint64_t word, int vpt, int row, bool row_in, int tx)
+{
+    // row: the grid row (gz * Y + gy) of this lane's step; row_in: it exists
+    const int lane = __lane_id();
+    if ((lane & 31) < vpt && row_in) {
+        const int64_t at = (int64_t)row * a.tiles_x + tx;
+        (lane < 32 ? a.mmask : a.smask)[at] = word;
+    }
+}
+
 template <int NDIM, bool MINMODE, int TY, int TZ>
 __device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u, int32_t* s_nxt, uint32_t* s_conn,
                                         uint32_t* s_tmp)
@@ -213,7 +234,9 @@ __device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u,
     __syncthreads();
 
     constexpr uint64_t CONN2 = make_conn2();
+    static_assert(VPT <= 32, "one mask word per lane");
     int nxt[VPT];
+    uint64_t word = 0;  // this lane's parked mask word
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
         const int ly = wv + 4 * (k % YPT);
@@ -277,8 +300,13 @@ __device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u,
             if (ptr) ptr[v] = pv;
         }
         nxt[k] = n;
-        wave_append(is_max, (uint32_t)v, &ctr[C_NMAX], a.umax, a.cap_max);
-        wave_append(is_sad, (uint32_t)v, &ctr[C_NSAD], a.usad, a.cap_sad);
+        park_word(word, is_max, k);
+        park_word(word, is_sad, 32 + k);
+    }
+    {
+        const int k = __lane_id() & 31;
+        const int ly = wv + 4 * (k % YPT), lz = k / YPT;
+        store_words(a, word, VPT, (z0 + lz) * Y + y0 + ly, y0 + ly < Y && z0 + lz < Z, tx);
     }
     if (__ballot(nan) != 0 && __lane_id() == 0) atomicOr(&ctr[C_NAN], 1u);
     const int N = X * Y * Z;
@@ -420,7 +448,9 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
     }
     __syncthreads();
 
+    static_assert(VPT <= 32, "one mask word per lane");
     int nxt[VPT];
+    uint64_t word = 0;  // this lane's parked mask word
 #pragma unroll
     for (int c = 0; c < YPT; ++c) {
         const int ly = wv + 4 * c;
@@ -494,9 +524,14 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
                 if (ptr) ptr[v] = pv;
             }
             nxt[c * TZ + lz] = n;
-            wave_append(is_max, (uint32_t)v, &ctr[C_NMAX], a.umax, a.cap_max);
-            wave_append(is_sad, (uint32_t)v, &ctr[C_NSAD], a.usad, a.cap_sad);
+            park_word(word, is_max, c * TZ + lz);
+            park_word(word, is_sad, 32 + c * TZ + lz);
         }
+    }
+    {
+        const int k = __lane_id() & 31;
+        const int ly = wv + 4 * (k / TZ), lz = k % TZ;
+        store_words(a, word, VPT, (z0 + lz) * Y + y0 + ly, y0 + ly < Y && z0 + lz < Z, tx);
     }
     if (__ballot(nan) != 0 && __lane_id() == 0) atomicOr(&ctr[C_NAN], 1u);
     alloc_exits<VPT>(nxt, s_tmp, ctr, a.exits, a.cap_exit, X * Y * Z);  // has barriers: the halo is no longer read
@@ -600,16 +635,15 @@ __global__ __launch_bounds__(256) void k_classify2d(TileArgs a)
     tile_nd<2, MINMODE, TY, 1>(a, xcd_tile(blockIdx.x, a.ntiles), s_u, s_nxt, nullptr, s_tmp);
 }
 
-TileArgs tile_args(const float* f, const Grid& g, int32_t* lab, int32_t* ptr, const Work& w, int64_t cap_max,
-                   int64_t cap_sad, int ty, int tz)
+TileArgs tile_args(const float* f, const Grid& g, int32_t* lab, int32_t* ptr, const Work& w, int ty, int tz)
 {
     TileArgs a{};
     a.f = f;
     a.lab = lab;
     a.ptr = ptr;
     a.ctr = w.ctr;
-    a.umax = w.umax;
-    a.usad = w.usad;
+    a.mmask = w.mmask;
+    a.smask = w.smask;
     a.exits = w.exits;
     a.X = g.dims[g.ndim - 1];
     a.Y = g.dims[g.ndim - 2];
@@ -618,8 +652,6 @@ TileArgs tile_args(const float* f, const Grid& g, int32_t* lab, int32_t* ptr, co
     a.tiles_y = (a.Y + ty - 1) / ty;
     const int tiles_z = (a.Z + tz - 1) / tz;
     a.ntiles = a.tiles_x * a.tiles_y * tiles_z;
-    a.cap_max = (uint32_t)cap_max;
-    a.cap_sad = (uint32_t)cap_sad;
     a.cap_exit = (uint32_t)w.cap_exit;
     return a;
 }
@@ -713,7 +745,7 @@ hipError_t launch_final_tiled(const Grid& g, int32_t* lab, const Work& w, const 
 {
     int ty, tz;
     tile_shape(tu, g.ndim, &ty, &tz);
-    const TileArgs a = tile_args(nullptr, g, lab, nullptr, w, 0, 0, ty, tz);
+    const TileArgs a = tile_args(nullptr, g, lab, nullptr, w, ty, tz);
     if (g.ndim == 3) {
         if (tu.tile3 == 1)
             hipLaunchKernelGGL((k_final_tiled<4, 16>), dim3(a.ntiles), dim3(256), 0, s, a, w.exres, tu.hops, flag_slot);
@@ -733,11 +765,11 @@ hipError_t launch_final_tiled(const Grid& g, int32_t* lab, const Work& w, const 
 }
 
 hipError_t launch_classify_tiled(const float* f, const Grid& g, bool minima, int32_t* lab, int32_t* ptr,
-                                 const Work& w, int64_t cap_max, int64_t cap_sad, const Tuning& tu, hipStream_t s)
+                                 const Work& w, const Tuning& tu, hipStream_t s)
 {
     int ty, tz;
     tile_shape(tu, g.ndim, &ty, &tz);
-    const TileArgs a = tile_args(f, g, lab, ptr, w, cap_max, cap_sad, ty, tz);
+    const TileArgs a = tile_args(f, g, lab, ptr, w, ty, tz);
     if (g.ndim == 3) {
         if (tu.tile3 == 1)
             launch_3d<4, 16>(a, minima, s);

@@ -25,10 +25,7 @@ namespace eg {
 constexpr int kMaxNb = 62;          // 2(2^5 - 1)
 constexpr int kJumpHops = 64;       // default links per pointer-jumping pass
 constexpr int kMaxPasses = 8;       // flag slots per pass sequence
-constexpr int kSortBlocks = 256;    // grid of the radix-sort kernels
-constexpr int kSortThreads = 256;
-constexpr int kRadixBits = 8;
-constexpr uint32_t kMinTilesPerBlock = 8;  // sort/CSR: 2048 keys per block at least
+constexpr int kArcBlocks = 1024;    // most blocks per field of the stage (d) kernels
 constexpr int kTile3Y = 8, kTile3Z = 8;  // default 3D tile: 64 x 8 x 8 vertices
 constexpr int kTile2Y = 32;             // default 2D tile: 64 x 32 vertices
 
@@ -58,9 +55,8 @@ enum : int {
     C_NAN = 0,
     C_NMAX = 1,
     C_NSAD = 2,
-    C_NKEYS = 3,
+    C_NPAIRS = 3,
     C_NARC = 4,
-    C_NSADF = 5,
     C_PASSES = 6,
     C_NEXIT = 7,  // exit-list entries requested by the tiles
     C_JUMP = 8,   // kMaxPasses "not converged" flags of the exit-list passes
@@ -82,17 +78,24 @@ struct Grid {
     int32_t dims[EG_MAX_NDIM];
 };
 
+// Critical vertices between classification and stage (d) are kept as two
+// bitmasks (maxima, saddles) in a row-padded layout: the grid is cut into
+// rows along its fastest axis (X vertices each), every row takes XW =
+// ceil(X / 64) 64-bit words, and vertex (row, x) is bit x % 64 of word
+// row * XW + x / 64.  A wave of a 64-wide tile writes exactly one word per
+// row, and a scan over the words lists the vertices in ascending order.
+inline int64_t mask_words(int64_t N, int64_t X) { return (N / X) * ((X + 63) / 64); }
+
 // Carved workspace.
 struct Work {
     uint32_t* ctr;    // [C_SLOTS]
-    uint32_t* umax;   // [cap_max] maxima in discovery order
-    uint32_t* usad;   // [cap_sad] saddles in discovery order
-    uint64_t* keysA;  // [cap_keys]
-    uint64_t* keysB;  // [cap_keys]
-    uint32_t* hist;   // [256 * kSortBlocks + 2 * kSortBlocks + 64]
+    uint64_t* mmask;  // [words] maxima
+    uint64_t* smask;  // [words] saddles
+    uint32_t* bsum;   // [4 * kArcBlocks] per-block counts of stage (d)
+    uint2* atmp;      // [cap_sad] the first two arcs of every saddle
     uint32_t* exits;  // [cap_exit] exit vertices published by the tiles
     int32_t* exres;   // [cap_exit] their labels while being resolved
-    int64_t cap_keys;
+    int64_t words;
     int64_t cap_exit;
     size_t bytes;
 };
@@ -103,47 +106,55 @@ struct TileArgs {
     int32_t* lab;
     int32_t* ptr;
     uint32_t* ctr;
-    uint32_t* umax;
-    uint32_t* usad;
+    uint64_t* mmask;
+    uint64_t* smask;
     uint32_t* exits;
     int32_t X, Y, Z, tiles_x, tiles_y, ntiles;
-    uint32_t cap_max, cap_sad, cap_exit;
+    uint32_t cap_exit, pad0;
+};
+
+// Everything stage (d) needs to know about its field.
+struct ArcArgs {
+    const float* f;
+    const int32_t* lab;
+    const uint64_t* mmask;
+    const uint64_t* smask;
+    uint32_t* bsum;
+    uint2* atmp;
+    uint32_t* ctr;
+    int32_t* header;
+    int32_t* maxima;
+    int32_t* saddles;
+    int32_t* beta;     // may be null
+    int32_t* offsets;
+    int32_t* arcs;
+    int32_t ndim, minima, N, X, XW, words;
+    int32_t dims[EG_MAX_NDIM];
+    uint32_t cap_max, cap_sad, cap_arc;
+    int32_t arc_blocks;  // blocks of this field in the stage (d) kernels (<= kArcBlocks)
 };
 
 // One field of a batch (device-resident plan, built on the host).
 struct BatchField {
     TileArgs ta;
+    ArcArgs arc;
     int32_t ndim, minima, N, pad0;
     int64_t tile_base;   // exclusive prefix over fields of tiles
-    int64_t quad_base;   // ... of label quads, ceil(N / 4)
-    int64_t sad_base;    // ... of saddle capacities
-    int64_t exit_base;   // ... of exit-list capacities
-    int64_t max_base;    // ... of maxima capacities
+    int64_t arc_base;    // ... of stage (d) blocks
     int32_t* exres;
-    int32_t* header;
-    int32_t* maxima;
-    int32_t* saddles;
-    int32_t* beta;
-    int32_t* offsets;
-    int32_t* arcs;
-    uint32_t cap_arc, cap_keys;
 };
 
 struct BatchPlan {
-    int32_t count, bits, fbits, pad0;
+    int32_t count, pad0;
     Tuning tuning;
-    int64_t total_tiles, total_quads, total_sad, total_exit, total_max, cap_keys;
+    int64_t total_tiles, total_arc_blocks;
     // fields are ordered by class (2D max, 2D min, 3D max, 3D min); class c
     // owns fields [class_field[c], class_field[c + 1]) and tiles
     // [class_tile[c], class_tile[c + 1])
     int32_t class_field[5];
     int32_t pad1;
     int64_t class_tile[5];
-    uint32_t* bctr;       // [C_SLOTS] batch counters
-    uint64_t* keysA;      // [cap_keys]
-    uint64_t* keysB;
-    uint32_t* hist;       // [256 * kSortBlocks + 2 * kSortBlocks + 64]
-    uint32_t* seg;        // [3 * (count + 1)]: per field, first key index, arc rank, saddle rank
+    uint32_t* bctr;       // [C_SLOTS] batch counters (label pass flags)
     BatchField* fields;   // device address of fields[] (right after this header)
     const BatchPlan* dev; // device address of this plan (start of the batch workspace)
     int64_t plan_bytes;
@@ -155,7 +166,7 @@ int make_rows(int ndim, int8_t (*off)[EG_MAX_NDIM], uint64_t* adj);
 void make_table(const Grid& g, LinkTable* t);
 // Host: carve (or size, when base == nullptr) the workspace of a grid with N
 // vertices.
-Work carve(void* base, int64_t N, int64_t cap_max, int64_t cap_sad, int64_t cap_pairs);
+Work carve(void* base, int64_t N, int64_t X, int64_t cap_sad);
 // Exit-list capacity for a grid of N vertices (label codes need N + cap < 2^31).
 int64_t exit_capacity(int64_t N);
 // Bits needed to hold any vertex id of a grid with N vertices.
@@ -205,24 +216,6 @@ __device__ __forceinline__ bool row_wins_tie(int j, int k)
     return (j >= k / 2) != MINMODE;
 }
 
-// Wave-aggregated append of `val` to list[counter++] for lanes with pred.
-// Must be called by all lanes of the wave together.
-__device__ __forceinline__ void wave_append(bool pred, uint32_t val, uint32_t* counter, uint32_t* list,
-                                            uint32_t cap)
-{
-    uint64_t m = __ballot(pred);
-    if (m == 0) return;
-    const int lane = __lane_id();
-    const int leader = __ffsll((unsigned long long)m) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
-    base = __shfl(base, leader);
-    if (pred) {
-        uint32_t pos = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-        if (pos < cap) list[pos] = val;
-    }
-}
-
 // Component of `seed` inside `mask` (BFS over link edges, bit-parallel).
 __device__ __forceinline__ uint64_t closure(uint64_t seed, uint64_t mask, const uint64_t* adj)
 {
@@ -241,25 +234,15 @@ __device__ __forceinline__ uint64_t closure(uint64_t seed, uint64_t mask, const 
 
 hipError_t launch_init(uint32_t* ctr, int32_t* header, hipStream_t s);
 hipError_t launch_classify(const float* f, const Grid& g, const LinkTable& t, bool minima, int32_t* lab,
-                           int32_t* ptr, const Work& w, int64_t cap_max, int64_t cap_sad, const Tuning& tu,
-                           hipStream_t s);
+                           int32_t* ptr, const Work& w, const Tuning& tu, hipStream_t s);
 hipError_t launch_classify_tiled(const float* f, const Grid& g, bool minima, int32_t* lab, int32_t* ptr,
-                                 const Work& w, int64_t cap_max, int64_t cap_sad, const Tuning& tu, hipStream_t s);
-TileArgs tile_args(const float* f, const Grid& g, int32_t* lab, int32_t* ptr, const Work& w, int64_t cap_max,
-                   int64_t cap_sad, int ty, int tz);
+                                 const Work& w, const Tuning& tu, hipStream_t s);
+TileArgs tile_args(const float* f, const Grid& g, int32_t* lab, int32_t* ptr, const Work& w, int ty, int tz);
+ArcArgs arc_args(const float* f, const Grid& g, const eg_out& o, const Work& w);
+uint32_t arc_blocks(int64_t N);
 hipError_t launch_classify_batched(const BatchPlan* dplan, const BatchPlan& hplan, hipStream_t s);
+hipError_t launch_batched_init(const BatchPlan* dplan, const BatchPlan& hplan, hipStream_t s);
 hipError_t launch_batched_rest(const BatchPlan* dplan, const BatchPlan& hplan, hipStream_t s);
-
-// Sort keys of stage (d), b = id_bits(N), 2b + 2 bits in all:
-//   bit 2b+1      0 for a maximum entry, 1 for a saddle entry (maxima sort first)
-//   bits b+1..2b  the vertex (the maximum, or the saddle)
-//   bit b         marker: 1 on the one entry per saddle that closes its row
-//   bits 0..b-1   the maximum an arc reaches, or the marker's component count
-__device__ __forceinline__ uint64_t max_key(uint32_t m, int b) { return uint64_t(m) << (b + 1); }
-__device__ __forceinline__ uint64_t saddle_key(uint32_t s, uint32_t low, uint32_t marker, int b)
-{
-    return (uint64_t(1) << (2 * b + 1)) | (uint64_t(s) << (b + 1)) | (uint64_t(marker) << b) | uint64_t(low);
-}
 
 // Label codes between classification and the label pass (int32):
 //   x >= 0            final: the maximum x
@@ -271,19 +254,10 @@ hipError_t launch_labels(const Grid& g, int32_t* lab, const Work& w, const Tunin
 // if some vertex is not final yet.
 hipError_t launch_final_tiled(const Grid& g, int32_t* lab, const Work& w, const Tuning& tu, int flag_slot,
                               hipStream_t s);
-hipError_t launch_reps(const float* f, const Grid& g, const LinkTable& t, bool minima, const int32_t* lab,
-                       const Work& w, int64_t cap_sad, int bits, hipStream_t s);
-// Sort keys[0 .. min(*count, cap)) over bits [0, nbits).  Returns in *sorted
-// the buffer holding the result (one of a, b).
-hipError_t launch_sort(uint64_t* a, uint64_t* b, const uint32_t* count, int64_t cap, int nbits, uint32_t* hist,
-                       uint64_t** sorted, hipStream_t s);
-hipError_t launch_load_maxima(const Work& w, int64_t cap_max, int bits, hipStream_t s);
-hipError_t launch_csr(const uint64_t* keys, const Work& w, int bits, const eg_out& o, hipStream_t s);
-// Per-block arc and marker counts of sorted keys and their scan; totals into
-// ctr[C_NARC], ctr[C_NSADF]; block bases at hist + 256 * kSortBlocks.
-hipError_t launch_csr_counts(const uint64_t* keys, const uint32_t* count, int64_t cap, int bits, uint32_t* hist,
-                             uint32_t* ctr, hipStream_t s);
-hipError_t launch_batched_init(const BatchPlan* dplan, const BatchPlan& hplan, hipStream_t s);
-hipError_t launch_finalize(const Work& w, const eg_out& o, hipStream_t s);
+// Stage (d) of one field: ascending maxima and saddles from the bitmasks,
+// the arcs of every saddle, the CSR and the header.
+hipError_t launch_arcs(const ArcArgs& a, hipStream_t s);
+// Stage (d) of every field of a batch (fields are blockIdx.y).
+hipError_t launch_arcs_batched(const BatchPlan* dplan, const BatchPlan& hplan, hipStream_t s);
 
 }  // namespace eg

@@ -92,34 +92,32 @@ int64_t exit_capacity(int64_t N)
     return std::max<int64_t>(0, std::min(cap, room));
 }
 
-Work carve(void* base, int64_t N, int64_t cap_max, int64_t cap_sad, int64_t cap_pairs)
+Work carve(void* base, int64_t N, int64_t X, int64_t cap_sad)
 {
     Work w{};
     w.cap_exit = exit_capacity(N);
-    w.cap_keys = std::max<int64_t>(cap_pairs + cap_sad + cap_max, 1);
+    w.words = mask_words(N, X);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t at = off;
         off = align256(off + bytes);
         return at;
     };
-    size_t o_ctr = take(sizeof(uint32_t) * C_SLOTS);
-    size_t o_umax = take(sizeof(uint32_t) * (size_t)std::max<int64_t>(cap_max, 1));
-    size_t o_usad = take(sizeof(uint32_t) * (size_t)std::max<int64_t>(cap_sad, 1));
-    size_t o_ka = take(sizeof(uint64_t) * (size_t)w.cap_keys);
-    size_t o_kb = take(sizeof(uint64_t) * (size_t)w.cap_keys);
-    size_t o_h = take(sizeof(uint32_t) * (256 * kSortBlocks + 2 * kSortBlocks + 64));
-    size_t o_ex = take(sizeof(uint32_t) * (size_t)std::max<int64_t>(w.cap_exit, 1));
-    size_t o_er = take(sizeof(int32_t) * (size_t)std::max<int64_t>(w.cap_exit, 1));
+    const size_t o_ctr = take(sizeof(uint32_t) * C_SLOTS);
+    const size_t o_mm = take(sizeof(uint64_t) * (size_t)w.words);
+    const size_t o_sm = take(sizeof(uint64_t) * (size_t)w.words);
+    const size_t o_bs = take(sizeof(uint32_t) * 4 * kArcBlocks);
+    const size_t o_at = take(sizeof(uint2) * (size_t)std::max<int64_t>(cap_sad, 1));
+    const size_t o_ex = take(sizeof(uint32_t) * (size_t)std::max<int64_t>(w.cap_exit, 1));
+    const size_t o_er = take(sizeof(int32_t) * (size_t)std::max<int64_t>(w.cap_exit, 1));
     w.bytes = off;
     if (base) {
         char* p = (char*)base;
         w.ctr = (uint32_t*)(p + o_ctr);
-        w.umax = (uint32_t*)(p + o_umax);
-        w.usad = (uint32_t*)(p + o_usad);
-        w.keysA = (uint64_t*)(p + o_ka);
-        w.keysB = (uint64_t*)(p + o_kb);
-        w.hist = (uint32_t*)(p + o_h);
+        w.mmask = (uint64_t*)(p + o_mm);
+        w.smask = (uint64_t*)(p + o_sm);
+        w.bsum = (uint32_t*)(p + o_bs);
+        w.atmp = (uint2*)(p + o_at);
         w.exits = (uint32_t*)(p + o_ex);
         w.exres = (int32_t*)(p + o_er);
     }

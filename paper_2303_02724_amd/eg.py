@@ -53,7 +53,6 @@ class eg_out(ctypes.Structure):
         ("cap_sad", ctypes.c_int64),
         ("arc_maxima", ctypes.c_void_p),
         ("cap_arc", ctypes.c_int64),
-        ("cap_pairs", ctypes.c_int64),
         ("workspace", ctypes.c_void_p),
         ("ws_bytes", ctypes.c_size_t),
         ("header", ctypes.c_void_p),
@@ -74,7 +73,7 @@ def lib():
                            "(run `python -c 'import __graft_entry__ as g; g.build()'`)")
     L = ctypes.CDLL(LIB_PATH)
     vp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
-    L.eg_workspace_bytes.argtypes = [ctypes.c_int, i64p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
+    L.eg_workspace_bytes.argtypes = [ctypes.c_int, i64p, ctypes.c_int64]
     L.eg_workspace_bytes.restype = ctypes.c_size_t
     for name in ("eg_build", "eg_classify", "eg_label", "eg_arcs"):
         fn = getattr(L, name)
@@ -108,8 +107,8 @@ def _dims(shape):
     return arr
 
 
-def workspace_bytes(shape, cap_max: int, cap_sad: int, cap_pairs: int) -> int:
-    return int(lib().eg_workspace_bytes(len(shape), _dims(shape), cap_max, cap_sad, cap_pairs))
+def workspace_bytes(shape, cap_sad: int) -> int:
+    return int(lib().eg_workspace_bytes(len(shape), _dims(shape), cap_sad))
 
 
 def link_table(ndim: int):
@@ -128,8 +127,7 @@ def link_table(ndim: int):
 def default_caps(n: int, ndim: int) -> dict:
     """Starting capacities; the library reports exact needs if they are short."""
     sad = min(n, max(4096, n // (8 if ndim <= 3 else 4)))
-    return {"cap_max": min(n, max(4096, n // 16)), "cap_sad": sad,
-            "cap_pairs": 3 * sad, "cap_arc": 3 * sad}
+    return {"cap_max": min(n, max(4096, n // 16)), "cap_sad": sad, "cap_arc": 3 * sad}
 
 
 @dataclass
@@ -180,7 +178,7 @@ class Builder:
         self.offsets = torch.empty(caps["cap_sad"] + 1, **i32)
         self.arcs = torch.empty(max(1, caps["cap_arc"]), **i32)
         self.header = torch.zeros(H_SLOTS, **i32)
-        ws = workspace_bytes(self.shape, caps["cap_max"], caps["cap_sad"], caps["cap_pairs"])
+        ws = workspace_bytes(self.shape, caps["cap_sad"])
         if ws == 0:
             raise EGError(EG_ERR_ARG, f"workspace query failed for {self.shape} {caps}")
         self.ws = torch.empty(ws + 256, dtype=torch.uint8, device=dev)
@@ -198,7 +196,6 @@ class Builder:
         o.cap_sad = caps["cap_sad"]
         o.arc_maxima = self.arcs.data_ptr()
         o.cap_arc = caps["cap_arc"]
-        o.cap_pairs = caps["cap_pairs"]
         o.workspace = aligned
         o.ws_bytes = ws
         o.header = self.header.data_ptr()
@@ -251,14 +248,11 @@ class Builder:
             c["cap_max"] = h[H_NMAX]
         if h[H_NSAD] > c["cap_sad"]:
             c["cap_sad"] = h[H_NSAD]
-        if h[H_NPAIRS] > c["cap_pairs"]:
-            c["cap_pairs"] = h[H_NPAIRS]
         if h[H_NARC] > c["cap_arc"]:
             c["cap_arc"] = h[H_NARC]
-        if h[H_NSAD] > self.caps["cap_sad"] and h[H_NPAIRS] < 0:
-            c["cap_pairs"] = max(c["cap_pairs"], 4 * c["cap_sad"])
         if h[H_NARC] < 0:
-            c["cap_arc"] = max(c["cap_arc"], c["cap_pairs"])
+            # the arcs of the saddles past the old capacity were not counted
+            c["cap_arc"] = max(c["cap_arc"], 3 * c["cap_sad"])
         self._alloc(c)
 
     def run(self, field: torch.Tensor, max_retries: int = 4) -> EGResult:

@@ -34,14 +34,15 @@ def test_exports_every_declared_function():
 
 
 def test_workspace_bytes():
-    assert eg.workspace_bytes((64, 64), 10, 10, 10) > 0
-    assert eg.workspace_bytes((64, 64), 10, 10, 10) <= eg.workspace_bytes((64, 64), 1000, 1000, 1000)
+    assert eg.workspace_bytes((64, 64), 10) > 0
+    assert eg.workspace_bytes((64, 64), 10) < eg.workspace_bytes((64, 64), 1000)
+    # bitmask rows are padded to 64 vertices: a short last axis costs more
+    assert eg.workspace_bytes((4096, 4), 0) > eg.workspace_bytes((4, 4096), 0)
     L = eg.lib()
-    bad = [((), 1, 1, 1), ((0, 4), 1, 1, 1), ((2,) * 6, 1, 1, 1), ((1 << 16, 1 << 16), 1, 1, 1),
-           ((4, 4), -1, 1, 1)]
-    for shape, a, b, c in bad:
+    bad = [((), 1), ((0, 4), 1), ((2,) * 6, 1), ((1 << 16, 1 << 16), 1), ((4, 4), -1), ((4, 4), 1 << 31)]
+    for shape, c in bad:
         dims = (ctypes.c_int64 * max(1, len(shape)))(*shape)
-        assert L.eg_workspace_bytes(len(shape), dims, a, b, c) == 0, shape
+        assert L.eg_workspace_bytes(len(shape), dims, c) == 0, shape
 
 
 def test_build_rejects_bad_arguments_on_host():
@@ -61,7 +62,7 @@ def test_build_rejects_bad_arguments_on_host():
     assert L.eg_build(fake, 2, dims, None, ctypes.byref(o)) == eg.EG_ERR_ARG
     # buffers present but no workspace
     o.labels = o.header = o.arc_offsets = o.maxima = o.saddles = o.arc_maxima = 0x2000
-    o.cap_max = o.cap_sad = o.cap_arc = o.cap_pairs = 4
+    o.cap_max = o.cap_sad = o.cap_arc = 4
     assert L.eg_build(fake, 2, dims, None, ctypes.byref(o)) == eg.EG_ERR_WORKSPACE
     o.workspace = 0x3001  # misaligned
     o.ws_bytes = 1 << 30
@@ -147,7 +148,7 @@ def test_link_table_fvectors_and_3d_histogram():
 def _fake_out(cap=4, ws=1 << 30):
     o = eg.eg_out()
     o.labels = o.header = o.arc_offsets = o.maxima = o.saddles = o.arc_maxima = 0x2000
-    o.cap_max = o.cap_sad = o.cap_arc = o.cap_pairs = cap
+    o.cap_max = o.cap_sad = o.cap_arc = cap
     o.workspace = 0x100000
     o.ws_bytes = ws
     return o
@@ -181,11 +182,12 @@ def test_batch_plan_validation_on_host():
                            pb) == eg.EG_ERR_WORKSPACE
     # short host plan buffer
     assert L.eg_batch_plan(n, fields, ndims, dims, outs, ctypes.c_void_p(0x200000), wsb, host, 8) == eg.EG_ERR_ARG
-    # cap_max must be at least 1 in a batch
+    # capacities must lie in [0, 2^31)
     outs0 = (eg.eg_out * n)(_fake_out(), _fake_out())
-    outs0[1].cap_max = 0
+    outs0[1].cap_max = -1
     assert L.eg_batch_plan(n, fields, ndims, dims, outs0, ctypes.c_void_p(0x200000), wsb, host,
-                           pb) == eg.EG_ERR_ARG
+                           pb) == eg.EG_ERR_TOO_LARGE
+    assert L.eg_batch_workspace_bytes(n, ndims, dims, outs0) == 0
     # per-field workspace too small
     outs1 = (eg.eg_out * n)(_fake_out(), _fake_out(ws=8))
     assert L.eg_batch_plan(n, fields, ndims, dims, outs1, ctypes.c_void_p(0x200000), wsb, host,

@@ -100,7 +100,7 @@ def test_capacity_overflow_then_retry():
     from paper_2303_02724_amd import eg
     f = W.random_field((40, 30, 20), 8, "uniform")
     t = torch.from_numpy(f).cuda()
-    b = eg.Builder(f.shape, cap_max=3, cap_sad=5, cap_pairs=7, cap_arc=2)
+    b = eg.Builder(f.shape, cap_max=3, cap_sad=5, cap_arc=2)
     b.launch(t)
     h = b.header_values() if b._stream.synchronize() is None else None
     assert h[eg.H_STATUS] == eg.EG_ERR_CAPACITY
@@ -149,7 +149,7 @@ def test_batched_replay_and_capacity_retry():
     fields = [W.batched_field(sp) for sp in specs]
     ts = [torch.from_numpy(f).cuda() for f in fields]
     # tiny capacities force a capacity report and a retry with grown buffers
-    caps = [{"cap_max": 1, "cap_sad": 1, "cap_pairs": 1, "cap_arc": 1} for _ in fields]
+    caps = [{"cap_max": 1, "cap_sad": 1, "cap_arc": 1} for _ in fields]
     bb = eg.BatchBuilder([f.shape for f in fields], caps=caps)
     res = bb.run(ts)
     want = [O.extremum_graph(f) for f in fields]
@@ -177,10 +177,10 @@ def test_serving_mix_equals_alone():
         t += rng.exponential(1 / 2000.0)
         reqs.append((t, int(rng.integers(0, len(fields)))))
     caps = {tuple(t.shape): {"cap_max": max(1, len(a["maxima"])), "cap_sad": max(1, len(a["saddles"])),
-                             "cap_pairs": max(1, int(a["saddle_beta"].sum())), "cap_arc": max(1, len(a["arc_maxima"]))}
+                             "cap_arc": max(1, len(a["arc_maxima"]))}
             for t, a in zip(fields, alone)}
     budget = 3 * max(serving.footprint(eg.Builder(sh, **caps[sh])) for sh in caps)
-    for caps_for, exact in ((lambda sh: caps[sh], True), (lambda sh: {"cap_max": 1, "cap_sad": 1, "cap_pairs": 1,
+    for caps_for, exact in ((lambda sh: caps[sh], True), (lambda sh: {"cap_max": 1, "cap_sad": 1,
                                                                        "cap_arc": 1}, False)):
         got = {}
         srv = serving.Server(hbm_budget=budget, max_slots=8, max_batch=4, lanes=2, caps_for=caps_for)
