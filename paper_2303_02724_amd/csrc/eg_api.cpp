@@ -181,8 +181,8 @@ eg_status eg_batch_plan(int count, const float* const* fields, const int* ndims,
     BatchField* F = (BatchField*)((char*)host_plan + L.o_fields);
     P->count = count;
     if (!decode_tuning(outs[0].tuning, &P->tuning)) return EG_ERR_ARG;
-    P->bctr = (uint32_t*)(dbase + L.o_bctr);
-    P->fields = (BatchField*)(dbase + L.o_fields);
+    P->bctr = gptr((uint32_t*)(dbase + L.o_bctr));
+    P->fields = gptr((BatchField*)(dbase + L.o_fields));
     P->dev = (const BatchPlan*)(dbase + L.o_plan);
     P->plan_bytes = (int64_t)L.plan_bytes;
     // plan order: by class (2D max, 2D min, 3D max, 3D min), stable
@@ -219,7 +219,7 @@ eg_status eg_batch_plan(int count, const float* const* fields, const int* ndims,
         B.N = g.N;
         B.tile_base = tiles;
         B.arc_base = arc_blocks_total;
-        B.exres = w.exres;
+        B.exres = gptr(w.exres);
         tiles += B.ta.ntiles;
         arc_blocks_total += B.arc.arc_blocks;
     }

@@ -9,9 +9,9 @@
 //   2. k_arc_count: for every saddle, the highest vertex of each upper-link
 //      component (UpperLinkRep, Sec. 3.4), the label it reaches, and the
 //      ascending distinct set of those labels: the saddle's arcs (arcs form
-//      a set, Sec. 2); the count and the first two arcs are kept;
+//      a set, Sec. 2); the count and the first four arcs are kept;
 //   3. k_scan_rows / k_arc_write: the CSR offsets from a scan of the counts,
-//      then the arcs (saddles with more than two distinct arcs, rare, are
+//      then the arcs (saddles with more than four distinct arcs, rare, are
 //      recomputed rather than stored);
 //   4. k_finalize: status and counts into the header.
 // No step uses an atomic: every position comes from a scan, so results do
@@ -70,10 +70,10 @@ struct OneField {
 };
 
 struct BatchFields {
-    const BatchPlan* plan;
+    EG_GPTR(const BatchPlan) plan;
     __device__ __forceinline__ const ArcArgs& locate(uint32_t& blk, uint32_t& nb) const
     {
-        const BatchField* fs = plan->fields;
+        const EG_GPTR(BatchField) fs = plan->fields;
         const int64_t b = blockIdx.x;
         int lo = 0, hi = plan->count - 1;
         while (lo < hi) {
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void k_mask_count(Sel sel)
 {
     __shared__ uint32_t tmp[4];
     uint32_t blk, nb;
-    const ArcArgs& A = sel.locate(blk, nb);
+    const ArcArgs A = sel.locate(blk, nb);  // a copy: loop loads cannot alias it
     uint32_t lo, hi;
     chunk((uint32_t)A.words, nb, blk, lo, hi);
     uint32_t cm = 0, cs = 0;
@@ -175,7 +175,7 @@ template <class Sel>
 __global__ __launch_bounds__(1024) void k_scan_rows(Sel sel, int row, int slot0, int slot1)
 {
     __shared__ uint32_t wsum[16];
-    const ArcArgs& A = sel.field();
+    const ArcArgs A = sel.field();
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int nb = A.arc_blocks;
 #pragma unroll
@@ -198,39 +198,47 @@ __global__ __launch_bounds__(1024) void k_scan_rows(Sel sel, int row, int slot0,
     }
 }
 
+// Expand the set bits of every lane's word into vertex ids at positions
+// pos, pos + 1, ... of out[] (below cap).  The wave walks its nonzero words
+// one at a time and each lane takes one bit, so the stores of a word are
+// contiguous.
+__device__ __forceinline__ void expand_words(uint64_t word, uint32_t pos, int32_t vbase, int32_t* __restrict__ out,
+                                             uint32_t cap)
+{
+    const int lane = __lane_id();
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (uint64_t nz = __ballot(word != 0); nz; nz &= nz - 1ull) {
+        const int w = __ffsll((unsigned long long)nz) - 1;
+        // w is uniform: plain lane reads, no permute
+        const uint64_t bits = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)word, w) |
+                              ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(word >> 32), w) << 32);
+        const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)pos, w) + (uint32_t)__popcll(bits & below);
+        const int32_t v = __builtin_amdgcn_readlane(vbase, w) + lane;
+        if (((bits >> lane) & 1ull) && p < cap) out[p] = v;
+    }
+}
+
 template <class Sel>
 __global__ __launch_bounds__(256) void k_mask_emit(Sel sel)
 {
     __shared__ uint32_t tmp[4];
     uint32_t blk, nb;
-    const ArcArgs& A = sel.locate(blk, nb);
+    const ArcArgs A = sel.locate(blk, nb);  // a copy: loop loads cannot alias it
     uint32_t lo, hi;
     chunk((uint32_t)A.words, nb, blk, lo, hi);
     uint32_t rm = A.bsum[blk], rs = A.bsum[kArcBlocks + blk];
     const uint32_t XW = (uint32_t)A.XW, X = (uint32_t)A.X;
     for (uint32_t base = lo; base < hi; base += 256) {
         const uint32_t i = base + threadIdx.x;
-        uint64_t m = i < hi ? A.mmask[i] : 0ull;
-        uint64_t sd = i < hi ? A.smask[i] : 0ull;
+        const uint64_t m = i < hi ? A.mmask[i] : 0ull;
+        const uint64_t sd = i < hi ? A.smask[i] : 0ull;
         uint32_t tm, ts;
-        uint32_t pm = rm + block_excl_scan((uint32_t)__popcll(m), tmp, tm);
-        uint32_t ps = rs + block_excl_scan((uint32_t)__popcll(sd), tmp, ts);
-        if (m | sd) {
-            const uint32_t row = i / XW, xw = i - row * XW;
-            const int32_t vbase = (int32_t)(row * X + xw * 64u);
-            while (m) {
-                const int b = __ffsll((unsigned long long)m) - 1;
-                m &= m - 1ull;
-                if (pm < A.cap_max) A.maxima[pm] = vbase + b;
-                ++pm;
-            }
-            while (sd) {
-                const int b = __ffsll((unsigned long long)sd) - 1;
-                sd &= sd - 1ull;
-                if (ps < A.cap_sad) A.saddles[ps] = vbase + b;
-                ++ps;
-            }
-        }
+        const uint32_t pm = rm + block_excl_scan((uint32_t)__popcll(m), tmp, tm);
+        const uint32_t ps = rs + block_excl_scan((uint32_t)__popcll(sd), tmp, ts);
+        const uint32_t row = i / XW, xw = i - row * XW;
+        const int32_t vbase = (int32_t)(row * X + xw * 64u);
+        expand_words(m, pm, vbase, A.maxima, A.cap_max);
+        expand_words(sd, ps, vbase, A.saddles, A.cap_sad);
         rm += tm;
         rs += ts;
     }
@@ -335,7 +343,8 @@ __device__ __forceinline__ void arc_count_body(const ArcArgs& A, uint32_t blk, u
         const int n = saddle_arcs<NDIM, MINMODE>(A, A.saddles[i], s_adj, s_list + tid, beta);
         if (A.beta) A.beta[i] = beta;
         A.offsets[i + 1] = n;  // the count until k_arc_write turns it into an offset
-        A.atmp[i] = make_uint2(s_list[tid], n > 1 ? s_list[256 + tid] : 0u);
+        A.atmp[i] = make_uint4(s_list[tid], n > 1 ? s_list[256 + tid] : 0u, n > 2 ? s_list[512 + tid] : 0u,
+                               n > 3 ? s_list[768 + tid] : 0u);
         sc += (uint32_t)n;
         sb += (uint32_t)beta;
     }
@@ -364,10 +373,12 @@ __device__ __forceinline__ void arc_write_body(const ArcArgs& A, uint32_t blk, u
         uint32_t total;
         const uint32_t pos = run + block_excl_scan(n, tmp, total);
         if (valid) {
-            if (n <= 2) {
-                const uint2 t = A.atmp[i];
-                if (pos < A.cap_arc) A.arcs[pos] = (int32_t)t.x;
-                if (n == 2 && pos + 1 < A.cap_arc) A.arcs[pos + 1] = (int32_t)t.y;
+            if (n <= 4) {
+                const uint4 t = A.atmp[i];
+                const uint32_t a4[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+                for (uint32_t k = 0; k < 4; ++k)
+                    if (k < n && pos + k < A.cap_arc) A.arcs[pos + k] = (int32_t)a4[k];
             } else {
                 int beta;
                 saddle_arcs<NDIM, MINMODE>(A, A.saddles[i], s_adj, s_list + tid, beta);
@@ -387,7 +398,7 @@ __global__ __launch_bounds__(256) void k_arc_count(OneField sel)
     __shared__ uint64_t s_adj[Rows<NDIM>::K];
     __shared__ uint32_t tmp[4];
     uint32_t blk, nb;
-    const ArcArgs& A = sel.locate(blk, nb);
+    const ArcArgs A = sel.locate(blk, nb);  // a copy: loop loads cannot alias it
     arc_count_body<NDIM, MINMODE>(A, blk, nb, s_list, s_adj, tmp);
 }
 
@@ -398,7 +409,7 @@ __global__ __launch_bounds__(256) void k_arc_write(OneField sel)
     __shared__ uint64_t s_adj[Rows<NDIM>::K];
     __shared__ uint32_t tmp[4];
     uint32_t blk, nb;
-    const ArcArgs& A = sel.locate(blk, nb);
+    const ArcArgs A = sel.locate(blk, nb);  // a copy: loop loads cannot alias it
     arc_write_body<NDIM, MINMODE>(A, blk, nb, s_list, s_adj, tmp);
 }
 
@@ -411,7 +422,7 @@ __global__ __launch_bounds__(256) void k_arc_batched(BatchFields sel)
     __shared__ uint64_t s_adj[14];
     __shared__ uint32_t tmp[4];
     uint32_t blk, nb;
-    const ArcArgs& A = sel.locate(blk, nb);
+    const ArcArgs A = sel.locate(blk, nb);  // a copy: loop loads cannot alias it
     const int kind = __builtin_amdgcn_readfirstlane((A.ndim == 3 ? 2 : 0) + (A.minima ? 1 : 0));
 #define EG_BODY(ND, MM)                                                  \
     if (WRITE)                                                           \
@@ -433,7 +444,7 @@ template <class Sel>
 __global__ void k_finalize(Sel sel)
 {
     if (threadIdx.x != 0) return;
-    const ArcArgs& A = sel.field();
+    const ArcArgs A = sel.field();
     const uint32_t* c = A.ctr;
     const int64_t nmax = c[C_NMAX], nsad = c[C_NSAD], narc = c[C_NARC];
     const bool sad_over = nsad > A.cap_sad;
@@ -466,19 +477,19 @@ uint32_t arc_blocks(int64_t N)
 ArcArgs arc_args(const float* f, const Grid& g, const eg_out& o, const Work& w)
 {
     ArcArgs a{};
-    a.f = f;
-    a.lab = o.labels;
-    a.mmask = w.mmask;
-    a.smask = w.smask;
-    a.bsum = w.bsum;
-    a.atmp = w.atmp;
-    a.ctr = w.ctr;
-    a.header = o.header;
-    a.maxima = o.maxima;
-    a.saddles = o.saddles;
-    a.beta = o.saddle_beta;
-    a.offsets = o.arc_offsets;
-    a.arcs = o.arc_maxima;
+    a.f = gptr(f);
+    a.lab = gptr<const int32_t>(o.labels);
+    a.mmask = gptr<const uint64_t>(w.mmask);
+    a.smask = gptr<const uint64_t>(w.smask);
+    a.bsum = gptr(w.bsum);
+    a.atmp = gptr(w.atmp);
+    a.ctr = gptr(w.ctr);
+    a.header = gptr(o.header);
+    a.maxima = gptr(o.maxima);
+    a.saddles = gptr(o.saddles);
+    a.beta = gptr(o.saddle_beta);
+    a.offsets = gptr(o.arc_offsets);
+    a.arcs = gptr(o.arc_maxima);
     a.ndim = g.ndim;
     a.minima = (o.flags & EG_MINIMA) ? 1 : 0;
     a.N = g.N;
@@ -531,7 +542,7 @@ hipError_t launch_arcs(const ArcArgs& a, hipStream_t s)
 
 hipError_t launch_arcs_batched(const BatchPlan* dplan, const BatchPlan& hplan, hipStream_t s)
 {
-    const BatchFields sel{dplan};
+    const BatchFields sel{gptr(dplan)};
     const unsigned grid = (unsigned)hplan.total_arc_blocks;
     const unsigned count = (unsigned)hplan.count;
     hipLaunchKernelGGL(k_mask_count<BatchFields>, dim3(grid), dim3(256), 0, s, sel);

@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void k_binit(const BatchPlan* __restrict__ pla
 
 __global__ __launch_bounds__(256) void k_bexit_init(const BatchPlan* __restrict__ plan)
 {
-    const BatchField& F = plan->fields[blockIdx.y];
+    const BatchField F = plan->fields[blockIdx.y];  // a copy: loop loads cannot alias it
     const uint32_t req = rd(&F.ta.ctr[C_NEXIT]);
     const uint32_t n = req < F.ta.cap_exit ? req : F.ta.cap_exit;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
@@ -47,12 +47,13 @@ __global__ __launch_bounds__(256) void k_bexit_init(const BatchPlan* __restrict_
 __global__ __launch_bounds__(256) void k_bexit_jump(const BatchPlan* __restrict__ plan, int pass)
 {
     if (!bgate(plan->bctr, C_JUMP, pass)) return;
-    const BatchField& F = plan->fields[blockIdx.y];
+    const BatchField F = plan->fields[blockIdx.y];  // a copy: loop loads cannot alias it
     const uint32_t req = rd(&F.ta.ctr[C_NEXIT]);
     const uint32_t n = req < F.ta.cap_exit ? req : F.ta.cap_exit;
     const int N = F.N;
     const int32_t* lab = F.ta.lab;
     int32_t* res = F.exres;
+    const int hops = plan->tuning.hops;
     bool notdone = false;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         int x = res[i];
@@ -61,7 +62,7 @@ __global__ __launch_bounds__(256) void k_bexit_jump(const BatchPlan* __restrict_
         do {
             x = next_link_b(lab, res, N, x);
             ++h;
-        } while (x < 0 && h < plan->tuning.hops);
+        } while (x < 0 && h < hops);
         res[i] = x;
         notdone |= x < 0;
     }
@@ -71,10 +72,11 @@ __global__ __launch_bounds__(256) void k_bexit_jump(const BatchPlan* __restrict_
 __global__ __launch_bounds__(256) void k_bfinal(const BatchPlan* __restrict__ plan, int pass)
 {
     if (!bgate(plan->bctr, C_FINAL, pass)) return;
-    const BatchField& F = plan->fields[blockIdx.y];
+    const BatchField F = plan->fields[blockIdx.y];  // a copy: loop loads cannot alias it
     const int N = F.N;
     int32_t* lab = F.ta.lab;
     const int32_t* res = F.exres;
+    const int hops = plan->tuning.hops;
     bool notdone = false;
     const int nq = N >> 2;
     int4* lab4 = reinterpret_cast<int4*>(lab);
@@ -87,7 +89,6 @@ __global__ __launch_bounds__(256) void k_bfinal(const BatchPlan* __restrict__ pl
         int y2 = x.z < 0 ? next_link_b(lab, res, N, x.z) : x.z;
         int y3 = x.w < 0 ? next_link_b(lab, res, N, x.w) : x.w;
         int h = 1;
-        const int hops = plan->tuning.hops;
         while ((y0 < 0 || y1 < 0 || y2 < 0 || y3 < 0) && h < hops) {
             if (y0 < 0) y0 = next_link_b(lab, res, N, y0);
             if (y1 < 0) y1 = next_link_b(lab, res, N, y1);
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(256) void k_bfinal(const BatchPlan* __restrict__ pl
     if (t < (N & 3)) {
         const int v = (nq << 2) + t;
         int y = lab[v];
-        for (int h = 0; y < 0 && h < plan->tuning.hops; ++h) y = next_link_b(lab, res, N, y);
+        for (int h = 0; y < 0 && h < hops; ++h) y = next_link_b(lab, res, N, y);
         lab[v] = y;
         notdone |= y < 0;
     }
@@ -121,8 +122,11 @@ hipError_t launch_batched_rest(const BatchPlan* dplan, const BatchPlan& hplan, h
     const dim3 grid(kBatchBlocksPerField, hplan.count);
     hipLaunchKernelGGL(k_bexit_init, grid, dim3(256), 0, s, dplan);
     for (int p = 0; p < hplan.tuning.passes; ++p) hipLaunchKernelGGL(k_bexit_jump, grid, dim3(256), 0, s, dplan, p);
-    for (int p = 0; p < hplan.tuning.passes; ++p) hipLaunchKernelGGL(k_bfinal, grid, dim3(256), 0, s, dplan, p);
-    hipError_t e = hipGetLastError();
+    // pass 0 in tile order, the rest linear (each gated by the pass before)
+    hipError_t e = launch_final_tiled_batched(dplan, hplan, s);
+    if (e != hipSuccess) return e;
+    for (int p = 1; p < hplan.tuning.passes; ++p) hipLaunchKernelGGL(k_bfinal, grid, dim3(256), 0, s, dplan, p);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_arcs_batched(dplan, hplan, s);
 }

@@ -571,8 +571,8 @@ __device__ __forceinline__ int xcd_tile(int b, int ntiles)
 // `hops` links and raise the pass flag if they stop short; the linear passes
 // after this one finish them.
 template <int TY, int TZ>
-__global__ __launch_bounds__(256) void k_final_tiled(TileArgs a, const int32_t* __restrict__ res, int hops,
-                                                     int flag_slot)
+__device__ __forceinline__ void final_tile(const TileArgs& a, int b, const int32_t* __restrict__ res, int hops,
+                                           uint32_t* flag)
 {
     constexpr int YPT = TY / 4;
     const int X = a.X, Y = a.Y, Z = a.Z;
@@ -580,7 +580,6 @@ __global__ __launch_bounds__(256) void k_final_tiled(TileArgs a, const int32_t* 
     const int SY = X, SZ = X * Y;
     int32_t* lab = a.lab;
     const int tid = threadIdx.x, lx = tid & 63, wv = tid >> 6;
-    const int b = xcd_tile(blockIdx.x, a.ntiles);
     const int tx = b % a.tiles_x;
     const int rr = b / a.tiles_x;
     const int ty = rr % a.tiles_y;
@@ -613,7 +612,58 @@ __global__ __launch_bounds__(256) void k_final_tiled(TileArgs a, const int32_t* 
 #pragma unroll
     for (int k = 0; k < VPT; ++k)
         if (vid[k] >= 0) lab[vid[k]] = x[k];
-    if (__ballot(notdone) != 0 && __lane_id() == 0) atomicOr(&a.ctr[flag_slot], 1u);
+    if (__ballot(notdone) != 0 && __lane_id() == 0) atomicOr(flag, 1u);
+}
+
+template <int TY, int TZ>
+__global__ __launch_bounds__(256) void k_final_tiled(TileArgs a, const int32_t* __restrict__ res, int hops,
+                                                     int flag_slot)
+{
+    final_tile<TY, TZ>(a, xcd_tile(blockIdx.x, a.ntiles), res, hops, &a.ctr[flag_slot]);
+}
+
+// The same pass over the tiles of every 2D (or every 3D) field of a batch:
+// classes 2 * (NDIM - 2) and the one after it (maximum and minimum graphs)
+// own consecutive tiles.
+template <int NDIM, int TY, int TZ>
+__global__ __launch_bounds__(256) void k_final_tiled_batched(const BatchPlan* __restrict__ plan)
+{
+    constexpr int c0 = 2 * (NDIM - 2);
+    const EG_GPTR(BatchField) fs = plan->fields;
+    const int64_t item = plan->class_tile[c0] + blockIdx.x;
+    int lo = plan->class_field[c0], hi = plan->class_field[c0 + 2] - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (fs[mid].tile_base <= item)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int f = __builtin_amdgcn_readfirstlane(lo);
+    const TileArgs a = fs[f].ta;
+    final_tile<TY, TZ>(a, (int)(item - fs[f].tile_base), fs[f].exres, plan->tuning.hops, &plan->bctr[C_FINAL]);
+}
+
+hipError_t launch_final_tiled_batched(const BatchPlan* dplan, const BatchPlan& hplan, hipStream_t s)
+{
+    const Tuning& tu = hplan.tuning;
+    const int64_t t2 = hplan.class_tile[2] - hplan.class_tile[0];
+    const int64_t t3 = hplan.class_tile[4] - hplan.class_tile[2];
+    if (t2 > 0) {
+        if (tu.tile2 == 1)
+            hipLaunchKernelGGL((k_final_tiled_batched<2, 16, 1>), dim3((unsigned)t2), dim3(256), 0, s, dplan);
+        else
+            hipLaunchKernelGGL((k_final_tiled_batched<2, 32, 1>), dim3((unsigned)t2), dim3(256), 0, s, dplan);
+    }
+    if (t3 > 0) {
+        if (tu.tile3 == 1)
+            hipLaunchKernelGGL((k_final_tiled_batched<3, 4, 16>), dim3((unsigned)t3), dim3(256), 0, s, dplan);
+        else if (tu.tile3 == 2)
+            hipLaunchKernelGGL((k_final_tiled_batched<3, 8, 4>), dim3((unsigned)t3), dim3(256), 0, s, dplan);
+        else
+            hipLaunchKernelGGL((k_final_tiled_batched<3, 8, 8>), dim3((unsigned)t3), dim3(256), 0, s, dplan);
+    }
+    return hipGetLastError();
 }
 
 template <bool MINMODE, int TY, int TZ>
@@ -638,13 +688,13 @@ __global__ __launch_bounds__(256) void k_classify2d(TileArgs a)
 TileArgs tile_args(const float* f, const Grid& g, int32_t* lab, int32_t* ptr, const Work& w, int ty, int tz)
 {
     TileArgs a{};
-    a.f = f;
-    a.lab = lab;
-    a.ptr = ptr;
-    a.ctr = w.ctr;
-    a.mmask = w.mmask;
-    a.smask = w.smask;
-    a.exits = w.exits;
+    a.f = gptr(f);
+    a.lab = gptr(lab);
+    a.ptr = gptr(ptr);
+    a.ctr = gptr(w.ctr);
+    a.mmask = gptr(w.mmask);
+    a.smask = gptr(w.smask);
+    a.exits = gptr(w.exits);
     a.X = g.dims[g.ndim - 1];
     a.Y = g.dims[g.ndim - 2];
     a.Z = g.ndim == 3 ? g.dims[0] : 1;
@@ -668,7 +718,7 @@ __global__ __launch_bounds__(256) void k_classify_batched(const BatchPlan* __res
     __shared__ uint32_t s_u[WORDS];
     __shared__ uint32_t s_conn[NDIM == 3 ? 512 : 1];
     __shared__ uint32_t s_tmp[40];
-    const BatchField* fs = plan->fields;
+    const EG_GPTR(BatchField) fs = plan->fields;
     const int f0 = plan->class_field[cls], f1 = plan->class_field[cls + 1];
     const int64_t item = plan->class_tile[cls] + blockIdx.x;
     // the field of this item: binary search over the class's tile bases

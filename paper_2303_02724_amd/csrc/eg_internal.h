@@ -92,7 +92,7 @@ struct Work {
     uint64_t* mmask;  // [words] maxima
     uint64_t* smask;  // [words] saddles
     uint32_t* bsum;   // [4 * kArcBlocks] per-block counts of stage (d)
-    uint2* atmp;      // [cap_sad] the first two arcs of every saddle
+    uint4* atmp;      // [cap_sad] the first four arcs of every saddle
     uint32_t* exits;  // [cap_exit] exit vertices published by the tiles
     int32_t* exres;   // [cap_exit] their labels while being resolved
     int64_t words;
@@ -100,34 +100,49 @@ struct Work {
     size_t bytes;
 };
 
+// Pointers to device memory in the structs below are typed as global-memory
+// pointers in device code (same 64-bit layout as the host's plain pointers).
+// Structs read from a batch plan would otherwise give the compiler generic
+// pointers, whose flat instructions also wait on the LDS counter.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define EG_GPTR(T) __attribute__((address_space(1))) T*
+#else
+#define EG_GPTR(T) T*
+#endif
+template <class T>
+__host__ __device__ inline EG_GPTR(T) gptr(T* p)
+{
+    return (EG_GPTR(T))p;
+}
+
 // Everything a classification tile needs to know about its field.
 struct TileArgs {
-    const float* f;
-    int32_t* lab;
-    int32_t* ptr;
-    uint32_t* ctr;
-    uint64_t* mmask;
-    uint64_t* smask;
-    uint32_t* exits;
+    EG_GPTR(const float) f;
+    EG_GPTR(int32_t) lab;
+    EG_GPTR(int32_t) ptr;
+    EG_GPTR(uint32_t) ctr;
+    EG_GPTR(uint64_t) mmask;
+    EG_GPTR(uint64_t) smask;
+    EG_GPTR(uint32_t) exits;
     int32_t X, Y, Z, tiles_x, tiles_y, ntiles;
     uint32_t cap_exit, pad0;
 };
 
 // Everything stage (d) needs to know about its field.
 struct ArcArgs {
-    const float* f;
-    const int32_t* lab;
-    const uint64_t* mmask;
-    const uint64_t* smask;
-    uint32_t* bsum;
-    uint2* atmp;
-    uint32_t* ctr;
-    int32_t* header;
-    int32_t* maxima;
-    int32_t* saddles;
-    int32_t* beta;     // may be null
-    int32_t* offsets;
-    int32_t* arcs;
+    EG_GPTR(const float) f;
+    EG_GPTR(const int32_t) lab;
+    EG_GPTR(const uint64_t) mmask;
+    EG_GPTR(const uint64_t) smask;
+    EG_GPTR(uint32_t) bsum;
+    EG_GPTR(uint4) atmp;
+    EG_GPTR(uint32_t) ctr;
+    EG_GPTR(int32_t) header;
+    EG_GPTR(int32_t) maxima;
+    EG_GPTR(int32_t) saddles;
+    EG_GPTR(int32_t) beta;  // may be null
+    EG_GPTR(int32_t) offsets;
+    EG_GPTR(int32_t) arcs;
     int32_t ndim, minima, N, X, XW, words;
     int32_t dims[EG_MAX_NDIM];
     uint32_t cap_max, cap_sad, cap_arc;
@@ -141,7 +156,7 @@ struct BatchField {
     int32_t ndim, minima, N, pad0;
     int64_t tile_base;   // exclusive prefix over fields of tiles
     int64_t arc_base;    // ... of stage (d) blocks
-    int32_t* exres;
+    EG_GPTR(int32_t) exres;
 };
 
 struct BatchPlan {
@@ -154,8 +169,8 @@ struct BatchPlan {
     int32_t class_field[5];
     int32_t pad1;
     int64_t class_tile[5];
-    uint32_t* bctr;       // [C_SLOTS] batch counters (label pass flags)
-    BatchField* fields;   // device address of fields[] (right after this header)
+    EG_GPTR(uint32_t) bctr;      // [C_SLOTS] batch counters (label pass flags)
+    EG_GPTR(BatchField) fields;  // device address of fields[] (right after this header)
     const BatchPlan* dev; // device address of this plan (start of the batch workspace)
     int64_t plan_bytes;
 };
@@ -254,6 +269,8 @@ hipError_t launch_labels(const Grid& g, int32_t* lab, const Work& w, const Tunin
 // if some vertex is not final yet.
 hipError_t launch_final_tiled(const Grid& g, int32_t* lab, const Work& w, const Tuning& tu, int flag_slot,
                               hipStream_t s);
+// The tile-ordered pass over every field of a batch; raises bctr[C_FINAL].
+hipError_t launch_final_tiled_batched(const BatchPlan* dplan, const BatchPlan& hplan, hipStream_t s);
 // Stage (d) of one field: ascending maxima and saddles from the bitmasks,
 // the arcs of every saddle, the CSR and the header.
 hipError_t launch_arcs(const ArcArgs& a, hipStream_t s);

@@ -107,7 +107,7 @@ Work carve(void* base, int64_t N, int64_t X, int64_t cap_sad)
     const size_t o_mm = take(sizeof(uint64_t) * (size_t)w.words);
     const size_t o_sm = take(sizeof(uint64_t) * (size_t)w.words);
     const size_t o_bs = take(sizeof(uint32_t) * 4 * kArcBlocks);
-    const size_t o_at = take(sizeof(uint2) * (size_t)std::max<int64_t>(cap_sad, 1));
+    const size_t o_at = take(sizeof(uint4) * (size_t)std::max<int64_t>(cap_sad, 1));
     const size_t o_ex = take(sizeof(uint32_t) * (size_t)std::max<int64_t>(w.cap_exit, 1));
     const size_t o_er = take(sizeof(int32_t) * (size_t)std::max<int64_t>(w.cap_exit, 1));
     w.bytes = off;
@@ -117,7 +117,7 @@ Work carve(void* base, int64_t N, int64_t X, int64_t cap_sad)
         w.mmask = (uint64_t*)(p + o_mm);
         w.smask = (uint64_t*)(p + o_sm);
         w.bsum = (uint32_t*)(p + o_bs);
-        w.atmp = (uint2*)(p + o_at);
+        w.atmp = (uint4*)(p + o_at);
         w.exits = (uint32_t*)(p + o_ex);
         w.exres = (int32_t*)(p + o_er);
     }

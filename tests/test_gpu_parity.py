@@ -219,6 +219,25 @@ def test_batched_with_tuning():
         assert_same(_result_np(r), O.extremum_graph(f), KEYS, f"batched tuned {f.shape}")
 
 
+def test_batched_long_paths_several_passes():
+    """Paths far longer than a tile and than the links one pass follows
+    (16 here): the exit-list chains need several gated jump passes before the
+    tile-ordered pass can finish every vertex of every field."""
+    import torch
+    from paper_2303_02724_amd import eg
+    shapes = [(2, 100000), (300, 700), (40, 50, 60), (3, 70, 4000)]
+    fields = [np.arange(int(np.prod(sh)), dtype=np.float32).reshape(sh) for sh in shapes]
+    fields.append(W.gaussian_mixture((200, 300), 77, n_gauss=4, noise=1e-3))
+    ts = [torch.from_numpy(f).cuda() for f in fields]
+    bb = eg.BatchBuilder([f.shape for f in fields], tuning=eg.tuning(hops=16))
+    res = bb.run(ts)
+    for f, r in zip(fields, res):
+        assert_same(_result_np(r), O.extremum_graph(f), KEYS, f"batched long {f.shape}")
+    # the path of the first field leaves a tile thousands of times, so its
+    # exit-list chain is longer than 16 * 16 links: at least three passes
+    assert res[0].counts["exits"] > 16 * 16
+
+
 def test_autotuner_records_a_choice(tmp_path):
     import torch
     from paper_2303_02724_amd import tune
