@@ -170,19 +170,32 @@ __global__ __launch_bounds__(256) void k_mask_count(Sel sel)
 
 // Exclusive scan, in place, of rows `row` and `row + 1` of a field's block
 // counts (nb <= kArcBlocks entries each); the row totals go to the counter
-// slots.  One block of 1024 threads per field.
+// slots.  One block of 1024 threads per field, kArcBlocks / 1024 entries per
+// thread staged through LDS.
 template <class Sel>
 __global__ __launch_bounds__(1024) void k_scan_rows(Sel sel, int row, int slot0, int slot1)
 {
+    constexpr int PER = kArcBlocks / 1024;
+    __shared__ uint32_t buf[kArcBlocks];
     __shared__ uint32_t wsum[16];
     const ArcArgs A = sel.field();
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int nb = A.arc_blocks;
-#pragma unroll
     for (int r = 0; r < 2; ++r) {
-        uint32_t* a = A.bsum + (row + r) * kArcBlocks;
-        const uint32_t x = tid < nb ? a[tid] : 0u;
-        const uint32_t inc = wave_incl_scan(x);
+        EG_GPTR(uint32_t) a = A.bsum + (row + r) * kArcBlocks;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = k * 1024 + tid;
+            buf[i] = i < nb ? a[i] : 0u;
+        }
+        __syncthreads();
+        uint32_t x[PER], sum = 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            x[k] = buf[tid * PER + k];
+            sum += x[k];
+        }
+        const uint32_t inc = wave_incl_scan(sum);
         if (lane == 63) wsum[w] = inc;
         __syncthreads();
         if (w == 0) {
@@ -191,30 +204,48 @@ __global__ __launch_bounds__(1024) void k_scan_rows(Sel sel, int row, int slot0,
             if (lane < 16) wsum[lane] = y;
         }
         __syncthreads();
-        const uint32_t ex = (w > 0 ? wsum[w - 1] : 0u) + inc - x;
-        if (tid < nb) a[tid] = ex;
+        uint32_t ex = (w > 0 ? wsum[w - 1] : 0u) + inc - sum;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            buf[tid * PER + k] = ex;
+            ex += x[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = k * 1024 + tid;
+            if (i < nb) a[i] = buf[i];
+        }
         if (tid == 0) A.ctr[r == 0 ? slot0 : slot1] = wsum[15];
         __syncthreads();
     }
 }
 
-// Expand the set bits of every lane's word into vertex ids at positions
-// pos, pos + 1, ... of out[] (below cap).  The wave walks its nonzero words
-// one at a time and each lane takes one bit, so the stores of a word are
-// contiguous.
-__device__ __forceinline__ void expand_words(uint64_t word, uint32_t pos, int32_t vbase, int32_t* __restrict__ out,
-                                             uint32_t cap)
+// Write the vertex ids of the set bits of one round of 256 words (one per
+// thread) to out[run + j], j < total (entries at or past cap are dropped);
+// local is the exclusive count of set bits before this thread's word.  The
+// ids are staged in LDS so that the global stores are whole-wave and
+// contiguous; a round with more ids than the stage (a very dense mask) writes
+// directly.  Every thread of the block must call it.
+constexpr int kStage = 4096;
+__device__ __forceinline__ void emit_round(uint64_t word, uint32_t local, uint32_t total, int32_t vbase,
+                                           uint32_t run, EG_GPTR(int32_t) out, uint32_t cap, int32_t* stage)
 {
-    const int lane = __lane_id();
-    const uint64_t below = (1ull << lane) - 1ull;
-    for (uint64_t nz = __ballot(word != 0); nz; nz &= nz - 1ull) {
-        const int w = __ffsll((unsigned long long)nz) - 1;
-        // w is uniform: plain lane reads, no permute
-        const uint64_t bits = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)word, w) |
-                              ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(word >> 32), w) << 32);
-        const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)pos, w) + (uint32_t)__popcll(bits & below);
-        const int32_t v = __builtin_amdgcn_readlane(vbase, w) + lane;
-        if (((bits >> lane) & 1ull) && p < cap) out[p] = v;
+    if (total == 0) return;
+    if (total <= (uint32_t)kStage) {
+        for (uint32_t j = local; word; ++j) {
+            stage[j] = vbase + (__ffsll((unsigned long long)word) - 1);
+            word &= word - 1ull;
+        }
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < total; j += 256)
+            if (run + j < cap) out[run + j] = stage[j];
+        __syncthreads();
+    } else {
+        for (uint32_t p = run + local; word; ++p) {
+            if (p < cap) out[p] = vbase + (__ffsll((unsigned long long)word) - 1);
+            word &= word - 1ull;
+        }
     }
 }
 
@@ -222,6 +253,7 @@ template <class Sel>
 __global__ __launch_bounds__(256) void k_mask_emit(Sel sel)
 {
     __shared__ uint32_t tmp[4];
+    __shared__ int32_t stage[kStage];
     uint32_t blk, nb;
     const ArcArgs A = sel.locate(blk, nb);  // a copy: loop loads cannot alias it
     uint32_t lo, hi;
@@ -233,12 +265,12 @@ __global__ __launch_bounds__(256) void k_mask_emit(Sel sel)
         const uint64_t m = i < hi ? A.mmask[i] : 0ull;
         const uint64_t sd = i < hi ? A.smask[i] : 0ull;
         uint32_t tm, ts;
-        const uint32_t pm = rm + block_excl_scan((uint32_t)__popcll(m), tmp, tm);
-        const uint32_t ps = rs + block_excl_scan((uint32_t)__popcll(sd), tmp, ts);
+        const uint32_t lm = block_excl_scan((uint32_t)__popcll(m), tmp, tm);
+        const uint32_t ls = block_excl_scan((uint32_t)__popcll(sd), tmp, ts);
         const uint32_t row = i / XW, xw = i - row * XW;
         const int32_t vbase = (int32_t)(row * X + xw * 64u);
-        expand_words(m, pm, vbase, A.maxima, A.cap_max);
-        expand_words(sd, ps, vbase, A.saddles, A.cap_sad);
+        emit_round(m, lm, tm, vbase, rm, A.maxima, A.cap_max, stage);
+        emit_round(sd, ls, ts, vbase, rs, A.saddles, A.cap_sad, stage);
         rm += tm;
         rs += ts;
     }
@@ -467,10 +499,10 @@ __global__ void k_finalize(Sel sel)
 
 // ------------------------------------------------------------------ launchers
 
-// Blocks per field of the stage (d) kernels: one per 32768 vertices.
+// Blocks per field of the stage (d) kernels: one per kArcVertsPerBlock vertices.
 uint32_t arc_blocks(int64_t N)
 {
-    const int64_t b = (N + 32767) / 32768;
+    const int64_t b = (N + kArcVertsPerBlock - 1) / kArcVertsPerBlock;
     return (uint32_t)(b < 1 ? 1 : b > kArcBlocks ? kArcBlocks : b);
 }
 

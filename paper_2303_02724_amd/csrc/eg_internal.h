@@ -25,7 +25,8 @@ namespace eg {
 constexpr int kMaxNb = 62;          // 2(2^5 - 1)
 constexpr int kJumpHops = 64;       // default links per pointer-jumping pass
 constexpr int kMaxPasses = 8;       // flag slots per pass sequence
-constexpr int kArcBlocks = 1024;    // most blocks per field of the stage (d) kernels
+constexpr int kArcBlocks = 8192;    // most blocks per field of the stage (d) kernels
+constexpr int kArcVertsPerBlock = 8192;  // stage (d) blocks: one per this many vertices
 constexpr int kTile3Y = 8, kTile3Z = 8;  // default 3D tile: 64 x 8 x 8 vertices
 constexpr int kTile2Y = 32;             // default 2D tile: 64 x 32 vertices
 
