@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--workload", default="grf512", choices=["grf512", "2d256", "5d32", "batched", "serving"])
     ap.add_argument("--requests", type=int, default=2000, help="serving workload: number of requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serving workload: Poisson arrival rate (1/s)")
+    ap.add_argument("--sat-rate", type=float, default=50000.0,
+                    help="serving workload: second arrival rate, above what one GPU sustains")
     ap.add_argument("--fields", type=int, default=256, help="batched workload: number of fields")
     ap.add_argument("--graph", action="store_true", help="batched workload: replay a captured HIP graph")
     ap.add_argument("--side", type=int, default=None, help="override the grid side (smoke runs)")
@@ -253,6 +255,14 @@ def serving_pool(n_requests, rate, seed=4, n_small=47, big_side=384, p_big=0.1):
     specs = W.batched_specs(count=n_small, meta_seed=seed + 100)
     fields = [W.batched_field(sp) for sp in specs]
     fields.append(W.gaussian_mixture((big_side,) * 3, seed + 200, n_gauss=8, noise=1e-3))
+    return fields, serving_requests(n_requests, rate, seed, n_small, p_big)
+
+
+def serving_requests(n_requests, rate, seed=4, n_small=47, p_big=0.1):
+    """(arrival_s, field index) pairs: Poisson arrivals at `rate`; index
+    n_small (the big field) with probability p_big, else uniform."""
+    import numpy as np
+
     rng = np.random.Generator(np.random.PCG64(seed))
     t = 0.0
     reqs = []
@@ -260,7 +270,7 @@ def serving_pool(n_requests, rate, seed=4, n_small=47, big_side=384, p_big=0.1):
         t += rng.exponential(1.0 / rate)
         fi = n_small if rng.random() < p_big else int(rng.integers(0, n_small))
         reqs.append((t, fi))
-    return fields, reqs
+    return reqs
 
 
 def run_serving(args):
@@ -281,16 +291,26 @@ def run_serving(args):
         caps[tuple(t.shape)] = {"cap_max": max(1, r.counts["maxima"]), "cap_sad": max(1, r.counts["saddles"]),
                                 "cap_arc": max(1, r.counts["arcs"])}
     torch.cuda.synchronize()
-    out = {}
-    for name, kw in [("continuous_batching", dict(max_batch=32, lanes=3, max_slots=96)),
-                     ("one_at_a_time", dict(max_batch=1, lanes=1, max_slots=1))]:
+    policies = [("continuous_batching", dict(max_batch=32, lanes=3, max_slots=96)),
+                ("one_at_a_time", dict(max_batch=1, lanes=1, max_slots=1))]
+    servers = {}
+    for name, kw in policies:
         srv = serving.Server(device=dev, caps_for=lambda sh: caps[sh], **kw)
         srv.prewarm([tuple(t.shape) for t in ts], per_shape=2 if kw["max_batch"] > 1 else 1)
-        # a short warm-up stream, then the measured one
-        srv.run(reqs[: min(50, len(reqs))], ts)
-        torch.cuda.synchronize()
-        st = srv.run(reqs, ts)
-        out[name] = st.summary()
+        srv.run(reqs[: min(50, len(reqs))], ts)  # warm-up stream
+        servers[name] = srv
+    torch.cuda.synchronize()
+
+    def measure(rq):
+        res = {}
+        for name, _ in policies:
+            torch.cuda.synchronize()
+            res[name] = servers[name].run(rq, ts).summary()
+        return res
+
+    out = measure(reqs)
+    # the same pool at an arrival rate above what the GPU sustains
+    sat = measure(serving_requests(args.requests, args.sat_rate))
     cb, fifo = out["continuous_batching"], out["one_at_a_time"]
     res = {
         "metric": METRIC,
@@ -311,6 +331,11 @@ def run_serving(args):
         "p99_ms": cb["p99_ms"],
         "serving": cb,
         "one_at_a_time": fifo,
+        "saturated": {"rate_hz": args.sat_rate,
+                      "continuous_batching": sat["continuous_batching"],
+                      "one_at_a_time": sat["one_at_a_time"],
+                      "throughput_ratio": sat["continuous_batching"]["vertices_per_s"] /
+                      sat["one_at_a_time"]["vertices_per_s"]},
         "field_gen_s": round(t_gen, 2),
     }
     print(json.dumps(res), flush=True)

@@ -8,11 +8,12 @@
 //      vertex order without a sort;
 //   2. k_arc_count: for every saddle, the highest vertex of each upper-link
 //      component (UpperLinkRep, Sec. 3.4), the label it reaches, and the
-//      ascending distinct set of those labels: the saddle's arcs (arcs form
-//      a set, Sec. 2); the count and the first four arcs are kept;
+//      number of distinct labels: the saddle's arcs (arcs form a set,
+//      Sec. 2); the four smallest are kept in registers and stored;
 //   3. k_scan_rows / k_arc_write: the CSR offsets from a scan of the counts,
-//      then the arcs (saddles with more than four distinct arcs, rare, are
-//      recomputed rather than stored);
+//      then the arcs (a saddle with more than four distinct arcs, rare, finds
+//      the rest in ascending order by one more pass over its components per
+//      arc);
 //   4. k_finalize: status and counts into the header.
 // No step uses an atomic: every position comes from a scan, so results do
 // not depend on scheduling.
@@ -278,14 +279,19 @@ __global__ __launch_bounds__(256) void k_mask_emit(Sel sel)
 
 // ------------------------------------------------------------------ arcs
 
-// The arcs of saddle v (Sec. 3.4, UpperLinkRep): the upper link split into
-// its components (bit-parallel BFS over the link edges), the highest vertex of
-// each (scanned in the order in which the later of two equal vertices wins),
-// and the label of that vertex.  The distinct labels are kept ascending in
-// list[0], list[256], ... (this thread's LDS column, room for K entries).
-// Returns their number; beta gets the number of components.
+// The neighbourhood of saddle v: order keys (0 outside the grid, below every
+// vertex) and linear offsets of the K Freudenthal rows, and the upper-link
+// mask (Alg. 1, Sec. 3.3).
 template <int NDIM, bool MINMODE>
-__device__ __forceinline__ int saddle_arcs(const ArcArgs& A, int v, const uint64_t* s_adj, uint32_t* list, int& beta)
+struct Nbhd {
+    static constexpr int K = Rows<NDIM>::K;
+    uint32_t us[K];
+    int offs[K];
+    uint64_t up;
+};
+
+template <int NDIM, bool MINMODE>
+__device__ __forceinline__ void load_nbhd(const ArcArgs& A, int v, Nbhd<NDIM, MINMODE>& nb)
 {
     constexpr Rows<NDIM> R = make_rows_ce<NDIM>();
     constexpr int K = Rows<NDIM>::K;
@@ -302,9 +308,7 @@ __device__ __forceinline__ int saddle_arcs(const ArcArgs& A, int v, const uint64
         }
     }
     const uint32_t uv = mode_key<MINMODE>(A.f[v]);
-    uint32_t us[K];
-    int offs[K];
-    uint64_t up = 0;
+    nb.up = 0;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         bool in = true;
@@ -317,37 +321,89 @@ __device__ __forceinline__ int saddle_arcs(const ArcArgs& A, int v, const uint64
                 off += d * st[i];
             }
         }
-        offs[j] = off;
-        const uint32_t u = in ? mode_key<MINMODE>(A.f[v + off]) : 0u;  // 0: below every vertex
-        us[j] = u;
+        nb.offs[j] = off;
+        const uint32_t u = in ? mode_key<MINMODE>(A.f[v + off]) : 0u;
+        nb.us[j] = u;
         const bool wins_tie = (j >= K / 2) != MINMODE;
-        up |= uint64_t(wins_tie ? (u >= uv) : (u > uv)) << j;
+        nb.up |= uint64_t(wins_tie ? (u >= uv) : (u > uv)) << j;
     }
-    int n = 0;
-    beta = 0;
-    for (uint64_t rem = up; rem;) {
+}
+
+// Calls f(label) for every upper-link component of saddle v: the label of
+// the component's highest vertex (UpperLinkRep, Sec. 3.4), the highest found
+// by scanning in the order in which the later of two equal vertices wins.
+// Components come from a bit-parallel BFS over the link edges.
+template <int NDIM, bool MINMODE, class F>
+__device__ __forceinline__ void for_each_arc_label(const ArcArgs& A, int v, const Nbhd<NDIM, MINMODE>& nb,
+                                                   const uint64_t* s_adj, F&& f)
+{
+    constexpr int K = Rows<NDIM>::K;
+    for (uint64_t rem = nb.up; rem;) {
         const uint64_t comp = closure(rem & (~rem + 1), rem, s_adj);
         rem &= ~comp;
-        ++beta;
         uint32_t best_u = 0;
         int best_off = 0;
 #pragma unroll
         for (int s = 0; s < K; ++s) {
             const int j = MINMODE ? K - 1 - s : s;
-            if (((comp >> j) & 1ull) && us[j] >= best_u) {
-                best_u = us[j];
-                best_off = offs[j];
+            if (((comp >> j) & 1ull) && nb.us[j] >= best_u) {
+                best_u = nb.us[j];
+                best_off = nb.offs[j];
             }
         }
-        const uint32_t L = (uint32_t)A.lab[v + best_off];
-        int p = 0;
-        while (p < n && list[p * 256] < L) ++p;
-        if (p < n && list[p * 256] == L) continue;
-        for (int q = n; q > p; --q) list[q * 256] = list[(q - 1) * 256];
-        list[p * 256] = L;
-        ++n;
+        f((uint32_t)A.lab[v + best_off]);
     }
-    return n;
+}
+
+// The four smallest distinct arc labels of a saddle, ascending (unused
+// entries ~0u; labels are vertex ids below 2^31).  `more` is set when the
+// saddle has further distinct labels above lo[3].
+struct Arcs4 {
+    uint32_t lo[4];
+    bool more;
+};
+
+template <int NDIM, bool MINMODE>
+__device__ __forceinline__ Arcs4 first_arcs(const ArcArgs& A, int v, const Nbhd<NDIM, MINMODE>& nb,
+                                            const uint64_t* s_adj, int& beta)
+{
+    Arcs4 r{{~0u, ~0u, ~0u, ~0u}, false};
+    beta = 0;
+    for_each_arc_label<NDIM, MINMODE>(A, v, nb, s_adj, [&](uint32_t L) {
+        ++beta;
+        if (L == r.lo[0] || L == r.lo[1] || L == r.lo[2] || L == r.lo[3]) return;
+        if (L > r.lo[3]) {  // a distinct label above a full list
+            r.more = true;
+            return;
+        }
+        if (r.lo[3] != ~0u) r.more = true;  // the list is full: its largest moves out
+        r.lo[3] = L;
+        // one insertion step keeps the list sorted
+        if (r.lo[3] < r.lo[2]) { const uint32_t t = r.lo[2]; r.lo[2] = r.lo[3]; r.lo[3] = t; }
+        if (r.lo[2] < r.lo[1]) { const uint32_t t = r.lo[1]; r.lo[1] = r.lo[2]; r.lo[2] = t; }
+        if (r.lo[1] < r.lo[0]) { const uint32_t t = r.lo[0]; r.lo[0] = r.lo[1]; r.lo[1] = t; }
+    });
+    return r;
+}
+
+// Distinct labels above `last`, ascending, one pass over the components
+// each: for saddles with more than four distinct arcs (rare).  Calls
+// emit(k, label) for the k-th of them and returns their number.
+template <int NDIM, bool MINMODE, class E>
+__device__ __forceinline__ uint32_t labels_above(const ArcArgs& A, int v, const Nbhd<NDIM, MINMODE>& nb,
+                                                 const uint64_t* s_adj, uint32_t last, E&& emit)
+{
+    uint32_t k = 0;
+    for (;;) {
+        uint32_t next = ~0u;
+        for_each_arc_label<NDIM, MINMODE>(A, v, nb, s_adj, [&](uint32_t L) {
+            if (L > last && L < next) next = L;
+        });
+        if (next == ~0u) return k;
+        emit(k, next);
+        ++k;
+        last = next;
+    }
 }
 
 template <int NDIM>
@@ -359,11 +415,11 @@ __device__ __forceinline__ void load_adj(uint64_t* s_adj)
     __syncthreads();
 }
 
-// Distinct-arc count, beta and the first two arcs of every saddle of the
+// Distinct-arc count, beta and the first four arcs of every saddle of the
 // block's chunk; the block's sums of both counts go to rows 2 and 3.
 template <int NDIM, bool MINMODE>
-__device__ __forceinline__ void arc_count_body(const ArcArgs& A, uint32_t blk, uint32_t nb, uint32_t* s_list,
-                                               uint64_t* s_adj, uint32_t* tmp)
+__device__ __forceinline__ void arc_count_body(const ArcArgs& A, uint32_t blk, uint32_t nb, uint64_t* s_adj,
+                                               uint32_t* tmp)
 {
     load_adj<NDIM>(s_adj);
     uint32_t lo, hi;
@@ -371,13 +427,17 @@ __device__ __forceinline__ void arc_count_body(const ArcArgs& A, uint32_t blk, u
     const int tid = threadIdx.x;
     uint32_t sc = 0, sb = 0;
     for (uint32_t i = lo + tid; i < hi; i += 256) {
+        const int v = A.saddles[i];
+        Nbhd<NDIM, MINMODE> h;
+        load_nbhd<NDIM, MINMODE>(A, v, h);
         int beta;
-        const int n = saddle_arcs<NDIM, MINMODE>(A, A.saddles[i], s_adj, s_list + tid, beta);
+        const Arcs4 r = first_arcs<NDIM, MINMODE>(A, v, h, s_adj, beta);
+        uint32_t n = (r.lo[0] != ~0u) + (r.lo[1] != ~0u) + (r.lo[2] != ~0u) + (r.lo[3] != ~0u);
+        if (r.more) n += labels_above<NDIM, MINMODE>(A, v, h, s_adj, r.lo[3], [](uint32_t, uint32_t) {});
         if (A.beta) A.beta[i] = beta;
-        A.offsets[i + 1] = n;  // the count until k_arc_write turns it into an offset
-        A.atmp[i] = make_uint4(s_list[tid], n > 1 ? s_list[256 + tid] : 0u, n > 2 ? s_list[512 + tid] : 0u,
-                               n > 3 ? s_list[768 + tid] : 0u);
-        sc += (uint32_t)n;
+        A.offsets[i + 1] = (int32_t)n;  // the count until k_arc_write turns it into an offset
+        A.atmp[i] = make_uint4(r.lo[0], r.lo[1], r.lo[2], r.lo[3]);
+        sc += n;
         sb += (uint32_t)beta;
     }
     sc = block_sum(sc, tmp);
@@ -389,8 +449,8 @@ __device__ __forceinline__ void arc_count_body(const ArcArgs& A, uint32_t blk, u
 }
 
 template <int NDIM, bool MINMODE>
-__device__ __forceinline__ void arc_write_body(const ArcArgs& A, uint32_t blk, uint32_t nb, uint32_t* s_list,
-                                               uint64_t* s_adj, uint32_t* tmp)
+__device__ __forceinline__ void arc_write_body(const ArcArgs& A, uint32_t blk, uint32_t nb, uint64_t* s_adj,
+                                               uint32_t* tmp)
 {
     load_adj<NDIM>(s_adj);
     uint32_t lo, hi;
@@ -405,17 +465,18 @@ __device__ __forceinline__ void arc_write_body(const ArcArgs& A, uint32_t blk, u
         uint32_t total;
         const uint32_t pos = run + block_excl_scan(n, tmp, total);
         if (valid) {
-            if (n <= 4) {
-                const uint4 t = A.atmp[i];
-                const uint32_t a4[4] = {t.x, t.y, t.z, t.w};
+            const uint4 t = A.atmp[i];
+            const uint32_t a4[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
-                for (uint32_t k = 0; k < 4; ++k)
-                    if (k < n && pos + k < A.cap_arc) A.arcs[pos + k] = (int32_t)a4[k];
-            } else {
-                int beta;
-                saddle_arcs<NDIM, MINMODE>(A, A.saddles[i], s_adj, s_list + tid, beta);
-                for (uint32_t k = 0; k < n; ++k)
-                    if (pos + k < A.cap_arc) A.arcs[pos + k] = (int32_t)s_list[k * 256 + tid];
+            for (uint32_t k = 0; k < 4; ++k)
+                if (k < n && pos + k < A.cap_arc) A.arcs[pos + k] = (int32_t)a4[k];
+            if (n > 4) {
+                const int v = A.saddles[i];
+                Nbhd<NDIM, MINMODE> h;
+                load_nbhd<NDIM, MINMODE>(A, v, h);
+                labels_above<NDIM, MINMODE>(A, v, h, s_adj, t.w, [&](uint32_t k, uint32_t L) {
+                    if (pos + 4 + k < A.cap_arc) A.arcs[pos + 4 + k] = (int32_t)L;
+                });
             }
             A.offsets[i + 1] = (int32_t)(pos + n);
         }
@@ -426,23 +487,21 @@ __device__ __forceinline__ void arc_write_body(const ArcArgs& A, uint32_t blk, u
 template <int NDIM, bool MINMODE>
 __global__ __launch_bounds__(256) void k_arc_count(OneField sel)
 {
-    __shared__ uint32_t s_list[Rows<NDIM>::K * 256];
     __shared__ uint64_t s_adj[Rows<NDIM>::K];
     __shared__ uint32_t tmp[4];
     uint32_t blk, nb;
     const ArcArgs A = sel.locate(blk, nb);  // a copy: loop loads cannot alias it
-    arc_count_body<NDIM, MINMODE>(A, blk, nb, s_list, s_adj, tmp);
+    arc_count_body<NDIM, MINMODE>(A, blk, nb, s_adj, tmp);
 }
 
 template <int NDIM, bool MINMODE>
 __global__ __launch_bounds__(256) void k_arc_write(OneField sel)
 {
-    __shared__ uint32_t s_list[Rows<NDIM>::K * 256];
     __shared__ uint64_t s_adj[Rows<NDIM>::K];
     __shared__ uint32_t tmp[4];
     uint32_t blk, nb;
     const ArcArgs A = sel.locate(blk, nb);  // a copy: loop loads cannot alias it
-    arc_write_body<NDIM, MINMODE>(A, blk, nb, s_list, s_adj, tmp);
+    arc_write_body<NDIM, MINMODE>(A, blk, nb, s_adj, tmp);
 }
 
 // Batches hold 2D and 3D fields of either graph: the body is chosen per
@@ -450,7 +509,6 @@ __global__ __launch_bounds__(256) void k_arc_write(OneField sel)
 template <bool WRITE>
 __global__ __launch_bounds__(256) void k_arc_batched(BatchFields sel)
 {
-    __shared__ uint32_t s_list[14 * 256];
     __shared__ uint64_t s_adj[14];
     __shared__ uint32_t tmp[4];
     uint32_t blk, nb;
@@ -458,9 +516,9 @@ __global__ __launch_bounds__(256) void k_arc_batched(BatchFields sel)
     const int kind = __builtin_amdgcn_readfirstlane((A.ndim == 3 ? 2 : 0) + (A.minima ? 1 : 0));
 #define EG_BODY(ND, MM)                                                  \
     if (WRITE)                                                           \
-        arc_write_body<ND, MM>(A, blk, nb, s_list, s_adj, tmp);          \
+        arc_write_body<ND, MM>(A, blk, nb, s_adj, tmp);                  \
     else                                                                 \
-        arc_count_body<ND, MM>(A, blk, nb, s_list, s_adj, tmp);
+        arc_count_body<ND, MM>(A, blk, nb, s_adj, tmp);
     switch (kind) {
         case 0: EG_BODY(2, false) break;
         case 1: EG_BODY(2, true) break;

@@ -287,11 +287,18 @@ hipError_t launch_labels(const Grid& g, int32_t* lab, const Work& w, const Tunin
     const uint32_t cap = (uint32_t)w.cap_exit;
     const int64_t ewant = (w.cap_exit + 255) / 256;
     const int eblocks = (int)(ewant < 2048 ? (ewant > 0 ? ewant : 1) : 2048);
+    // later passes usually find their flag clear and return at once: smaller
+    // grids keep those launches cheap
+    const int eblocks_late = eblocks < 1024 ? eblocks : 1024;
+    // the first pass reads entries that other threads of the same pass have
+    // already advanced, which shortens long chains: it needs every entry
+    // initialised first
     hipLaunchKernelGGL(k_exit_init, dim3(eblocks), dim3(256), 0, s, w.exits, w.exres, lab, w.ctr, cap);
     for (int p = 0; p < tu.passes; ++p)
-        hipLaunchKernelGGL(k_exit_jump, dim3(eblocks), dim3(256), 0, s, w.exres, lab, N, w.ctr, cap, p, tu.hops);
+        hipLaunchKernelGGL(k_exit_jump, dim3(p == 0 ? eblocks : eblocks_late), dim3(256), 0, s, w.exres, lab, N,
+                           w.ctr, cap, p, tu.hops);
     const int64_t want = ((int64_t)N / 4 + 255) / 256;
-    const int blocks = (int)(want < 8192 ? (want > 0 ? want : 1) : 8192);
+    const int blocks = (int)(want < 2048 ? (want > 0 ? want : 1) : 2048);
     int p = 0;
     if (g.ndim == 2 || g.ndim == 3) {
         // pass 0 in tile order (the classification wrote exit-list codes)

@@ -219,6 +219,29 @@ def test_batched_with_tuning():
         assert_same(_result_np(r), O.extremum_graph(f), KEYS, f"batched tuned {f.shape}")
 
 
+@pytest.mark.parametrize("shape", [(8, 8, 8, 8, 8), (12, 12, 12, 12), (40, 40, 40)])
+def test_saddles_with_more_than_four_arcs(shape):
+    """The arc kernels keep the four smallest distinct arcs of a saddle in
+    registers and find any further ones by extra passes: white noise has
+    saddles with five and six distinct arcs in 3D, 4D and 5D."""
+    f = W.random_field(shape, 5, "uniform")
+    for minima in (False, True):
+        want = O.extremum_graph(f, minima)
+        assert np.diff(want["arc_offsets"]).max() > 4  # the case is present
+        assert_same(gpu_graph(f, minima), want, KEYS + ["ptr"], f"{shape} minima={minima}")
+
+
+def test_batched_saddles_with_more_than_four_arcs():
+    import torch
+    from paper_2303_02724_amd import eg
+    fields = [W.random_field((40, 40, 40), 5, "uniform"), W.random_field((300, 200), 6, "uniform")]
+    ts = [torch.from_numpy(f).cuda() for f in fields]
+    for minima in (False, True):
+        res = eg.BatchBuilder([f.shape for f in fields], minima=minima).run(ts)
+        for f, r in zip(fields, res):
+            assert_same(_result_np(r), O.extremum_graph(f, minima), KEYS, f"batched {f.shape} minima={minima}")
+
+
 def test_batched_long_paths_several_passes():
     """Paths far longer than a tile and than the links one pass follows
     (16 here): the exit-list chains need several gated jump passes before the
