@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--minima", action="store_true", help="minimum graph instead of maximum graph")
     ap.add_argument("--stage-reps", type=int, default=20, help="repetitions for the per-stage timings")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (library default tile shape and links per pass)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB three times (a reference for HBM byte counters)")
     ap.add_argument("--cpu-planes", type=int, default=None,
@@ -382,7 +384,17 @@ def main():
             torch.cuda.synchronize()
         del src, dst
 
-    b = eg.Builder(f.shape, minima=args.minima, device=dev)
+    # the autotuner picks the launch configuration on this field (untimed);
+    # every choice gives identical results
+    tuning, tune_ms = 0, None
+    if not args.no_tune:
+        from paper_2303_02724_amd import tune
+
+        tr = tune.tune(t, minima=args.minima, reps=5, path=None)
+        tuning, tune_ms = tr["tuning"], tr["times_ms"]
+        torch.cuda.empty_cache()
+
+    b = eg.Builder(f.shape, minima=args.minima, device=dev, tuning=tuning)
     res = b.run(t)  # sizes the buffers (untimed)
     counts = dict(res.counts)
     counts["jump_passes"] = res.passes
@@ -442,6 +454,7 @@ def main():
         "gpu_event_ms_per_step": gpu_ms / args.steps,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "counts": counts,
+        "tuning": {"choice": hex(tuning), "candidates_ms": {hex(k): round(v, 4) for k, v in (tune_ms or {}).items()}},
         "h2d_ms": round(h2d_s * 1e3, 3),
         "field_gen_s": round(t_gen, 2),
     }

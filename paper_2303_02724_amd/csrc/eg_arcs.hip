@@ -9,11 +9,11 @@
 //   2. k_arc_count: for every saddle, the highest vertex of each upper-link
 //      component (UpperLinkRep, Sec. 3.4), the label it reaches, and the
 //      number of distinct labels: the saddle's arcs (arcs form a set,
-//      Sec. 2); the four smallest are kept in registers and stored;
+//      Sec. 2); the smallest are kept in registers (four are stored);
 //   3. k_scan_rows / k_arc_write: the CSR offsets from a scan of the counts,
-//      then the arcs (a saddle with more than four distinct arcs, rare, finds
-//      the rest in ascending order by one more pass over its components per
-//      arc);
+//      then the arcs (a saddle with more distinct arcs than the register
+//      list holds, rare, finds the rest in ascending order by one more pass
+//      over its components per arc);
 //   4. k_finalize: status and counts into the header.
 // No step uses an atomic: every position comes from a scan, so results do
 // not depend on scheduling.
@@ -355,33 +355,47 @@ __device__ __forceinline__ void for_each_arc_label(const ArcArgs& A, int v, cons
     }
 }
 
-// The four smallest distinct arc labels of a saddle, ascending (unused
-// entries ~0u; labels are vertex ids below 2^31).  `more` is set when the
-// saddle has further distinct labels above lo[3].
-struct Arcs4 {
-    uint32_t lo[4];
+// The S smallest distinct arc labels of a saddle, ascending (unused entries
+// ~0u; labels are vertex ids below 2^31).  `more` is set when the saddle has
+// further distinct labels above lo[S-1].  S = 4 in 2D/3D (at most 3 and 6
+// components), 8 in 4D/5D, where more components are common.
+template <int NDIM>
+struct ArcList {
+    static constexpr int S = NDIM >= 4 ? 8 : 4;
+    uint32_t lo[S];
     bool more;
 };
 
 template <int NDIM, bool MINMODE>
-__device__ __forceinline__ Arcs4 first_arcs(const ArcArgs& A, int v, const Nbhd<NDIM, MINMODE>& nb,
-                                            const uint64_t* s_adj, int& beta)
+__device__ __forceinline__ ArcList<NDIM> first_arcs(const ArcArgs& A, int v, const Nbhd<NDIM, MINMODE>& nb,
+                                                    const uint64_t* s_adj, int& beta)
 {
-    Arcs4 r{{~0u, ~0u, ~0u, ~0u}, false};
+    constexpr int S = ArcList<NDIM>::S;
+    ArcList<NDIM> r;
+#pragma unroll
+    for (int k = 0; k < S; ++k) r.lo[k] = ~0u;
+    r.more = false;
     beta = 0;
     for_each_arc_label<NDIM, MINMODE>(A, v, nb, s_adj, [&](uint32_t L) {
         ++beta;
-        if (L == r.lo[0] || L == r.lo[1] || L == r.lo[2] || L == r.lo[3]) return;
-        if (L > r.lo[3]) {  // a distinct label above a full list
+        bool dup = false;
+#pragma unroll
+        for (int k = 0; k < S; ++k) dup |= L == r.lo[k];
+        if (dup) return;
+        if (L > r.lo[S - 1]) {  // a distinct label above a full list
             r.more = true;
             return;
         }
-        if (r.lo[3] != ~0u) r.more = true;  // the list is full: its largest moves out
-        r.lo[3] = L;
+        if (r.lo[S - 1] != ~0u) r.more = true;  // the list is full: its largest moves out
+        r.lo[S - 1] = L;
         // one insertion step keeps the list sorted
-        if (r.lo[3] < r.lo[2]) { const uint32_t t = r.lo[2]; r.lo[2] = r.lo[3]; r.lo[3] = t; }
-        if (r.lo[2] < r.lo[1]) { const uint32_t t = r.lo[1]; r.lo[1] = r.lo[2]; r.lo[2] = t; }
-        if (r.lo[1] < r.lo[0]) { const uint32_t t = r.lo[0]; r.lo[0] = r.lo[1]; r.lo[1] = t; }
+#pragma unroll
+        for (int k = S - 1; k > 0; --k)
+            if (r.lo[k] < r.lo[k - 1]) {
+                const uint32_t t = r.lo[k - 1];
+                r.lo[k - 1] = r.lo[k];
+                r.lo[k] = t;
+            }
     });
     return r;
 }
@@ -431,9 +445,12 @@ __device__ __forceinline__ void arc_count_body(const ArcArgs& A, uint32_t blk, u
         Nbhd<NDIM, MINMODE> h;
         load_nbhd<NDIM, MINMODE>(A, v, h);
         int beta;
-        const Arcs4 r = first_arcs<NDIM, MINMODE>(A, v, h, s_adj, beta);
-        uint32_t n = (r.lo[0] != ~0u) + (r.lo[1] != ~0u) + (r.lo[2] != ~0u) + (r.lo[3] != ~0u);
-        if (r.more) n += labels_above<NDIM, MINMODE>(A, v, h, s_adj, r.lo[3], [](uint32_t, uint32_t) {});
+        const ArcList<NDIM> r = first_arcs<NDIM, MINMODE>(A, v, h, s_adj, beta);
+        constexpr int S = ArcList<NDIM>::S;
+        uint32_t n = 0;
+#pragma unroll
+        for (int k = 0; k < S; ++k) n += r.lo[k] != ~0u;
+        if (r.more) n += labels_above<NDIM, MINMODE>(A, v, h, s_adj, r.lo[S - 1], [](uint32_t, uint32_t) {});
         if (A.beta) A.beta[i] = beta;
         A.offsets[i + 1] = (int32_t)n;  // the count until k_arc_write turns it into an offset
         A.atmp[i] = make_uint4(r.lo[0], r.lo[1], r.lo[2], r.lo[3]);
@@ -471,12 +488,25 @@ __device__ __forceinline__ void arc_write_body(const ArcArgs& A, uint32_t blk, u
             for (uint32_t k = 0; k < 4; ++k)
                 if (k < n && pos + k < A.cap_arc) A.arcs[pos + k] = (int32_t)a4[k];
             if (n > 4) {
+                // past the four stored arcs: the list again, then (beyond
+                // its S entries) ascending selection
                 const int v = A.saddles[i];
                 Nbhd<NDIM, MINMODE> h;
                 load_nbhd<NDIM, MINMODE>(A, v, h);
-                labels_above<NDIM, MINMODE>(A, v, h, s_adj, t.w, [&](uint32_t k, uint32_t L) {
-                    if (pos + 4 + k < A.cap_arc) A.arcs[pos + 4 + k] = (int32_t)L;
-                });
+                constexpr int S = ArcList<NDIM>::S;
+                uint32_t last = t.w;
+                if constexpr (S > 4) {
+                    int beta;
+                    const ArcList<NDIM> r = first_arcs<NDIM, MINMODE>(A, v, h, s_adj, beta);
+#pragma unroll
+                    for (uint32_t k = 4; k < (uint32_t)S; ++k)
+                        if (k < n && pos + k < A.cap_arc) A.arcs[pos + k] = (int32_t)r.lo[k];
+                    last = r.lo[S - 1];
+                }
+                if (n > (uint32_t)S)
+                    labels_above<NDIM, MINMODE>(A, v, h, s_adj, last, [&](uint32_t k, uint32_t L) {
+                        if (pos + S + k < A.cap_arc) A.arcs[pos + S + k] = (int32_t)L;
+                    });
             }
             A.offsets[i + 1] = (int32_t)(pos + n);
         }

@@ -242,6 +242,41 @@ def test_batched_saddles_with_more_than_four_arcs():
             assert_same(_result_np(r), O.extremum_graph(f, minima), KEYS, f"batched {f.shape} minima={minima}")
 
 
+def test_batched_graph_replays_match_eager():
+    """eg_build_batched captured in a HIP graph: every replay, with other
+    device work and synchronisation between replays, gives the eager result
+    (the library clears its counters with kernels, never with memsets)."""
+    import torch
+    from paper_2303_02724_amd import eg
+    specs = W.batched_specs(count=9, side2=(40, 260), side3=(16, 44), meta_seed=31)
+    fields = [W.batched_field(sp) for sp in specs]
+    ts = [torch.from_numpy(f).cuda() for f in fields]
+    bb = eg.BatchBuilder([f.shape for f in fields])
+    eager = [_result_np(r) for r in bb.run(ts)]  # sizes the buffers, plans
+    want = [O.extremum_graph(f) for f in fields]
+    for e, o, f in zip(eager, want, fields):
+        assert_same(e, o, KEYS, f"eager {f.shape}")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        bb.launch(stream=side)  # warm the capture stream
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        bb.launch(stream=side)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for b in bb.builders:  # scribble on every output between replays
+            b.labels.fill_(-7)
+            b.arcs.fill_(-7)
+            b.header.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for b, e, f in zip(bb.builders, eager, fields):
+            assert_same(_result_np(b.finish()), e, KEYS, f"replay {rep} {f.shape}")
+
+
 def test_batched_long_paths_several_passes():
     """Paths far longer than a tile and than the links one pass follows
     (16 here): the exit-list chains need several gated jump passes before the
