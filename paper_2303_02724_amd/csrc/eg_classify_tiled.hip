@@ -76,13 +76,16 @@ __device__ __forceinline__ int tile_to_global(int n, int x0, int y0, int z0, int
     return (z0 + lz) * SZ + (y0 + ly) * SY + x0 + lx;
 }
 
-// Resolve the tile's successor array by pointer doubling.  cur[k] holds the
+// Resolve the tile's successor array by pointer jumping.  cur[k] holds the
 // successor of this thread's k-th vertex (s_idx(k) is its tile index): >= 0 a
 // tile index (a maximum is its own successor), < 0 the exit code of the first
 // vertex outside the tile.  Each round replaces every successor by the
-// successor's successor, so log2 of the longest in-tile path bounds the
-// rounds.  On return cur[k] is a tile-local maximum (>= 0) or an exit code.
-// Must be called by the whole workgroup, after s_nxt holds every successor.
+// successor's successor, in place: a value read is always a vertex further
+// along the same path (or its end), so a round needs no barrier between its
+// reads and writes, and only changed entries are written.  log2 of the
+// longest in-tile path bounds the rounds.  On return cur[k] is a tile-local
+// maximum (>= 0) or an exit code.  Must be called by the whole workgroup,
+// after s_nxt holds every successor.
 template <int VPT, class Idx>
 __device__ __forceinline__ void double_tile_chains(int (&cur)[VPT], int32_t* s_nxt, Idx s_idx)
 {
@@ -93,13 +96,13 @@ __device__ __forceinline__ void double_tile_chains(int (&cur)[VPT], int32_t* s_n
             const int n = cur[k];
             if (n >= 0) {
                 const int m = s_nxt[n];
-                changed |= m != n;
-                cur[k] = m;
+                if (m != n) {
+                    changed = 1;
+                    cur[k] = m;
+                    s_nxt[s_idx(k)] = m;
+                }
             }
         }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < VPT; ++k) s_nxt[s_idx(k)] = cur[k];
         if (!__syncthreads_or(changed)) break;
     }
 }
