@@ -28,6 +28,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "vertices/s + HBM GB/s for extremum graph (512³ f32); batched p99 latency"
+VALU_PEAK_GINSTS = 256 * 4 * 2.4 / 4  # G wave64 VALU instructions/s (SIMD16: 4 cycles each)
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per vertex: classify reads f and writes the pointer;
 # the whole path reads f, writes pointers, reads them and writes labels
@@ -93,6 +94,26 @@ def recorded_traffic(kernel: str, workload: str):
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def recorded_valu(kernel: str, workload: str):
+    """VALU instructions (wave64) per launch from the committed counter
+    summary, if it was taken on the current kernel sources (else None)."""
+    p = os.path.join(ROOT, "profiles", f"valu_{kernel}_{workload}.txt")
+    if not os.path.exists(p):
+        return None
+    vals = {}
+    with open(p) as fh:
+        for line in fh:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != kernel_source_hash(kernel):
+        return None
+    try:
+        return float(vals["sq_insts_valu_per_launch"])
     except (KeyError, ValueError):
         return None
 
@@ -434,6 +455,14 @@ def main():
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes,
             "avg_launch_ms": round(cls_ms, 4), "dominant_stage": dom, "dominant_stage_kernel": kernel_name}
+    # what actually limits the kernel: vector instruction issue (counted
+    # wave64 instructions of one launch over its measured duration, against
+    # 256 CUs x 4 SIMDs x 2.4 GHz with a wave64 instruction every 4 cycles)
+    valu = recorded_valu("k_classify", cfg["workload"])
+    if valu is not None:
+        rate = valu / (cls_ms * 1e-3) / 1e9
+        roof["valu_issue"] = {"insts_per_launch": valu, "achieved": round(rate, 1), "peak": VALU_PEAK_GINSTS,
+                              "unit": "G wave64 instructions/s", "frac": round(rate / VALU_PEAK_GINSTS, 4)}
 
     out = {
         "metric": METRIC,

@@ -124,7 +124,7 @@ typedef struct eg_out {
  * Workspace bytes that eg_build needs for a field of the given shape and the
  * given saddle capacity (eg_out.cap_sad; the other capacities do not enter):
  * about 4.25 bytes per vertex (more when the last axis is much shorter than
- * 64) plus 16 bytes per saddle slot.  Pure,
+ * 64; 4 more for 1D, 4D and 5D grids) plus 16 bytes per saddle slot.  Pure,
  * host-only.  Returns 0 on invalid arguments (ndim outside [1, EG_MAX_NDIM],
  * a dim < 1, N >= 2^31, a capacity outside [0, 2^31)).
  */

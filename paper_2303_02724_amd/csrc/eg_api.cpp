@@ -60,10 +60,10 @@ eg_status check_one(const float* field, int ndim, const int64_t* dims, const eg_
     if ((o->cap_max > 0 && !o->maxima) || (o->cap_sad > 0 && !o->saddles) || (o->cap_arc > 0 && !o->arc_maxima))
         return EG_ERR_ARG;
     const int64_t X = g->dims[g->ndim - 1];
-    const Work need = carve(nullptr, g->N, X, o->cap_sad);
+    const Work need = carve(nullptr, g->ndim, g->N, X, o->cap_sad);
     if (!o->workspace || (reinterpret_cast<uintptr_t>(o->workspace) & 255u) || o->ws_bytes < need.bytes)
         return EG_ERR_WORKSPACE;
-    *w = carve(o->workspace, g->N, X, o->cap_sad);
+    *w = carve(o->workspace, g->ndim, g->N, X, o->cap_sad);
     return EG_OK;
 }
 
@@ -250,7 +250,7 @@ size_t eg_workspace_bytes(int ndim, const int64_t* dims, int64_t cap_sad)
     Grid g;
     if (!grid_from(ndim, dims, &g)) return 0;
     if (!caps_ok(0, cap_sad, 0)) return 0;
-    return carve(nullptr, g.N, g.dims[ndim - 1], cap_sad).bytes;
+    return carve(nullptr, ndim, g.N, g.dims[ndim - 1], cap_sad).bytes;
 }
 
 eg_status eg_build(const float* field, int ndim, const int64_t* dims, void* stream, const eg_out* out)

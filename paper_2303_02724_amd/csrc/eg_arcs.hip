@@ -307,7 +307,10 @@ __device__ __forceinline__ void load_nbhd(const ArcArgs& A, int v, Nbhd<NDIM, MI
             stride *= d;
         }
     }
-    const uint32_t uv = mode_key<MINMODE>(A.f[v]);
+    // keys stored by classification already carry the reversal of the
+    // minimum graph
+    const bool stored = A.keys != nullptr;
+    const uint32_t uv = stored ? A.keys[v] : mode_key<MINMODE>(A.f[v]);
     nb.up = 0;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -322,7 +325,7 @@ __device__ __forceinline__ void load_nbhd(const ArcArgs& A, int v, Nbhd<NDIM, MI
             }
         }
         nb.offs[j] = off;
-        const uint32_t u = in ? mode_key<MINMODE>(A.f[v + off]) : 0u;
+        const uint32_t u = !in ? 0u : stored ? A.keys[v + off] : mode_key<MINMODE>(A.f[v + off]);
         nb.us[j] = u;
         const bool wins_tie = (j >= K / 2) != MINMODE;
         nb.up |= uint64_t(wins_tie ? (u >= uv) : (u > uv)) << j;
@@ -598,6 +601,7 @@ ArcArgs arc_args(const float* f, const Grid& g, const eg_out& o, const Work& w)
 {
     ArcArgs a{};
     a.f = gptr(f);
+    a.keys = gptr<const uint32_t>(w.keys);
     a.lab = gptr<const int32_t>(o.labels);
     a.mmask = gptr<const uint64_t>(w.mmask);
     a.smask = gptr<const uint64_t>(w.smask);

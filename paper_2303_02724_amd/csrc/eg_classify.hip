@@ -27,7 +27,7 @@ hipError_t launch_init(uint32_t* ctr, int32_t* header, hipStream_t s)
 // Visit the closed neighbourhood of v in the order in which later vertices
 // win ties; fills the upper-link mask and the steepest-ascent target.
 template <int NDIM, bool MINMODE>
-__device__ __forceinline__ void scan_neighbourhood(const float* __restrict__ f, const LinkTable& t, int v,
+__device__ __forceinline__ void scan_neighbourhood(const uint32_t* __restrict__ keys, const LinkTable& t, int v,
                                                    uint32_t bits, uint32_t uv, uint64_t& up, int& best)
 {
     constexpr int K = 2 * ((1 << NDIM) - 1);
@@ -36,7 +36,7 @@ __device__ __forceinline__ void scan_neighbourhood(const float* __restrict__ f, 
     auto visit = [&](int j) {
         if ((bits & t.forb[j]) == 0) {
             const int u_id = v + t.lin[j];
-            const uint32_t u = mode_key<MINMODE>(f[u_id]);
+            const uint32_t u = keys[u_id];
             const bool above = row_wins_tie<MINMODE>(j, K) ? (u >= uv) : (u > uv);
             up |= uint64_t(above) << j;
             if (u >= best_u) {
@@ -109,11 +109,25 @@ __device__ __forceinline__ void mask_or(bool pred, int64_t word, int bit, uint64
     if (lead && word >= 0 && bits) atomicOr((unsigned long long*)&mask[word], (unsigned long long)bits);
 }
 
+// Order keys of every vertex (reversed for the minimum graph), once, for the
+// grids whose classification reads neighbours from memory; NaN is flagged.
+template <bool MINMODE>
+__global__ __launch_bounds__(256) void k_keys(const float* __restrict__ f, int N, uint32_t* __restrict__ keys,
+                                              uint32_t* __restrict__ ctr)
+{
+    bool nan = false;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        const float x = f[i];
+        nan |= x != x;
+        keys[i] = mode_key<MINMODE>(x);
+    }
+    if (__ballot(nan) != 0 && __lane_id() == 0) atomicOr(&ctr[C_NAN], 1u);
+}
+
 template <int NDIM, bool MINMODE>
-__global__ __launch_bounds__(256) void k_classify_generic(const float* __restrict__ f, Grid g, LinkTable t,
+__global__ __launch_bounds__(256) void k_classify_generic(const uint32_t* __restrict__ keys, Grid g, LinkTable t,
                                                           int32_t* __restrict__ lab, int32_t* __restrict__ ptr,
-                                                          uint32_t* __restrict__ ctr, uint64_t* __restrict__ mmask,
-                                                          uint64_t* __restrict__ smask)
+                                                          uint64_t* __restrict__ mmask, uint64_t* __restrict__ smask)
 {
     constexpr int K = 2 * ((1 << NDIM) - 1);
     __shared__ uint64_t s_adj[K];
@@ -121,15 +135,13 @@ __global__ __launch_bounds__(256) void k_classify_generic(const float* __restric
     __syncthreads();
 
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    bool is_max = false, is_sad = false, nan = false;
+    bool is_max = false, is_sad = false;
     if (v < g.N) {
         const uint32_t bits = boundary_bits<NDIM>(g, v);
-        const float fv = f[v];
-        nan = fv != fv;
-        const uint32_t uv = mode_key<MINMODE>(fv);
+        const uint32_t uv = keys[v];
         uint64_t up = 0;
         int best;
-        scan_neighbourhood<NDIM, MINMODE>(f, t, v, bits, uv, up, best);
+        scan_neighbourhood<NDIM, MINMODE>(keys, t, v, bits, uv, up, best);
         is_max = up == 0;
         if (!is_max) is_sad = closure(up & (~up + 1), up, s_adj) != up;
         lab[v] = is_max ? v : -(best + 1);  // final label, or "same as best"
@@ -141,7 +153,6 @@ __global__ __launch_bounds__(256) void k_classify_generic(const float* __restric
     const int64_t word = v < g.N ? (int64_t)row * ((X + 63) >> 6) + (x >> 6) : -1;
     mask_or(is_max, word, x & 63, mmask);
     mask_or(is_sad, word, x & 63, smask);
-    if (__ballot(nan) != 0 && __lane_id() == 0) atomicOr(&ctr[C_NAN], 1u);
 }
 
 template <int NDIM, bool MINMODE>
@@ -151,8 +162,11 @@ static void launch_classify_t(const float* f, const Grid& g, const LinkTable& t,
     const int64_t zwant = (w.words + 255) / 256;
     const int zblocks = (int)(zwant < 4096 ? (zwant > 0 ? zwant : 1) : 4096);
     hipLaunchKernelGGL(k_zero_words, dim3(zblocks), dim3(256), 0, s, w.mmask, w.smask, w.words);
+    const int64_t kwant = ((int64_t)g.N + 255) / 256;
+    const int kblocks = (int)(kwant < 8192 ? kwant : 8192);
+    hipLaunchKernelGGL(k_keys<MINMODE>, dim3(kblocks), dim3(256), 0, s, f, g.N, w.keys, w.ctr);
     const int blocks = (int)((g.N + 255) / 256);
-    hipLaunchKernelGGL((k_classify_generic<NDIM, MINMODE>), dim3(blocks), dim3(256), 0, s, f, g, t, lab, ptr, w.ctr,
+    hipLaunchKernelGGL((k_classify_generic<NDIM, MINMODE>), dim3(blocks), dim3(256), 0, s, w.keys, g, t, lab, ptr,
                        w.mmask, w.smask);
 }
 

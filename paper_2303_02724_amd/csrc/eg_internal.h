@@ -96,6 +96,7 @@ struct Work {
     uint4* atmp;      // [cap_sad] the first four arcs of every saddle
     uint32_t* exits;  // [cap_exit] exit vertices published by the tiles
     int32_t* exres;   // [cap_exit] their labels while being resolved
+    uint32_t* keys;   // [N] order keys of the untiled grids (1D, 4D, 5D); else null
     int64_t words;
     int64_t cap_exit;
     size_t bytes;
@@ -132,6 +133,7 @@ struct TileArgs {
 // Everything stage (d) needs to know about its field.
 struct ArcArgs {
     EG_GPTR(const float) f;
+    EG_GPTR(const uint32_t) keys;  // order keys when classification stored them, else null
     EG_GPTR(const int32_t) lab;
     EG_GPTR(const uint64_t) mmask;
     EG_GPTR(const uint64_t) smask;
@@ -182,7 +184,7 @@ int make_rows(int ndim, int8_t (*off)[EG_MAX_NDIM], uint64_t* adj);
 void make_table(const Grid& g, LinkTable* t);
 // Host: carve (or size, when base == nullptr) the workspace of a grid with N
 // vertices.
-Work carve(void* base, int64_t N, int64_t X, int64_t cap_sad);
+Work carve(void* base, int ndim, int64_t N, int64_t X, int64_t cap_sad);
 // Exit-list capacity for a grid of N vertices (label codes need N + cap < 2^31).
 int64_t exit_capacity(int64_t N);
 // Bits needed to hold any vertex id of a grid with N vertices.

@@ -92,7 +92,7 @@ int64_t exit_capacity(int64_t N)
     return std::max<int64_t>(0, std::min(cap, room));
 }
 
-Work carve(void* base, int64_t N, int64_t X, int64_t cap_sad)
+Work carve(void* base, int ndim, int64_t N, int64_t X, int64_t cap_sad)
 {
     Work w{};
     w.cap_exit = exit_capacity(N);
@@ -110,6 +110,10 @@ Work carve(void* base, int64_t N, int64_t X, int64_t cap_sad)
     const size_t o_at = take(sizeof(uint4) * (size_t)std::max<int64_t>(cap_sad, 1));
     const size_t o_ex = take(sizeof(uint32_t) * (size_t)std::max<int64_t>(w.cap_exit, 1));
     const size_t o_er = take(sizeof(int32_t) * (size_t)std::max<int64_t>(w.cap_exit, 1));
+    // grids without LDS tiles read every neighbour from memory: their order
+    // keys are computed once, before classification
+    const bool untiled = ndim != 2 && ndim != 3;
+    const size_t o_k = untiled ? take(sizeof(uint32_t) * (size_t)N) : 0;
     w.bytes = off;
     if (base) {
         char* p = (char*)base;
@@ -120,6 +124,7 @@ Work carve(void* base, int64_t N, int64_t X, int64_t cap_sad)
         w.atmp = (uint4*)(p + o_at);
         w.exits = (uint32_t*)(p + o_ex);
         w.exres = (int32_t*)(p + o_er);
+        w.keys = untiled ? (uint32_t*)(p + o_k) : nullptr;
     }
     return w;
 }
