@@ -78,10 +78,11 @@ def kernel_source_hash(kernel: str = "k_classify") -> str:
     return h.hexdigest()
 
 
-def recorded_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel sources (otherwise None)."""
-    p = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+def recorded_counter(prefix: str, key: str, kernel: str, workload: str, tile3: int):
+    """A per-launch figure from a committed counter summary
+    (profiles/<prefix>_<kernel>_<workload>.txt), used only if the summary was
+    taken on the current kernel sources and the same tile shape (else None)."""
+    p = os.path.join(ROOT, "profiles", f"{prefix}_{kernel}_{workload}.txt")
     if not os.path.exists(p):
         return None
     vals = {}
@@ -93,27 +94,7 @@ def recorded_traffic(kernel: str, workload: str):
     if vals.get("source_sha256") != kernel_source_hash(kernel):
         return None
     try:
-        return float(vals["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
-
-
-def recorded_valu(kernel: str, workload: str):
-    """VALU instructions (wave64) per launch from the committed counter
-    summary, if it was taken on the current kernel sources (else None)."""
-    p = os.path.join(ROOT, "profiles", f"valu_{kernel}_{workload}.txt")
-    if not os.path.exists(p):
-        return None
-    vals = {}
-    with open(p) as fh:
-        for line in fh:
-            if ":" in line:
-                k, v = line.split(":", 1)
-                vals[k.strip()] = v.strip()
-    if vals.get("source_sha256") != kernel_source_hash(kernel):
-        return None
-    try:
-        return float(vals["sq_insts_valu_per_launch"])
+        return float(vals[f"tile3_{tile3}_{key}"])
     except (KeyError, ValueError):
         return None
 
@@ -450,7 +431,8 @@ def main():
     cls_ms = stages["classify"]
     alg_bytes = CLASSIFY_BYTES_PER_VERTEX * N
     achieved = alg_bytes / (cls_ms * 1e-3) / 1e9
-    traffic = recorded_traffic("k_classify", cfg["workload"])
+    tile3 = tuning & 0xF
+    traffic = recorded_counter("traffic", "traffic_bytes_per_launch", "k_classify", cfg["workload"], tile3)
     roof = {"bound": "hbm", "kernel": "k_classify (stages a + c)", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes,
@@ -458,7 +440,7 @@ def main():
     # what actually limits the kernel: vector instruction issue (counted
     # wave64 instructions of one launch over its measured duration, against
     # 256 CUs x 4 SIMDs x 2.4 GHz with a wave64 instruction every 4 cycles)
-    valu = recorded_valu("k_classify", cfg["workload"])
+    valu = recorded_counter("valu", "sq_insts_valu_per_launch", "k_classify", cfg["workload"], tile3)
     if valu is not None:
         rate = valu / (cls_ms * 1e-3) / 1e9
         roof["valu_issue"] = {"insts_per_launch": valu, "achieved": round(rate, 1), "peak": VALU_PEAK_GINSTS,
