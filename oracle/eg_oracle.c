@@ -35,6 +35,12 @@
  *               of Alg. 2), i.e. the descending manifold that contains v.
  *   arcs        for every saddle s and rep r: the arc (s, label(r)); arcs form
  *               a set (Sec. 2), so duplicates are dropped.
+ *   paths       the geometry of Alg. 2: for every saddle s and every upper-link
+ *               component, the vertex list s, r, grad(r), grad(grad(r)), ...,
+ *               up to the maximum, r being the component's rep.  A saddle's
+ *               components are listed in ascending order of their smallest
+ *               vertex id (the order a BFS seeded at the lowest unvisited
+ *               upper-link vertex finds them).
  *
  * Parallelism: OpenMP over vertices for the per-vertex classification; the
  * label walk is serial with memoisation.  Nothing is blocked, fused or
@@ -128,7 +134,15 @@ static int neighbours(const grid_t* g, int64_t v, int64_t* ids, int64_t (*coords
 /* Classify one vertex: gradient target, beta+, and the highest vertex of each
  * upper-link component (reps, in order of discovery; caller sorts if needed).
  * Returns the number of reps (= beta+). */
+static int classify_vertex_mins(const grid_t* g, int64_t v, int64_t* ptr_out, int64_t* reps, int64_t* mins);
 static int classify_vertex(const grid_t* g, int64_t v, int64_t* ptr_out, int64_t* reps)
+{
+    return classify_vertex_mins(g, v, ptr_out, reps, NULL);
+}
+
+/* The same, also giving the smallest vertex id of each component (mins may
+ * be NULL). */
+static int classify_vertex_mins(const grid_t* g, int64_t v, int64_t* ptr_out, int64_t* reps, int64_t* mins)
 {
     int64_t ids[EGO_MAXNB];
     int64_t coords[EGO_MAXNB][EGO_MAXDIM];
@@ -155,10 +169,11 @@ static int classify_vertex(const grid_t* g, int64_t v, int64_t* ptr_out, int64_t
         int head = 0, tail = 0;
         queue[tail++] = a;
         comp[a] = ncomp;
-        int64_t rep = ids[up[a]];
+        int64_t rep = ids[up[a]], lo = ids[up[a]];
         while (head < tail) {
             int x = queue[head++];
             if (above(g, ids[up[x]], rep)) rep = ids[up[x]];
+            if (ids[up[x]] < lo) lo = ids[up[x]];
             for (int b = 0; b < nu; ++b) {
                 if (comp[b] >= 0) continue;
                 if (grid_adjacent(g->n, coords[up[x]], coords[up[b]])) {
@@ -168,6 +183,7 @@ static int classify_vertex(const grid_t* g, int64_t v, int64_t* ptr_out, int64_t
             }
         }
         reps[ncomp] = rep;
+        if (mins) mins[ncomp] = lo;
         ++ncomp;
     }
     return ncomp;
@@ -338,5 +354,101 @@ int ego_arcs(const float* f, int ndim, const int64_t* dims, int minima,
         int len = saddle_row(&g, labels, saddles[i], row);
         memcpy(arc_maxima + offsets[i], row, sizeof(int32_t) * (size_t)len);
     }
+    return EGO_OK;
+}
+
+/* Whole-field pass 4: gradient-path geometry (Alg. 2).  For each saddle (the
+ * ascending list) and each of its upper-link components, in ascending order of
+ * the component's smallest vertex id: the path s, rep, grad(rep), ..., m.
+ * pair_offsets[i] .. pair_offsets[i+1] index the paths of saddle i;
+ * path_offsets (CSR over all paths) index vertices.  Two sweeps (count, then
+ * fill).  Returns EGO_ERR_CAPACITY with the required counts in *n_pairs and
+ * *n_vertices if a capacity is too small. */
+typedef struct {
+    int64_t rep, lo;
+} comp_t;
+
+static int cmp_comp(const void* a, const void* b)
+{
+    int64_t x = ((const comp_t*)a)->lo, y = ((const comp_t*)b)->lo;
+    return (x > y) - (x < y);
+}
+
+static int saddle_paths(const grid_t* g, int64_t s, comp_t* comps)
+{
+    int64_t reps[EGO_MAXNB], mins[EGO_MAXNB], p;
+    int b = classify_vertex_mins(g, s, &p, reps, mins);
+    for (int j = 0; j < b; ++j) {
+        comps[j].rep = reps[j];
+        comps[j].lo = mins[j];
+    }
+    qsort(comps, (size_t)b, sizeof(comp_t), cmp_comp);
+    return b;
+}
+
+static int64_t path_length(const int32_t* ptr, int64_t r)
+{
+    int64_t len = 2; /* s and r */
+    while (ptr[r] != r) {
+        r = ptr[r];
+        ++len;
+    }
+    return len;
+}
+
+int ego_paths(const float* f, int ndim, const int64_t* dims, int minima, const int32_t* ptr,
+              const int32_t* saddles, int64_t n_sad, int32_t* pair_offsets, int32_t* path_offsets,
+              int64_t cap_pairs, int32_t* vertices, int64_t cap_vertices, int64_t* n_pairs,
+              int64_t* n_vertices)
+{
+    grid_t g;
+    int st = setup(&g, f, ndim, dims, minima);
+    if (st != EGO_OK) return st;
+    int64_t* vcount = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_sad > 0 ? n_sad : 1));
+    if (!vcount) return EGO_ERR_NOMEM;
+    /* sweep 1: components and path vertices per saddle */
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n_sad; ++i) {
+        comp_t comps[EGO_MAXNB];
+        int b = saddle_paths(&g, saddles[i], comps);
+        int64_t nv = 0;
+        for (int j = 0; j < b; ++j) nv += path_length(ptr, comps[j].rep);
+        pair_offsets[i + 1] = b;
+        vcount[i] = nv;
+    }
+    pair_offsets[0] = 0;
+    int64_t tp = 0, tv = 0;
+    for (int64_t i = 0; i < n_sad; ++i) {
+        tp += pair_offsets[i + 1];
+        pair_offsets[i + 1] = (int32_t)tp;
+        const int64_t nv = vcount[i];
+        vcount[i] = tv; /* first vertex of the saddle's paths */
+        tv += nv;
+    }
+    *n_pairs = tp;
+    *n_vertices = tv;
+    if (tp > cap_pairs || tv > cap_vertices) {
+        free(vcount);
+        return EGO_ERR_CAPACITY;
+    }
+    /* sweep 2: fill */
+    path_offsets[0] = 0;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n_sad; ++i) {
+        comp_t comps[EGO_MAXNB];
+        int b = saddle_paths(&g, saddles[i], comps);
+        int64_t at = vcount[i];
+        for (int j = 0; j < b; ++j) {
+            int64_t r = comps[j].rep;
+            vertices[at++] = saddles[i];
+            vertices[at++] = (int32_t)r;
+            while (ptr[r] != r) {
+                r = ptr[r];
+                vertices[at++] = (int32_t)r;
+            }
+            path_offsets[pair_offsets[i] + j + 1] = (int32_t)at;
+        }
+    }
+    free(vcount);
     return EGO_OK;
 }

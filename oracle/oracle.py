@@ -68,6 +68,9 @@ def _bind(lib):
     lib.ego_arcs.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, vp, ctypes.c_int64,
                              vp, vp, ctypes.c_int64, vp]
     lib.ego_arcs.restype = ctypes.c_int
+    lib.ego_paths.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, vp, ctypes.c_int64, vp, vp, ctypes.c_int64,
+                              vp, ctypes.c_int64, vp, vp]
+    lib.ego_paths.restype = ctypes.c_int
     return lib
 
 
@@ -169,6 +172,31 @@ def arcs(f, labels: np.ndarray, saddles: np.ndarray, minima: bool = False):
         if st != 0:
             raise OracleError(f"oracle status {st}")
         return offsets, am[: int(n_arc[0])].copy()
+
+
+def paths(f, ptr: np.ndarray, saddles: np.ndarray, minima: bool = False):
+    """Gradient-path geometry (Alg. 2): (pair_offsets, path_offsets, vertices).
+    Saddle i owns paths pair_offsets[i] .. pair_offsets[i+1]; path k is
+    vertices[path_offsets[k] .. path_offsets[k+1]] = s, rep, ..., maximum."""
+    lib = _load()
+    f, dims = _prep(f)
+    ptr = np.ascontiguousarray(ptr, dtype=np.int32)
+    saddles = np.ascontiguousarray(saddles, dtype=np.int32)
+    pair_offsets = np.zeros(saddles.size + 1, dtype=np.int32)
+    cap_p, cap_v = max(16, 3 * saddles.size), max(64, 64 * saddles.size)
+    while True:
+        po = np.zeros(cap_p + 1, dtype=np.int32)
+        verts = np.empty(cap_v, dtype=np.int32)
+        n_p = np.zeros(1, dtype=np.int64)
+        n_v = np.zeros(1, dtype=np.int64)
+        st = lib.ego_paths(_p(f), f.ndim, _p(dims), int(minima), _p(ptr), _p(saddles), saddles.size,
+                           _p(pair_offsets), _p(po), cap_p, _p(verts), cap_v, _p(n_p), _p(n_v))
+        if st == 5:
+            cap_p, cap_v = max(cap_p, int(n_p[0])), max(cap_v, int(n_v[0]))
+            continue
+        if st != 0:
+            raise OracleError(f"oracle status {st}")
+        return pair_offsets, po[: int(n_p[0]) + 1].copy(), verts[: int(n_v[0])].copy()
 
 
 def extremum_graph(f, minima: bool = False) -> dict:

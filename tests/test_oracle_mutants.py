@@ -42,6 +42,16 @@ MUTANTS = {
     # minima graph obtained by negating values but keeping the index tie-break
     "minima_negate_only": ("return fb > fa || (fb == fa && b > a);",
                            "return fb > fa || (fb == fa && a > b);"),
+    # paths of a saddle ordered by their reps instead of the components' smallest vertex
+    "paths_order_by_rep": ("int64_t x = ((const comp_t*)a)->lo, y = ((const comp_t*)b)->lo;",
+                           "int64_t x = ((const comp_t*)a)->rep, y = ((const comp_t*)b)->rep;"),
+    # a component's smallest vertex tracked as its largest
+    "paths_lo_as_hi": ("if (ids[up[x]] < lo) lo = ids[up[x]];", "if (ids[up[x]] > lo) lo = ids[up[x]];"),
+    # the walk starts one step past the rep
+    "paths_skip_rep": ("            int64_t r = comps[j].rep;\n            vertices[at++] = saddles[i];\n"
+                       "            vertices[at++] = (int32_t)r;",
+                       "            int64_t r = comps[j].rep;\n            vertices[at++] = saddles[i];\n"
+                       "            r = ptr[r];\n            vertices[at++] = (int32_t)r;"),
 }
 
 
@@ -55,6 +65,8 @@ def _pins():
     P.test_constant_field((4, 5, 3))
     P.test_banchoff_2d_from_beta()
     P.test_minima_graph_is_flipped_negated_maxima_graph((5, 4, 6))
+    for shape in [(6, 7), (5, 4, 3)]:
+        P.test_paths_match_brute(shape, "uniform")
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))

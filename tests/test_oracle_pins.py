@@ -118,6 +118,66 @@ def test_oracle_matches_brute_alg2_reps():
         assert list(oreps) == reps
 
 
+# ------------------------------------------------------------------ path geometry
+
+def _brute_paths(b):
+    """The brute force's Alg. 2 paths, flattened in the oracle's layout."""
+    pair_offsets, path_offsets, verts = [0], [0], []
+    for s in b["saddles"]:
+        for p, m in b["paths"][int(s)]:
+            verts += list(p) + [m]
+            path_offsets.append(len(verts))
+        pair_offsets.append(len(path_offsets) - 1)
+    return (np.array(pair_offsets, np.int32), np.array(path_offsets, np.int32), np.array(verts, np.int32))
+
+
+@pytest.mark.parametrize("shape", [(9,), (6, 7), (5, 4, 3), (3, 3, 2, 3)], ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("kind", ["uniform", "ties"])
+def test_paths_match_brute(shape, kind):
+    """Alg. 2 taken literally (brute.py walks the gradient from each rep until
+    a maximum) gives the same paths, in the same order: saddles ascending,
+    components by their smallest vertex id."""
+    for seed in range(2):
+        f = W.random_field(shape, seed + 31 * len(shape), kind)
+        for minima in (False, True):
+            g = O.extremum_graph(f, minima)
+            got = O.paths(f, g["ptr"], g["saddles"], minima)
+            want = _brute_paths(B.extremum_graph(f, minima))
+            for a, b, name in zip(got, want, ("pair_offsets", "path_offsets", "vertices")):
+                np.testing.assert_array_equal(a, b, err_msg=f"{shape} {kind} minima={minima} {name}")
+
+
+def _above(f, a, b, minima):
+    fa, fb = float(f.flat[a]), float(f.flat[b])
+    return (fa > fb or (fa == fb and a > b)) if not minima else (fb > fa or (fb == fa and b > a))
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (24, 20, 16), (10, 9, 8, 7)], ids=lambda s: "x".join(map(str, s)))
+def test_path_invariants(shape):
+    """Every path starts at its saddle, steps between Freudenthal neighbours,
+    rises strictly in the order, and ends at the maximum that labels its
+    rep; a saddle has beta+ paths whose ends are exactly its arc row."""
+    f = W.gaussian_mixture(shape, 41, n_gauss=6, noise=1e-3)
+    for minima in (False, True):
+        g = O.extremum_graph(f, minima)
+        po, pth, vs = O.paths(f, g["ptr"], g["saddles"], minima)
+        assert po[-1] == pth.size - 1 == int(g["saddle_beta"].sum())
+        maxima = set(g["maxima"].tolist())
+        for i, s in enumerate(g["saddles"]):
+            ends = set()
+            assert po[i + 1] - po[i] == g["saddle_beta"][i]
+            for k in range(po[i], po[i + 1]):
+                p = vs[pth[k]:pth[k + 1]]
+                assert p[0] == s and len(p) >= 2
+                for a, b in zip(p[:-1], p[1:]):
+                    assert b in set(O.neighbours(shape, int(a)).tolist())
+                    assert _above(f, int(b), int(a), minima)
+                assert int(p[-1]) in maxima and g["labels"][p[1]] == p[-1]
+                ends.add(int(p[-1]))
+            row = g["arc_maxima"][g["arc_offsets"][i]:g["arc_offsets"][i + 1]]
+            assert ends == set(row.tolist())
+
+
 def test_nan_rejected():
     f = W.random_field((4, 4), 1)
     f[2, 3] = np.nan
