@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--minima", action="store_true", help="minimum graph instead of maximum graph")
     ap.add_argument("--stage-reps", type=int, default=20, help="repetitions for the per-stage timings")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-paths", action="store_true", help="skip the gradient-path geometry measurement")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (library default tile shape and links per pass)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -97,6 +98,38 @@ def recorded_counter(prefix: str, key: str, kernel: str, workload: str, tile3: i
         return float(vals[f"tile3_{tile3}_{key}"])
     except (KeyError, ValueError):
         return None
+
+
+def measure_paths(args, f, t, tuning):
+    """Gradient-path geometry (eg_paths) of the same field, after a build with
+    pointers: HIP-event time of the paths stage alone."""
+    import torch
+
+    from paper_2303_02724_amd import eg
+
+    b = eg.Builder(f.shape, minima=args.minima, want_ptr=True, device=t.device, tuning=tuning)
+    b.run(t)
+    p = b.paths(t)  # sizes the path buffers
+    npaths, nverts = int(p.path_offsets.numel()) - 1, int(p.vertices.numel())
+    lengths = (p.path_offsets[1:] - p.path_offsets[:-1]).cpu()
+    s = torch.cuda.current_stream()
+    reps = max(3, args.stage_reps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.launch_paths(t, stream=s)
+    e0.record(s)
+    for _ in range(reps):
+        b.launch_paths(t, stream=s)
+    e1.record(s)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    res = {"ms": round(ms, 4), "paths": npaths, "vertices": nverts,
+           "longest": int(lengths.max()) if npaths else 0,
+           "mean_length": round(float(lengths.float().mean()), 2) if npaths else 0.0,
+           # per path vertex: its pointer and key read, its id written
+           "GBs_at_12B_per_vertex": round(12 * nverts / (ms * 1e-3) / 1e9, 1)}
+    del b, p
+    torch.cuda.empty_cache()
+    return res
 
 
 def make_field(args):
@@ -469,6 +502,8 @@ def main():
         "h2d_ms": round(h2d_s * 1e3, 3),
         "field_gen_s": round(t_gen, 2),
     }
+    if not args.no_paths:
+        out["paths"] = measure_paths(args, f, t, tuning)
     if args.profile_stage:
         torch.cuda.synchronize()
         if args.profile_stage != "classify":

@@ -176,6 +176,47 @@ eg_status eg_arcs(const float* field, int ndim, const int64_t* dims, void* strea
                   const eg_out* out);
 
 /*
+ * Gradient-path geometry (Sec. 3.4, Alg. 2): for every saddle s and every
+ * component of its upper link, the vertex list of the path that Alg. 2 walks:
+ * s, r, ptr(r), ptr(ptr(r)), ..., m, where r is the component's highest vertex
+ * (UpperLinkRep) and m the maximum it reaches (ptr(m) = m).  Saddles come in
+ * the order of eg_out.saddles; the components of a saddle in ascending order
+ * of their smallest vertex id.  There are beta+ paths per saddle; the set of
+ * their last vertices is the saddle's arc row.
+ *
+ *   pair_offsets   [cap_sad + 1]  saddle i owns paths pair_offsets[i] .. pair_offsets[i+1]
+ *   path_offsets   [cap_paths + 1] path k is path_vertices[path_offsets[k] .. path_offsets[k+1])
+ *   path_vertices  [cap_vertices] vertex ids
+ *   header         [EG_P_SLOTS] int32 device: status, number of paths, number of vertices
+ *
+ * eg_paths(field, ndim, dims, stream, out, paths) reads the outputs of an
+ * eg_build (or eg_classify + eg_label + eg_arcs) with the same `out`, queued
+ * earlier on the same stream: out->ptr must be given.
+ * Host errors as eg_build, plus EG_ERR_ARG for a missing ptr, saddle_beta or
+ * paths buffer.  Device: EG_ERR_CAPACITY with the required counts when a
+ * capacity is short (entries below each capacity are written), or when the
+ * saddles themselves exceeded out->cap_sad; EG_ERR_ARG when out->ptr does not
+ * hold this field's pointers (a step that leaves the grid or does not rise
+ * ends that walk).
+ */
+#define EG_P_STATUS 0
+#define EG_P_PATHS 1
+#define EG_P_VERTICES 2
+#define EG_P_SLOTS 4
+
+typedef struct eg_paths_out {
+    int32_t* pair_offsets;
+    int32_t* path_offsets;
+    int64_t cap_paths;
+    int32_t* path_vertices;
+    int64_t cap_vertices;
+    int32_t* header;
+} eg_paths_out;
+
+eg_status eg_paths(const float* field, int ndim, const int64_t* dims, void* stream, const eg_out* out,
+                   const eg_paths_out* paths);
+
+/*
  * Batches: the extremum graphs of `count` independent 2D or 3D fields in one
  * launch sequence.  Classification runs one launch per class of fields (2D or
  * 3D, maximum or minimum graph) over a work list of (field, tile) items;

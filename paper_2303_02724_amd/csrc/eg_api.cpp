@@ -245,6 +245,29 @@ eg_status eg_build_batched(const void* host_plan, void* stream)
     return e == hipSuccess ? EG_OK : EG_ERR_HIP;
 }
 
+eg_status eg_paths(const float* field, int ndim, const int64_t* dims, void* stream, const eg_out* out,
+                   const eg_paths_out* paths)
+{
+    Grid g;
+    Work w;
+    const eg_status st = check_one(field, ndim, dims, out, &g, &w);
+    if (st != EG_OK) return st;
+    if (!paths || !out->ptr || !paths->pair_offsets || !paths->path_offsets || !paths->header) return EG_ERR_ARG;
+    if (paths->cap_paths < 0 || paths->cap_vertices < 0) return EG_ERR_TOO_LARGE;
+    if (paths->cap_paths >= kMaxIndex || paths->cap_vertices >= kMaxIndex) return EG_ERR_TOO_LARGE;
+    if (paths->cap_vertices > 0 && !paths->path_vertices) return EG_ERR_ARG;
+    PathArgs p{};
+    p.ptr = gptr<const int32_t>(out->ptr);
+    p.pair_offsets = gptr(paths->pair_offsets);
+    p.path_offsets = gptr(paths->path_offsets);
+    p.vertices = gptr(paths->path_vertices);
+    p.header = gptr(paths->header);
+    p.cap_paths = (uint32_t)paths->cap_paths;
+    p.cap_vertices = (uint32_t)paths->cap_vertices;
+    const hipError_t e = launch_paths(arc_args(field, g, *out, w), p, (hipStream_t)stream);
+    return e == hipSuccess ? EG_OK : EG_ERR_HIP;
+}
+
 size_t eg_workspace_bytes(int ndim, const int64_t* dims, int64_t cap_sad)
 {
     Grid g;

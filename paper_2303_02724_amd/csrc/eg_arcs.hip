@@ -332,13 +332,14 @@ __device__ __forceinline__ void load_nbhd(const ArcArgs& A, int v, Nbhd<NDIM, MI
     }
 }
 
-// Calls f(label) for every upper-link component of saddle v: the label of
-// the component's highest vertex (UpperLinkRep, Sec. 3.4), the highest found
-// by scanning in the order in which the later of two equal vertices wins.
-// Components come from a bit-parallel BFS over the link edges.
+// Calls f(rep) for every upper-link component of saddle v, with rep the
+// component's highest vertex (UpperLinkRep, Sec. 3.4), found by scanning in
+// the order in which the later of two equal vertices wins.  Components come
+// from a bit-parallel BFS over the link edges seeded at the lowest remaining
+// row; rows are in linear-index order, so components come in ascending order
+// of their smallest vertex.
 template <int NDIM, bool MINMODE, class F>
-__device__ __forceinline__ void for_each_arc_label(const ArcArgs& A, int v, const Nbhd<NDIM, MINMODE>& nb,
-                                                   const uint64_t* s_adj, F&& f)
+__device__ __forceinline__ void for_each_rep(int v, const Nbhd<NDIM, MINMODE>& nb, const uint64_t* s_adj, F&& f)
 {
     constexpr int K = Rows<NDIM>::K;
     for (uint64_t rem = nb.up; rem;) {
@@ -354,8 +355,16 @@ __device__ __forceinline__ void for_each_arc_label(const ArcArgs& A, int v, cons
                 best_off = nb.offs[j];
             }
         }
-        f((uint32_t)A.lab[v + best_off]);
+        f(v + best_off);
     }
+}
+
+// f(label) for every component: the label its rep reaches.
+template <int NDIM, bool MINMODE, class F>
+__device__ __forceinline__ void for_each_arc_label(const ArcArgs& A, int v, const Nbhd<NDIM, MINMODE>& nb,
+                                                   const uint64_t* s_adj, F&& f)
+{
+    for_each_rep<NDIM, MINMODE>(v, nb, s_adj, [&](int rep) { f((uint32_t)A.lab[rep]); });
 }
 
 // The S smallest distinct arc labels of a saddle, ascending (unused entries
@@ -444,7 +453,9 @@ __device__ __forceinline__ void arc_count_body(const ArcArgs& A, uint32_t blk, u
     const int tid = threadIdx.x;
     uint32_t sc = 0, sb = 0;
     for (uint32_t i = lo + tid; i < hi; i += 256) {
-        const int v = A.saddles[i];
+        // saddle ids come from the compaction; the check keeps a stage run
+        // on a workspace without classification inside the grid
+        const int v = min(max(A.saddles[i], 0), A.N - 1);
         Nbhd<NDIM, MINMODE> h;
         load_nbhd<NDIM, MINMODE>(A, v, h);
         int beta;
@@ -493,7 +504,7 @@ __device__ __forceinline__ void arc_write_body(const ArcArgs& A, uint32_t blk, u
             if (n > 4) {
                 // past the four stored arcs: the list again, then (beyond
                 // its S entries) ascending selection
-                const int v = A.saddles[i];
+                const int v = min(max(A.saddles[i], 0), A.N - 1);
                 Nbhd<NDIM, MINMODE> h;
                 load_nbhd<NDIM, MINMODE>(A, v, h);
                 constexpr int S = ArcList<NDIM>::S;
@@ -559,6 +570,170 @@ __global__ __launch_bounds__(256) void k_arc_batched(BatchFields sel)
         default: EG_BODY(3, true) break;
     }
 #undef EG_BODY
+}
+
+// ------------------------------------------------------------------ paths
+
+template <bool MINMODE>
+__device__ __forceinline__ uint32_t key_of(const ArcArgs& A, int x)
+{
+    return A.keys != nullptr ? A.keys[x] : mode_key<MINMODE>(A.f[x]);
+}
+
+// The walk of Alg. 2 from rep: visit(r) for rep and every vertex after it, up
+// to the maximum (ptr(m) = m).  Every step must stay in the grid and rise in
+// the order; a pointer that does not (out->ptr not holding this field's
+// pointers) ends the walk and returns false, so no input can make it leave
+// the grid or loop.
+template <bool MINMODE, class V>
+__device__ __forceinline__ bool walk(const ArcArgs& A, const EG_GPTR(const int32_t) ptr, int r, V&& visit)
+{
+    visit(r);
+    uint32_t ur = key_of<MINMODE>(A, r);
+    for (;;) {
+        const int q = ptr[r];
+        if (q == r) return true;
+        if ((unsigned)q >= (unsigned)A.N) return false;
+        const uint32_t uq = key_of<MINMODE>(A, q);
+        if (!(uq > ur || (uq == ur && (MINMODE ? q < r : q > r)))) return false;
+        visit(q);
+        r = q;
+        ur = uq;
+    }
+}
+
+__global__ void k_path_reset(OneField sel)
+{
+    if (threadIdx.x == 0) sel.field().ctr[C_PBAD] = 0;
+}
+
+// Paths and path vertices of every saddle of the block's chunk (kept for the
+// write pass in the workspace), block sums into rows 0 and 1.
+template <int NDIM, bool MINMODE>
+__global__ __launch_bounds__(256) void k_path_count(OneField sel, PathArgs P)
+{
+    __shared__ uint64_t s_adj[Rows<NDIM>::K];
+    __shared__ uint32_t tmp[4];
+    uint32_t blk, nb;
+    const ArcArgs A = sel.locate(blk, nb);  // a copy: loop loads cannot alias it
+    load_adj<NDIM>(s_adj);
+    uint32_t lo, hi;
+    chunk(saddle_count(A), nb, blk, lo, hi);
+    uint32_t sp = 0, sv = 0;
+    bool bad = false;
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) {
+        const int v = A.saddles[i];
+        uint32_t np = 0, nv = 0;
+        if ((unsigned)v < (unsigned)A.N) {
+            Nbhd<NDIM, MINMODE> h;
+            load_nbhd<NDIM, MINMODE>(A, v, h);
+            for_each_rep<NDIM, MINMODE>(v, h, s_adj, [&](int rep) {
+                ++np;
+                ++nv;  // the saddle, then rep .. maximum
+                bad |= !walk<MINMODE>(A, P.ptr, rep, [&](int) { ++nv; });
+            });
+        } else {
+            bad = true;
+        }
+        A.atmp[i] = make_uint4(np, nv, 0u, 0u);
+        sp += np;
+        sv += nv;
+    }
+    if (__ballot(bad) != 0 && __lane_id() == 0) atomicOr(&A.ctr[C_PBAD], 1u);
+    sp = block_sum(sp, tmp);
+    sv = block_sum(sv, tmp);
+    if (threadIdx.x == 0) {
+        A.bsum[blk] = sp;
+        A.bsum[kArcBlocks + blk] = sv;
+    }
+}
+
+template <int NDIM, bool MINMODE>
+__global__ __launch_bounds__(256) void k_path_write(OneField sel, PathArgs P)
+{
+    __shared__ uint64_t s_adj[Rows<NDIM>::K];
+    __shared__ uint32_t tmp[4];
+    uint32_t blk, nb;
+    const ArcArgs A = sel.locate(blk, nb);  // a copy: loop loads cannot alias it
+    load_adj<NDIM>(s_adj);
+    uint32_t lo, hi;
+    chunk(saddle_count(A), nb, blk, lo, hi);
+    uint32_t runp = A.bsum[blk], runv = A.bsum[kArcBlocks + blk];
+    for (uint32_t base = lo; base < hi; base += 256) {
+        const uint32_t i = base + threadIdx.x;
+        const bool valid = i < hi;
+        const uint4 c = valid ? A.atmp[i] : make_uint4(0u, 0u, 0u, 0u);
+        uint32_t tp, tv;
+        uint32_t pk = runp + block_excl_scan(c.x, tmp, tp);
+        uint32_t at = runv + block_excl_scan(c.y, tmp, tv);
+        const int v = valid ? A.saddles[i] : 0;
+        if (valid) P.pair_offsets[i] = (int32_t)pk;
+        if (valid && (unsigned)v < (unsigned)A.N) {
+            Nbhd<NDIM, MINMODE> h;
+            load_nbhd<NDIM, MINMODE>(A, v, h);
+            for_each_rep<NDIM, MINMODE>(v, h, s_adj, [&](int rep) {
+                if (pk <= P.cap_paths) P.path_offsets[pk] = (int32_t)at;
+                ++pk;
+                if (at < P.cap_vertices) P.vertices[at] = v;
+                ++at;
+                walk<MINMODE>(A, P.ptr, rep, [&](int r) {
+                    if (at < P.cap_vertices) P.vertices[at] = r;
+                    ++at;
+                });
+            });
+        }
+        runp += tp;
+        runv += tv;
+    }
+}
+
+// Closing entries of both offset arrays and the header.
+__global__ void k_path_finalize(OneField sel, PathArgs P)
+{
+    if (threadIdx.x != 0) return;
+    const ArcArgs A = sel.field();
+    const uint32_t nsad = A.ctr[C_NSAD], np = A.ctr[C_PATHS], nv = A.ctr[C_PVERTS];
+    const uint32_t n = nsad < A.cap_sad ? nsad : A.cap_sad;
+    P.pair_offsets[n] = (int32_t)np;
+    if (np <= P.cap_paths) P.path_offsets[np] = (int32_t)nv;
+    const bool short_ = nsad > A.cap_sad || np > P.cap_paths || nv > P.cap_vertices;
+    P.header[EG_P_STATUS] = A.ctr[C_NAN] ? EG_ERR_NAN : A.ctr[C_PBAD] ? EG_ERR_ARG : short_ ? EG_ERR_CAPACITY : EG_OK;
+    P.header[EG_P_PATHS] = (int32_t)np;
+    P.header[EG_P_VERTICES] = (int32_t)nv;
+}
+
+template <int NDIM, bool MINMODE>
+static void launch_paths_t(const OneField& sel, const PathArgs& p, uint32_t nb, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_path_reset, dim3(1), dim3(64), 0, s, sel);
+    hipLaunchKernelGGL((k_path_count<NDIM, MINMODE>), dim3(nb), dim3(256), 0, s, sel, p);
+    hipLaunchKernelGGL(k_scan_rows<OneField>, dim3(1), dim3(1024), 0, s, sel, 0, (int)C_PATHS, (int)C_PVERTS);
+    hipLaunchKernelGGL((k_path_write<NDIM, MINMODE>), dim3(nb), dim3(256), 0, s, sel, p);
+}
+
+hipError_t launch_paths(const ArcArgs& a, const PathArgs& p, hipStream_t s)
+{
+    const OneField sel{a};
+    const uint32_t nb = (uint32_t)a.arc_blocks;
+#define EG_CASE(N)                                    \
+    case N:                                           \
+        if (a.minima)                                 \
+            launch_paths_t<N, true>(sel, p, nb, s);   \
+        else                                          \
+            launch_paths_t<N, false>(sel, p, nb, s);  \
+        break;
+    switch (a.ndim) {
+        EG_CASE(1)
+        EG_CASE(2)
+        EG_CASE(3)
+        EG_CASE(4)
+        EG_CASE(5)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef EG_CASE
+    hipLaunchKernelGGL(k_path_finalize, dim3(1), dim3(64), 0, s, sel, p);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ header

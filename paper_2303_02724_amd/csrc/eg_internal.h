@@ -59,6 +59,9 @@ enum : int {
     C_NPAIRS = 3,
     C_NARC = 4,
     C_PASSES = 6,
+    C_PATHS = 40,     // paths (sum of beta over the saddles) for eg_paths
+    C_PVERTS = 41,    // their vertices
+    C_PBAD = 42,      // eg_paths met a pointer that leaves the grid or does not rise
     C_NEXIT = 7,  // exit-list entries requested by the tiles
     C_JUMP = 8,   // kMaxPasses "not converged" flags of the exit-list passes
     C_FINAL = 16, // kMaxPasses "not converged" flags of the per-vertex passes
@@ -150,6 +153,16 @@ struct ArcArgs {
     int32_t dims[EG_MAX_NDIM];
     uint32_t cap_max, cap_sad, cap_arc;
     int32_t arc_blocks;  // blocks of this field in the stage (d) kernels (<= kArcBlocks)
+};
+
+// The outputs of eg_paths for one field.
+struct PathArgs {
+    EG_GPTR(const int32_t) ptr;
+    EG_GPTR(int32_t) pair_offsets;
+    EG_GPTR(int32_t) path_offsets;
+    EG_GPTR(int32_t) vertices;
+    EG_GPTR(int32_t) header;
+    uint32_t cap_paths, cap_vertices;
 };
 
 // One field of a batch (device-resident plan, built on the host).
@@ -277,6 +290,8 @@ hipError_t launch_final_tiled_batched(const BatchPlan* dplan, const BatchPlan& h
 // Stage (d) of one field: ascending maxima and saddles from the bitmasks,
 // the arcs of every saddle, the CSR and the header.
 hipError_t launch_arcs(const ArcArgs& a, hipStream_t s);
+// Gradient-path geometry of one field (after stage (d)).
+hipError_t launch_paths(const ArcArgs& a, const PathArgs& p, hipStream_t s);
 // Stage (d) of every field of a batch (fields are blockIdx.y).
 hipError_t launch_arcs_batched(const BatchPlan* dplan, const BatchPlan& hplan, hipStream_t s);
 

@@ -60,6 +60,20 @@ class eg_out(ctypes.Structure):
     ]
 
 
+class eg_paths_out(ctypes.Structure):
+    _fields_ = [
+        ("pair_offsets", ctypes.c_void_p),
+        ("path_offsets", ctypes.c_void_p),
+        ("cap_paths", ctypes.c_int64),
+        ("path_vertices", ctypes.c_void_p),
+        ("cap_vertices", ctypes.c_int64),
+        ("header", ctypes.c_void_p),
+    ]
+
+
+P_STATUS, P_PATHS, P_VERTICES = range(3)
+P_SLOTS = 4
+
 _lib = None
 
 
@@ -79,6 +93,8 @@ def lib():
         fn = getattr(L, name)
         fn.argtypes = [vp, ctypes.c_int, i64p, vp, ctypes.POINTER(eg_out)]
         fn.restype = ctypes.c_int
+    L.eg_paths.argtypes = [vp, ctypes.c_int, i64p, vp, ctypes.POINTER(eg_out), ctypes.POINTER(eg_paths_out)]
+    L.eg_paths.restype = ctypes.c_int
     L.eg_batch_plan_bytes.argtypes = [ctypes.c_int]
     L.eg_batch_plan_bytes.restype = ctypes.c_size_t
     L.eg_batch_workspace_bytes.argtypes = [ctypes.c_int, vp, vp, vp]
@@ -141,6 +157,16 @@ class EGResult:
     ptr: torch.Tensor | None
     passes: int
     counts: dict = dc_field(default_factory=dict)
+
+
+@dataclass
+class EGPaths:
+    """Gradient-path geometry: saddle i owns paths pair_offsets[i] ..
+    pair_offsets[i+1]; path k is vertices[path_offsets[k] .. path_offsets[k+1]]
+    = saddle, rep, ..., maximum."""
+    pair_offsets: torch.Tensor
+    path_offsets: torch.Tensor
+    vertices: torch.Tensor
 
 
 class Builder:
@@ -254,6 +280,53 @@ class Builder:
             # the arcs of the saddles past the old capacity were not counted
             c["cap_arc"] = max(c["cap_arc"], 3 * c["cap_sad"])
         self._alloc(c)
+
+    def _alloc_paths(self, cap_paths: int, cap_vertices: int):
+        i32 = dict(dtype=torch.int32, device=self.device)
+        self.p_pair = torch.empty(self.caps["cap_sad"] + 1, **i32)
+        self.p_off = torch.empty(cap_paths + 1, **i32)
+        self.p_verts = torch.empty(max(1, cap_vertices), **i32)
+        self.p_header = torch.zeros(P_SLOTS, **i32)
+        po = eg_paths_out()
+        po.pair_offsets = self.p_pair.data_ptr()
+        po.path_offsets = self.p_off.data_ptr()
+        po.cap_paths = cap_paths
+        po.path_vertices = self.p_verts.data_ptr()
+        po.cap_vertices = cap_vertices
+        po.header = self.p_header.data_ptr()
+        self.pout = po
+        self.pcaps = (cap_paths, cap_vertices)
+
+    def launch_paths(self, field: torch.Tensor, stream=None):
+        """Queue eg_paths after a build of `field` on the same stream."""
+        if self.ptr is None:
+            raise EGError(EG_ERR_ARG, "paths need the steepest-ascent pointers: Builder(..., want_ptr=True)")
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        st = lib().eg_paths(ctypes.c_void_p(field.data_ptr()), len(self.shape), self._dims,
+                            ctypes.c_void_p(s.cuda_stream), ctypes.byref(self.out), ctypes.byref(self.pout))
+        if st != EG_OK:
+            raise EGError(st, "eg_paths")
+        self._stream = s
+
+    def paths(self, field: torch.Tensor, max_retries: int = 4) -> EGPaths:
+        """Gradient-path geometry of the last build of `field` (run() first),
+        growing the path buffers while the library reports a shortfall."""
+        h = self.header_values()
+        npairs = max(0, h[H_NPAIRS])
+        if getattr(self, "pcaps", None) is None or self.pcaps[0] < npairs or self.p_pair.numel() < self.caps["cap_sad"] + 1:
+            self._alloc_paths(max(1, npairs), max(64, 32 * npairs))
+        for _ in range(max_retries + 1):
+            self.launch_paths(field)
+            self._stream.synchronize()
+            ph = [int(x) for x in self.p_header.cpu().tolist()]
+            if ph[P_STATUS] == EG_ERR_CAPACITY and h[H_NSAD] <= self.caps["cap_sad"]:
+                self._alloc_paths(max(self.pcaps[0], ph[P_PATHS]), max(self.pcaps[1], ph[P_VERTICES]))
+                continue
+            if ph[P_STATUS] != EG_OK:
+                raise EGError(ph[P_STATUS], f"paths header={ph}")
+            nsad, npaths, nverts = h[H_NSAD], ph[P_PATHS], ph[P_VERTICES]
+            return EGPaths(self.p_pair[:nsad + 1], self.p_off[:npaths + 1], self.p_verts[:nverts])
+        raise EGError(EG_ERR_CAPACITY, "path capacity retries exhausted")
 
     def run(self, field: torch.Tensor, max_retries: int = 4) -> EGResult:
         """launch + finish, growing the buffers while the library reports a
@@ -387,6 +460,14 @@ def build_batched(fields, minima=False, **kw):
     """Extremum graphs of a list of 2D/3D float32 device tensors in one batch."""
     bb = BatchBuilder([f.shape for f in fields], minima=minima, device=fields[0].device, **kw)
     return bb.run([f.contiguous() for f in fields])
+
+
+def build_paths(field: torch.Tensor, minima: bool = False, tuning: int = 0, **caps):
+    """Extremum graph and gradient-path geometry of ``field``: (EGResult, EGPaths)."""
+    b = Builder(field.shape, minima=minima, want_ptr=True, device=field.device, tuning=tuning, **caps)
+    field = field.contiguous()
+    r = b.run(field)
+    return r, b.paths(field)
 
 
 def build(field: torch.Tensor, minima: bool = False, want_ptr: bool = False, tuning: int = 0,

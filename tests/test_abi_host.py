@@ -194,3 +194,27 @@ def test_batch_plan_validation_on_host():
                            pb) == eg.EG_ERR_WORKSPACE
     # a plan without a device workspace cannot be launched
     assert L.eg_build_batched(None, None) == eg.EG_ERR_ARG
+
+
+def test_paths_rejects_bad_arguments_on_host():
+    L = eg.lib()
+    dims = (ctypes.c_int64 * 2)(8, 8)
+    fake = ctypes.c_void_p(0x1000)
+    o = _fake_out()
+    po = eg.eg_paths_out()
+    # no paths struct, then no ptr
+    assert L.eg_paths(fake, 2, dims, None, ctypes.byref(o), None) == eg.EG_ERR_ARG
+    po.pair_offsets = po.path_offsets = po.path_vertices = po.header = 0x5000
+    po.cap_paths = po.cap_vertices = 4
+    assert L.eg_paths(fake, 2, dims, None, ctypes.byref(o), ctypes.byref(po)) == eg.EG_ERR_ARG
+    o.ptr = 0x6000
+    po.header = None
+    assert L.eg_paths(fake, 2, dims, None, ctypes.byref(o), ctypes.byref(po)) == eg.EG_ERR_ARG
+    po.header = 0x5000
+    po.cap_vertices = -1
+    assert L.eg_paths(fake, 2, dims, None, ctypes.byref(o), ctypes.byref(po)) == eg.EG_ERR_TOO_LARGE
+    po.cap_vertices = 4
+    po.path_vertices = None
+    assert L.eg_paths(fake, 2, dims, None, ctypes.byref(o), ctypes.byref(po)) == eg.EG_ERR_ARG
+    # the field and workspace checks of eg_build come first
+    assert L.eg_paths(None, 2, dims, None, ctypes.byref(o), ctypes.byref(po)) == eg.EG_ERR_ARG

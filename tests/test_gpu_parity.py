@@ -277,6 +277,66 @@ def test_batched_graph_replays_match_eager():
             assert_same(_result_np(b.finish()), e, KEYS, f"replay {rep} {f.shape}")
 
 
+def _gpu_paths(f, minima=False, **caps):
+    import torch
+    from paper_2303_02724_amd import eg
+    t = torch.from_numpy(np.ascontiguousarray(f, dtype=np.float32)).cuda()
+    r, p = eg.build_paths(t, minima=minima, **caps)
+    return (r, p.pair_offsets.cpu().numpy(), p.path_offsets.cpu().numpy(), p.vertices.cpu().numpy())
+
+
+def _assert_paths(f, minima, ctx="", **caps):
+    want = O.extremum_graph(f, minima)
+    wp = O.paths(f, want["ptr"], want["saddles"], minima)
+    r, *got = _gpu_paths(f, minima, **caps)
+    for a, b, name in zip(got, wp, ("pair_offsets", "path_offsets", "vertices")):
+        if not np.array_equal(a, b):
+            raise AssertionError(f"{ctx} minima={minima} {name}: gpu {a[:12]} oracle {b[:12]} "
+                                 f"sizes {a.size} {b.size}")
+
+
+@pytest.mark.parametrize("shape", [(40,), (17, 23), (9, 10, 11), (7, 6, 5, 4), (5, 4, 5, 3, 4), (1, 1), (3, 2, 1)])
+@pytest.mark.parametrize("kind", ["uniform", "ties"])
+def test_paths_equal_oracle(shape, kind):
+    f = W.random_field(shape, 61, kind)
+    for minima in (False, True):
+        _assert_paths(f, minima, f"{shape} {kind}")
+
+
+def test_paths_grf_and_mixtures():
+    f = W.gaussian_random_field((40, 72, 96), 9, corr_len=4.0, workers=4)
+    _assert_paths(f, False, "grf")
+    _assert_paths(f, True, "grf")
+    g = W.gaussian_mixture((256, 256), 0, n_gauss=8, noise=1e-3)
+    _assert_paths(g, False, "2d256")
+
+
+def test_paths_long_and_capacity_regrowth():
+    # one path thousands of vertices long (a serpentine-free ramp with a
+    # saddle), and starting capacities far too small
+    x = np.arange(3000, dtype=np.float32)
+    f = np.concatenate([x, x[::-1] - 0.5, x + 100.0]).astype(np.float32)
+    _assert_paths(f, False, "1d ramps")
+    g = W.random_field((30, 40), 62, "uniform")
+    _assert_paths(g, False, "tiny caps", cap_max=1, cap_sad=1, cap_arc=1)
+
+
+def test_paths_reject_pointers_of_another_field():
+    """A pointer array that does not describe the field (here: every entry
+    outside the grid) ends each walk at once and is reported, never followed."""
+    import torch
+    from paper_2303_02724_amd import eg
+    f = W.random_field((20, 30), 63, "uniform")
+    t = torch.from_numpy(f).cuda()
+    b = eg.Builder(f.shape, want_ptr=True)
+    b.run(t)
+    b.paths(t)  # valid first
+    b.ptr.fill_(f.size + 5)
+    b.launch_paths(t)
+    torch.cuda.synchronize()
+    assert int(b.p_header[eg.P_STATUS].item()) == eg.EG_ERR_ARG
+
+
 def test_batched_long_paths_several_passes():
     """Paths far longer than a tile and than the links one pass follows
     (16 here): the exit-list chains need several gated jump passes before the
