@@ -713,8 +713,14 @@ static void launch_paths_t(const OneField& sel, const PathArgs& p, uint32_t nb, 
 
 hipError_t launch_paths(const ArcArgs& a, const PathArgs& p, hipStream_t s)
 {
-    const OneField sel{a};
-    const uint32_t nb = (uint32_t)a.arc_blocks;
+    // walks are chains of dependent loads: one block per 256 saddle slots
+    // keeps as many in flight as there are saddles
+    ArcArgs ap = a;
+    const int64_t want = ((int64_t)a.cap_sad + 255) / 256;
+    const int64_t nbp = want < kArcBlocks ? want : kArcBlocks;
+    if (nbp > ap.arc_blocks) ap.arc_blocks = (int32_t)nbp;
+    const OneField sel{ap};
+    const uint32_t nb = (uint32_t)ap.arc_blocks;
 #define EG_CASE(N)                                    \
     case N:                                           \
         if (a.minima)                                 \
