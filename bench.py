@@ -132,6 +132,24 @@ def measure_paths(args, f, t, tuning):
     return res
 
 
+def measure_simplify(res, t, minima):
+    """Graph simplification (host): arc bundling then persistence-directed
+    cancellation at 5 % of the field's value range, as in the paper's
+    experiments."""
+    from paper_2303_02724_amd import eg
+
+    thr = 0.05 * float(t.max() - t.min())
+    t0 = time.perf_counter()
+    s = eg.simplify(res, t, threshold=thr, minima=minima)
+    ms = (time.perf_counter() - t0) * 1e3
+    rows = s["arc_offsets"]
+    return {"ms_host": round(ms, 3), "threshold": thr, "cancellations": int(s["pair_saddle"].size),
+            "maxima_left": int((s["max_rep"] == range(s["max_rep"].size)).sum()),
+            "saddles_left": int((rows[1:] > rows[:-1]).sum()), "arcs_left": int(rows[-1]),
+            "maxima_in": int(res.maxima.numel()), "saddles_in": int(res.saddles.numel()),
+            "arcs_in": int(res.arc_maxima.numel())}
+
+
 def make_field(args):
     from paper_2303_02724_amd import workloads as W
 
@@ -504,6 +522,7 @@ def main():
     }
     if not args.no_paths:
         out["paths"] = measure_paths(args, f, t, tuning)
+    out["simplify"] = measure_simplify(res, t, args.minima)
     if args.profile_stage:
         torch.cuda.synchronize()
         if args.profile_stage != "classify":

@@ -217,6 +217,55 @@ eg_status eg_paths(const float* field, int ndim, const int64_t* dims, void* stre
                    const eg_paths_out* paths);
 
 /*
+ * Simplification of a finished extremum graph (Sec. 3.5), on the host: the
+ * graph has one node per critical point and the cancellations depend on one
+ * another, as in the paper's serial implementation.
+ *
+ *   EG_SIMPLIFY_BUNDLE  arc bundling: for every pair of maxima that share
+ *                       saddles, the highest shared saddle represents the pair;
+ *                       a saddle survives iff it represents one of its pairs.
+ *   EG_SIMPLIFY_CANCEL  persistence-directed cancellation: saddles are taken in
+ *                       order of cost = height of their lowest maximum - height
+ *                       of the saddle (ties: the lower saddle first), costs
+ *                       recomputed when a saddle comes up; at cost <= threshold
+ *                       the lowest maximum merges into the saddle's highest
+ *                       maximum.  A saddle joining k maxima can be cancelled
+ *                       k - 1 times.  Applied after bundling when both are set.
+ *
+ * Heights are the field values in the graph's order (ties by vertex id),
+ * reversed for a minimum graph (flags = EG_MINIMA).  All pointers are host
+ * memory.  Inputs: the graph as eg_build returns it (ascending maxima and
+ * saddles, CSR arcs of maxima ids) and the field value at every maximum and
+ * saddle.  Outputs:
+ *   out_offsets [nsad + 1], out_arcs [arc_offsets[nsad]]  the simplified arcs of
+ *       every saddle (an empty row for a removed saddle), ascending maxima ids
+ *   max_rep [nmax]     index of the maximum each maximum merged into (its own
+ *                      index if it survives)
+ *   pair_saddle, pair_max [arc_offsets[nsad]], pair_cost   the cancellations in
+ *                      order: saddle index, maximum index, cost; *n_pairs of them
+ * EG_ERR_ARG for NULL pointers, unknown ops, a NaN threshold, unsorted maxima,
+ * malformed offsets or an arc to a vertex that is not in maxima.
+ */
+#define EG_SIMPLIFY_BUNDLE 0x1u
+#define EG_SIMPLIFY_CANCEL 0x2u
+
+typedef struct eg_graph_host {
+    uint32_t flags;
+    int64_t nmax;
+    const int32_t* maxima;
+    const float* max_values;
+    int64_t nsad;
+    const int32_t* saddles;
+    const float* sad_values;
+    const int32_t* arc_offsets;
+    const int32_t* arc_maxima;
+} eg_graph_host;
+
+eg_status eg_simplify(const eg_graph_host* graph, uint32_t ops, double threshold, int32_t* out_offsets,
+                      int32_t* out_arcs, int32_t* max_rep, int32_t* pair_saddle, int32_t* pair_max,
+                      double* pair_cost, int64_t* n_pairs);
+
+/*
  * Batches: the extremum graphs of `count` independent 2D or 3D fields in one
  * launch sequence.  Classification runs one launch per class of fields (2D or
  * 3D, maximum or minimum graph) over a work list of (field, tile) items;

@@ -74,6 +74,22 @@ class eg_paths_out(ctypes.Structure):
 P_STATUS, P_PATHS, P_VERTICES = range(3)
 P_SLOTS = 4
 
+SIMPLIFY_BUNDLE, SIMPLIFY_CANCEL = 0x1, 0x2
+
+
+class eg_graph_host(ctypes.Structure):
+    _fields_ = [
+        ("flags", ctypes.c_uint32),
+        ("nmax", ctypes.c_int64),
+        ("maxima", ctypes.c_void_p),
+        ("max_values", ctypes.c_void_p),
+        ("nsad", ctypes.c_int64),
+        ("saddles", ctypes.c_void_p),
+        ("sad_values", ctypes.c_void_p),
+        ("arc_offsets", ctypes.c_void_p),
+        ("arc_maxima", ctypes.c_void_p),
+    ]
+
 _lib = None
 
 
@@ -95,6 +111,9 @@ def lib():
         fn.restype = ctypes.c_int
     L.eg_paths.argtypes = [vp, ctypes.c_int, i64p, vp, ctypes.POINTER(eg_out), ctypes.POINTER(eg_paths_out)]
     L.eg_paths.restype = ctypes.c_int
+    L.eg_simplify.argtypes = [ctypes.POINTER(eg_graph_host), ctypes.c_uint32, ctypes.c_double, vp, vp, vp, vp, vp,
+                              vp, ctypes.POINTER(ctypes.c_int64)]
+    L.eg_simplify.restype = ctypes.c_int
     L.eg_batch_plan_bytes.argtypes = [ctypes.c_int]
     L.eg_batch_plan_bytes.restype = ctypes.c_size_t
     L.eg_batch_workspace_bytes.argtypes = [ctypes.c_int, vp, vp, vp]
@@ -475,3 +494,55 @@ def build(field: torch.Tensor, minima: bool = False, want_ptr: bool = False, tun
     """Extremum graph of ``field`` (float32 device tensor, 1..5 axes)."""
     b = Builder(field.shape, minima=minima, want_ptr=want_ptr, device=field.device, tuning=tuning, **caps)
     return b.run(field.contiguous())
+
+
+def simplify_graph(maxima, max_values, saddles, sad_values, arc_offsets, arc_maxima, ops: int, threshold: float,
+                   minima: bool = False) -> dict:
+    """eg_simplify on host (numpy) arrays of one extremum graph: arc bundling
+    and/or persistence-directed cancellation (ops = SIMPLIFY_BUNDLE |
+    SIMPLIFY_CANCEL).  Returns the simplified arcs of every saddle (CSR, empty
+    rows for removed saddles), the representative of every maximum, and the
+    cancellations in order."""
+    import numpy as np
+
+    arr = {
+        "maxima": np.ascontiguousarray(maxima, dtype=np.int32),
+        "max_values": np.ascontiguousarray(max_values, dtype=np.float32),
+        "saddles": np.ascontiguousarray(saddles, dtype=np.int32),
+        "sad_values": np.ascontiguousarray(sad_values, dtype=np.float32),
+        "arc_offsets": np.ascontiguousarray(arc_offsets, dtype=np.int32),
+        "arc_maxima": np.ascontiguousarray(arc_maxima, dtype=np.int32),
+    }
+    g = eg_graph_host()
+    g.flags = EG_MINIMA if minima else 0
+    g.nmax = arr["maxima"].size
+    g.nsad = arr["saddles"].size
+    for k, a in arr.items():
+        setattr(g, k, a.ctypes.data_as(ctypes.c_void_p))
+    narc = int(arr["arc_offsets"][-1]) if arr["arc_offsets"].size else 0
+    offs = np.zeros(g.nsad + 1, np.int32)
+    arcs = np.zeros(max(1, narc), np.int32)
+    rep = np.zeros(max(1, g.nmax), np.int32)
+    ps, pm = np.zeros(max(1, narc), np.int32), np.zeros(max(1, narc), np.int32)
+    pc = np.zeros(max(1, narc), np.float64)
+    n = ctypes.c_int64(0)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    st = lib().eg_simplify(ctypes.byref(g), int(ops), float(threshold), p(offs), p(arcs), p(rep), p(ps), p(pm),
+                           p(pc), ctypes.byref(n))
+    if st != EG_OK:
+        raise EGError(st, "eg_simplify")
+    k = int(n.value)
+    return {"arc_offsets": offs, "arc_maxima": arcs[:int(offs[-1])], "max_rep": rep[:g.nmax],
+            "pair_saddle": ps[:k], "pair_max": pm[:k], "pair_cost": pc[:k]}
+
+
+def simplify(result: "EGResult", field: "torch.Tensor", ops: int = SIMPLIFY_BUNDLE | SIMPLIFY_CANCEL,
+             threshold: float = 0.0, minima: bool = False) -> dict:
+    """Simplify the graph of an eg.build result of ``field``: the values at its
+    critical points are gathered on the device, the graph operations run on
+    the host (eg_simplify)."""
+    flat = field.reshape(-1)
+    mv = flat[result.maxima.long()].cpu().numpy()
+    sv = flat[result.saddles.long()].cpu().numpy()
+    return simplify_graph(result.maxima.cpu().numpy(), mv, result.saddles.cpu().numpy(), sv,
+                          result.arc_offsets.cpu().numpy(), result.arc_maxima.cpu().numpy(), ops, threshold, minima)

@@ -337,6 +337,30 @@ def test_paths_reject_pointers_of_another_field():
     assert int(b.p_header[eg.P_STATUS].item()) == eg.EG_ERR_ARG
 
 
+def test_simplify_gpu_graph_equals_reference():
+    """eg.simplify on a GPU-built graph (values gathered on the device) equals
+    the reference simplification of the oracle's graph."""
+    import torch
+    from oracle import simplify as S
+    from paper_2303_02724_amd import eg
+    f = W.gaussian_mixture((40, 36, 32), 12, n_gauss=6, noise=1e-3)
+    t = torch.from_numpy(f).cuda()
+    fv = f.reshape(-1)
+    for minima in (False, True):
+        r = eg.build(t, minima=minima)
+        want = O.extremum_graph(f, minima)
+        g = (want["maxima"], fv[want["maxima"]], want["saddles"], fv[want["saddles"]], want["arc_offsets"],
+             want["arc_maxima"])
+        thr = 0.05
+        lib = eg.simplify(r, t, threshold=thr, minima=minima)
+        sm, ss, rows, pairs = S.cancel(*g, thr, minima, keep=S.bundle(*g, minima=minima))
+        assert [(int(i), int(want["maxima"][m])) for i, m in zip(lib["pair_saddle"], lib["pair_max"])] == \
+            [(i, m) for i, m, _ in pairs]
+        lo, la = lib["arc_offsets"], lib["arc_maxima"]
+        assert {i: la[lo[i]:lo[i + 1]].tolist() for i in range(len(lo) - 1) if lo[i + 1] > lo[i]} == \
+            dict(zip(ss, rows))
+
+
 def test_batched_long_paths_several_passes():
     """Paths far longer than a tile and than the links one pass follows
     (16 here): the exit-list chains need several gated jump passes before the

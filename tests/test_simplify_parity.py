@@ -1,0 +1,63 @@
+"""The library's eg_simplify (host code, so these run without a GPU) against
+the reference in oracle/simplify.py, on graphs the oracle computed."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle import simplify as S
+from paper_2303_02724_amd import eg
+from paper_2303_02724_amd import workloads as W
+
+
+def _graph(f, minima):
+    g = O.extremum_graph(f, minima)
+    fv = np.asarray(f, np.float32).reshape(-1)
+    return (g["maxima"], fv[g["maxima"]], g["saddles"], fv[g["saddles"]], g["arc_offsets"], g["arc_maxima"])
+
+
+def _compare(g, ops, t, minima, ctx):
+    maxima, mv, sad, sv, offs, arcs = g
+    lib = eg.simplify_graph(*g, ops, t, minima)
+    keep = S.bundle(*g, minima=minima) if ops & eg.SIMPLIFY_BUNDLE else None
+    if ops & eg.SIMPLIFY_CANCEL:
+        sm, ss, rows, pairs = S.cancel(*g, t, minima, keep=keep)
+    else:
+        sm, ss, rows, pairs = S.cancel(*g, -np.inf, minima, keep=keep)
+    # cancellations, in order
+    got = [(int(i), int(maxima[m]), float(c)) for i, m, c in
+           zip(lib["pair_saddle"], lib["pair_max"], lib["pair_cost"])]
+    assert got == [(i, m, float(c)) for i, m, c in pairs], ctx
+    # surviving maxima and saddle rows
+    rep = lib["max_rep"]
+    assert sorted(int(maxima[j]) for j in range(len(maxima)) if rep[j] == j) == sm, ctx
+    lo, la = lib["arc_offsets"], lib["arc_maxima"]
+    got_rows = {i: la[lo[i]:lo[i + 1]].tolist() for i in range(len(sad)) if lo[i + 1] > lo[i]}
+    assert got_rows == dict(zip(ss, rows)), ctx
+
+
+@pytest.mark.parametrize("shape,kind", [((50,), "uniform"), ((40, 50), "mix"), ((24, 20, 18), "mix"),
+                                        ((14, 12, 10), "uniform"), ((30, 30), "ties"), ((8, 7, 6, 5), "uniform")])
+def test_library_simplify_equals_reference(shape, kind):
+    f = (W.gaussian_mixture(shape, 11, n_gauss=6, noise=1e-3) if kind == "mix"
+         else W.random_field(shape, 11, kind))
+    for minima in (False, True):
+        g = _graph(f, minima)
+        costs = [c for _, _, c in S.cancel(*g, np.inf, minima)[3]]
+        for ops in (eg.SIMPLIFY_BUNDLE, eg.SIMPLIFY_CANCEL, eg.SIMPLIFY_BUNDLE | eg.SIMPLIFY_CANCEL):
+            for t in (0.0, float(np.quantile(costs, 0.3)) if costs else 0.0, np.inf):
+                _compare(g, ops, t, minima, f"{shape} {kind} minima={minima} ops={ops} t={t}")
+
+
+def test_library_simplify_rejects_bad_graphs():
+    g = _graph(W.random_field((20, 20), 3), False)
+    maxima, mv, sad, sv, offs, arcs = g
+    with pytest.raises(eg.EGError):
+        eg.simplify_graph(maxima[::-1], mv, sad, sv, offs, arcs, 3, 1.0)  # maxima not ascending
+    bad = arcs.copy()
+    bad[0] = -5
+    with pytest.raises(eg.EGError):
+        eg.simplify_graph(maxima, mv, sad, sv, offs, bad, 3, 1.0)  # an arc to a non-maximum
+    with pytest.raises(eg.EGError):
+        eg.simplify_graph(*g, 8, 1.0)  # unknown operation
+    with pytest.raises(eg.EGError):
+        eg.simplify_graph(*g, 3, float("nan"))
