@@ -5,7 +5,9 @@ slowest, most literal way, straight from the paper's definitions.
 
 * Edges: GridAdjacency (Alg. 1) evaluated on *every pair* of grid vertices.
 * Order: simulated perturbation, compared as Python tuples (f[v], v); the
-  minimum graph compares (-f[v], -v), i.e. the reversed order.
+  minimum graph compares (-f[v], -v), i.e. the reversed order.  Integer and
+  float64 samples become Python ints and floats, which compare exactly;
+  other types are converted to float32 first.
 * Link, upper link, beta+: Sec. 3.3 and Table 1; components by BFS over the
   upper link with the link edges taken from the global edge set.
 * Gradient: the highest vertex of the upper link (Sec. 3.3).
@@ -31,11 +33,13 @@ def grid_adjacency(p, q) -> bool:
 
 
 def extremum_graph(f, minima: bool = False) -> dict:
-    f = np.asarray(f, dtype=np.float32)
+    f = np.asarray(f)
+    if not (np.issubdtype(f.dtype, np.integer) or f.dtype in (np.float32, np.float64)):
+        f = f.astype(np.float32)
     shape = f.shape
     verts = list(itertools.product(*[range(d) for d in shape]))  # C order
     N = len(verts)
-    vals = [float(x) for x in f.reshape(-1)]
+    vals = f.reshape(-1).tolist()
 
     def key(v):
         return (-vals[v], -v) if minima else (vals[v], v)

@@ -17,9 +17,11 @@
  *               outside the grid simply do not exist (truncated link).
  *   order       simulated perturbation (Sec. 3.3): a strict total order,
  *               u below v iff f[u] < f[v], or f[u] == f[v] and u < v, with u, v
- *               row-major linear indices (C order, dims[0] slowest).  IEEE
- *               comparison makes -0 equal to +0.  The minima graph uses the
- *               reversed order.
+ *               row-major linear indices (C order, dims[0] slowest).  Samples
+ *               are compared as values of the field's own type (8- to 64-bit
+ *               signed or unsigned integers, float32, float64: the input types
+ *               of Sec. 4); IEEE comparison makes -0 equal to +0.  The minima
+ *               graph uses the reversed order.
  *   upper link  U(v) = link vertices above v; link edges are pairs of link
  *               vertices that are themselves adjacent (Sec. 3.3).
  *   beta+       number of connected components of U(v), found by BFS over the
@@ -59,8 +61,13 @@
 
 enum { EGO_OK = 0, EGO_ERR_ARG = 1, EGO_ERR_NAN = 4, EGO_ERR_CAPACITY = 5, EGO_ERR_NOMEM = 7 };
 
+/* sample types */
+enum { EGO_F32 = 0, EGO_F64 = 1, EGO_I8 = 2, EGO_U8 = 3, EGO_I16 = 4, EGO_U16 = 5, EGO_I32 = 6, EGO_U32 = 7,
+       EGO_I64 = 8, EGO_U64 = 9, EGO_NTYPES = 10 };
+
 typedef struct {
-    const float* f;
+    const void* f;
+    int dtype;
     int n;
     int64_t dims[EGO_MAXDIM];
     int64_t N;
@@ -96,13 +103,43 @@ static int grid_adjacent(int n, const int64_t* p, const int64_t* q)
     return !same && (in01 || in0m1);
 }
 
+/* Sign of f[a] - f[b], comparing the samples as values of their own type. */
+#define EGO_CMP(T)                                                   \
+    {                                                                \
+        const T x = ((const T*)g->f)[a], y = ((const T*)g->f)[b];    \
+        return (x > y) - (x < y);                                    \
+    }
+static int value_cmp(const grid_t* g, int64_t a, int64_t b)
+{
+    switch (g->dtype) {
+        case EGO_F32: EGO_CMP(float)
+        case EGO_F64: EGO_CMP(double)
+        case EGO_I8: EGO_CMP(int8_t)
+        case EGO_U8: EGO_CMP(uint8_t)
+        case EGO_I16: EGO_CMP(int16_t)
+        case EGO_U16: EGO_CMP(uint16_t)
+        case EGO_I32: EGO_CMP(int32_t)
+        case EGO_U32: EGO_CMP(uint32_t)
+        case EGO_I64: EGO_CMP(int64_t)
+        default: EGO_CMP(uint64_t)
+    }
+}
+#undef EGO_CMP
+
+static int is_nan(const grid_t* g, int64_t v)
+{
+    if (g->dtype == EGO_F32) return isnan(((const float*)g->f)[v]);
+    if (g->dtype == EGO_F64) return isnan(((const double*)g->f)[v]);
+    return 0;
+}
+
 /* a above b in the order that defines the graph (maxima: the simulated
  * perturbation order; minima: its reverse). */
 static int above(const grid_t* g, int64_t a, int64_t b)
 {
-    float fa = g->f[a], fb = g->f[b];
-    if (!g->minima) return fa > fb || (fa == fb && a > b);
-    return fb > fa || (fb == fa && b > a);
+    const int c = value_cmp(g, a, b);
+    if (!g->minima) return c > 0 || (c == 0 && a > b);
+    return c < 0 || (c == 0 && b > a);
 }
 
 /* All neighbours of v: every offset in {-1,0,1}^n \ {0} whose target lies in
@@ -189,10 +226,11 @@ static int classify_vertex_mins(const grid_t* g, int64_t v, int64_t* ptr_out, in
     return ncomp;
 }
 
-static int setup(grid_t* g, const float* f, int ndim, const int64_t* dims, int minima)
+static int setup(grid_t* g, const void* f, int dtype, int ndim, const int64_t* dims, int minima)
 {
-    if (!f || ndim < 1 || ndim > EGO_MAXDIM || !dims) return EGO_ERR_ARG;
+    if (!f || dtype < 0 || dtype >= EGO_NTYPES || ndim < 1 || ndim > EGO_MAXDIM || !dims) return EGO_ERR_ARG;
     g->f = f;
+    g->dtype = dtype;
     g->n = ndim;
     g->minima = minima ? 1 : 0;
     g->N = 1;
@@ -216,21 +254,21 @@ int ego_num_threads(void)
 }
 
 /* Neighbour ids of vertex v (count returned; at most 3^ndim - 1). */
-int ego_neighbours(const float* f, int ndim, const int64_t* dims, int64_t v, int64_t* out)
+int ego_neighbours(const void* f, int dtype, int ndim, const int64_t* dims, int64_t v, int64_t* out)
 {
     grid_t g;
-    if (setup(&g, f, ndim, dims, 0) != EGO_OK || v < 0 || v >= g.N) return -1;
+    if (setup(&g, f, dtype, ndim, dims, 0) != EGO_OK || v < 0 || v >= g.N) return -1;
     int64_t coords[EGO_MAXNB][EGO_MAXDIM];
     return neighbours(&g, v, out, coords);
 }
 
 /* One vertex: gradient target, beta+ and the reps (highest vertex of each
  * upper-link component, in ascending vertex order). */
-int ego_vertex(const float* f, int ndim, const int64_t* dims, int minima, int64_t v,
+int ego_vertex(const void* f, int dtype, int ndim, const int64_t* dims, int minima, int64_t v,
                int64_t* ptr_out, int64_t* reps_out)
 {
     grid_t g;
-    if (setup(&g, f, ndim, dims, minima) != EGO_OK || v < 0 || v >= g.N) return -1;
+    if (setup(&g, f, dtype, ndim, dims, minima) != EGO_OK || v < 0 || v >= g.N) return -1;
     int64_t reps[EGO_MAXNB];
     int b = classify_vertex(&g, v, ptr_out, reps);
     /* ascending order for a canonical result */
@@ -245,10 +283,10 @@ int ego_vertex(const float* f, int ndim, const int64_t* dims, int minima, int64_
 }
 
 /* Label of one vertex: walk the gradient until it stops at a maximum. */
-int64_t ego_label_of(const float* f, int ndim, const int64_t* dims, int minima, int64_t v)
+int64_t ego_label_of(const void* f, int dtype, int ndim, const int64_t* dims, int minima, int64_t v)
 {
     grid_t g;
-    if (setup(&g, f, ndim, dims, minima) != EGO_OK || v < 0 || v >= g.N) return -1;
+    if (setup(&g, f, dtype, ndim, dims, minima) != EGO_OK || v < 0 || v >= g.N) return -1;
     int64_t reps[EGO_MAXNB];
     for (;;) {
         int64_t nxt;
@@ -260,14 +298,14 @@ int64_t ego_label_of(const float* f, int ndim, const int64_t* dims, int minima, 
 
 /* Whole-field pass 1: per-vertex gradient target and beta+.
  * Returns EGO_ERR_NAN if any sample is NaN (outputs then undefined). */
-int ego_classify(const float* f, int ndim, const int64_t* dims, int minima,
+int ego_classify(const void* f, int dtype, int ndim, const int64_t* dims, int minima,
                  int32_t* ptr, int32_t* beta)
 {
     grid_t g;
-    int st = setup(&g, f, ndim, dims, minima);
+    int st = setup(&g, f, dtype, ndim, dims, minima);
     if (st != EGO_OK) return st;
     for (int64_t v = 0; v < g.N; ++v)
-        if (isnan(f[v])) return EGO_ERR_NAN;
+        if (is_nan(&g, v)) return EGO_ERR_NAN;
     int64_t N = g.N;
 #pragma omp parallel for schedule(dynamic, 4096)
     for (int64_t v = 0; v < N; ++v) {
@@ -326,12 +364,12 @@ static int saddle_row(const grid_t* g, const int32_t* labels, int64_t s, int32_t
     return len;
 }
 
-int ego_arcs(const float* f, int ndim, const int64_t* dims, int minima,
+int ego_arcs(const void* f, int dtype, int ndim, const int64_t* dims, int minima,
              const int32_t* labels, const int32_t* saddles, int64_t n_sad,
              int32_t* offsets, int32_t* arc_maxima, int64_t cap_arc, int64_t* n_arc)
 {
     grid_t g;
-    int st = setup(&g, f, ndim, dims, minima);
+    int st = setup(&g, f, dtype, ndim, dims, minima);
     if (st != EGO_OK) return st;
     /* sweep 1: row lengths into offsets[i+1] */
     offsets[0] = 0;
@@ -396,13 +434,13 @@ static int64_t path_length(const int32_t* ptr, int64_t r)
     return len;
 }
 
-int ego_paths(const float* f, int ndim, const int64_t* dims, int minima, const int32_t* ptr,
+int ego_paths(const void* f, int dtype, int ndim, const int64_t* dims, int minima, const int32_t* ptr,
               const int32_t* saddles, int64_t n_sad, int32_t* pair_offsets, int32_t* path_offsets,
               int64_t cap_pairs, int32_t* vertices, int64_t cap_vertices, int64_t* n_pairs,
               int64_t* n_vertices)
 {
     grid_t g;
-    int st = setup(&g, f, ndim, dims, minima);
+    int st = setup(&g, f, dtype, ndim, dims, minima);
     if (st != EGO_OK) return st;
     int64_t* vcount = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_sad > 0 ? n_sad : 1));
     if (!vcount) return EGO_ERR_NOMEM;

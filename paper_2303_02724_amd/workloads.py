@@ -188,3 +188,49 @@ def random_field(shape, seed: int, kind: str = "uniform") -> np.ndarray:
     else:
         raise ValueError(kind)
     return a.astype(np.float32)
+
+
+TYPED = ("float64", "int8", "uint8", "int16", "uint16", "int32", "uint32", "int64", "uint64")
+
+
+def typed_field(shape, seed: int, dtype: str) -> np.ndarray:
+    """Fields of other sample types, drawn so that a comparison made in a
+    narrower or differently signed type would change the order:
+
+    * float64: small integers plus multiples of 2^-40 (equal after rounding to
+      float32, distinct in float64), with -0, +0 and infinities mixed in;
+    * 8- and 16-bit integers: a handful of values drawn over the whole range
+      plus its two ends (many ties);
+    * 32-bit: a few clusters spread over the whole range (both sides of 2^31
+      for uint32, of 0 for int32), members 0..3 apart (equal in float32);
+    * 64-bit: the same with clusters spread over the whole 64-bit range
+      (members equal in float64).
+    """
+    rng = _rng(seed)
+    shape = tuple(int(s) for s in shape)
+    n = int(np.prod(shape))
+    dt = np.dtype(dtype)
+    if dt == np.float64:
+        a = rng.integers(0, 4, size=n).astype(np.float64) + rng.integers(0, 4, size=n) * 2.0 ** -40
+        special = rng.random(n)
+        a[special < 0.04] = -0.0
+        a[(special >= 0.04) & (special < 0.08)] = 0.0
+        a[(special >= 0.08) & (special < 0.10)] = np.inf
+        a[(special >= 0.10) & (special < 0.12)] = -np.inf
+        return a.reshape(shape)
+    info = np.iinfo(dt)
+    if dt.itemsize <= 2:
+        vals = np.concatenate([rng.integers(int(info.min), int(info.max) + 1, size=5, dtype=np.int64),
+                               [int(info.min), int(info.max)]])
+        return vals[rng.integers(0, vals.size, size=n)].astype(dt).reshape(shape)
+    # cluster centres anywhere in the range (kept 4 away from its ends), then small offsets
+    lo, hi = int(info.min), int(info.max) - 4
+    centres = [int(x) for x in rng.integers(0, 2 ** 62, size=4)]
+    span = hi - lo
+    cs = [lo + (c * span) // (2 ** 62) for c in centres] + [lo, hi, (lo + hi) // 2]
+    pick = rng.integers(0, len(cs), size=n)
+    off = rng.integers(0, 4, size=n)
+    out = np.empty(n, dtype=dt)
+    for i in range(n):
+        out[i] = cs[int(pick[i])] + int(off[i])
+    return out.reshape(shape)

@@ -16,7 +16,7 @@ from tests import test_oracle_pins as P
 
 MUTANTS = {
     # tie-break direction reversed (equal values: smaller index wins)
-    "tie_break": ("return fa > fb || (fa == fb && a > b);", "return fa > fb || (fa == fb && a < b);"),
+    "tie_break": ("return c > 0 || (c == 0 && a > b);", "return c > 0 || (c == 0 && a < b);"),
     # mixed-sign offsets accepted: the 3^n - 1 box neighbourhood instead of Alg. 1
     "adjacency_mixed_signs": ("if (!(d == 0 || d == -1)) in0m1 = 0;",
                               "if (!(d == 0 || d == -1 || d == 1)) in0m1 = 0;"),
@@ -40,8 +40,16 @@ MUTANTS = {
     "no_dedup": ("if (len == 0 || row[len - 1] != row[j]) row[len++] = row[j];",
                  "row[len++] = row[j];"),
     # minima graph obtained by negating values but keeping the index tie-break
-    "minima_negate_only": ("return fb > fa || (fb == fa && b > a);",
-                           "return fb > fa || (fb == fa && a > b);"),
+    "minima_negate_only": ("return c < 0 || (c == 0 && b > a);",
+                           "return c < 0 || (c == 0 && a > b);"),
+    # float64 samples compared after rounding to float32
+    "f64_as_f32": ("case EGO_F64: EGO_CMP(double)", "case EGO_F64: EGO_CMP(float)"),
+    # 64-bit integers compared through double (exact only below 2^53)
+    "i64_as_double": ("case EGO_I64: EGO_CMP(int64_t)",
+                      "case EGO_I64: { const double x = (double)((const int64_t*)g->f)[a],"
+                      " y = (double)((const int64_t*)g->f)[b]; return (x > y) - (x < y); }"),
+    # unsigned 32-bit samples compared as signed
+    "u32_as_signed": ("case EGO_U32: EGO_CMP(uint32_t)", "case EGO_U32: EGO_CMP(int32_t)"),
     # paths of a saddle ordered by their reps instead of the components' smallest vertex
     "paths_order_by_rep": ("int64_t x = ((const comp_t*)a)->lo, y = ((const comp_t*)b)->lo;",
                            "int64_t x = ((const comp_t*)a)->rep, y = ((const comp_t*)b)->rep;"),
@@ -67,6 +75,8 @@ def _pins():
     P.test_minima_graph_is_flipped_negated_maxima_graph((5, 4, 6))
     for shape in [(6, 7), (5, 4, 3)]:
         P.test_paths_match_brute(shape, "uniform")
+    for dt in P.TYPED:
+        P.test_typed_fields_match_brute(dt)
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))

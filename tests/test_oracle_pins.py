@@ -428,3 +428,41 @@ def test_sampled_queries_match_whole_field():
         p, b, reps = O.vertex(f, int(v))
         assert p == g["ptr"][v] and b == g["beta"][v]
         assert O.label_of(f, int(v)) == g["labels"][v]
+
+
+# ------------------------------------------------------------------ sample types
+
+TYPED = W.TYPED
+
+
+@pytest.mark.parametrize("dt", TYPED)
+def test_typed_fields_match_brute(dt):
+    """Every sample type the paper's input accepts (Sec. 4) is compared in its
+    own type: the brute force compares Python ints / floats exactly."""
+    for shape in [(23,), (6, 7), (4, 3, 4), (3, 2, 3, 3), (2, 3, 2, 2, 3)]:
+        f = W.typed_field(shape, 5 + len(shape), dt)
+        for minima in (False, True):
+            _same(O.extremum_graph(f, minima), B.extremum_graph(f, minima))
+
+
+@pytest.mark.parametrize("dt", TYPED)
+def test_typed_fields_rank_invariance(dt):
+    """The graph depends on the order only: a typed field and its float32 rank
+    field (ranks by numpy's stable sort of the native values) agree."""
+    for shape in [(40, 33), (12, 11, 10), (6, 5, 6, 5)]:
+        f = W.typed_field(shape, 9, dt)
+        flat = f.reshape(-1)
+        if flat.dtype == np.float64:
+            flat = np.where(flat == 0, 0.0, flat)  # -0 == +0 before the sort
+        order = np.argsort(flat, kind="stable")
+        rank = np.empty(flat.size, np.float32)
+        rank[order] = np.arange(flat.size, dtype=np.float32)
+        for minima in (False, True):
+            _same(O.extremum_graph(f, minima), O.extremum_graph(rank.reshape(f.shape), minima))
+
+
+def test_float64_nan_rejected():
+    f = W.typed_field((5, 4), 1, "float64")
+    f[1, 2] = np.nan
+    with pytest.raises(O.OracleError):
+        O.extremum_graph(f)
