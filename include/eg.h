@@ -2,7 +2,8 @@
  * eg.h -- C ABI of the MI355X extremum-graph library (libeg_hip.so).
  *
  * Computes the extremum graph of a piecewise-linear scalar field sampled on an
- * n-dimensional grid (n = 1..5), following Ande, Subhash and Natarajan,
+ * n-dimensional grid (n = 1..5; float32 samples, other sample types through
+ * eg_order_field), following Ande, Subhash and Natarajan,
  * "TACHYON: Efficient Shared Memory Parallel Computation of Extremum Graphs":
  *
  *   - grid vertices are the integer points of the box dims[0] x ... x dims[n-1],
@@ -233,7 +234,8 @@ eg_status eg_paths(const float* field, int ndim, const int64_t* dims, void* stre
  *                       k - 1 times.  Applied after bundling when both are set.
  *
  * Heights are the field values in the graph's order (ties by vertex id),
- * reversed for a minimum graph (flags = EG_MINIMA).  All pointers are host
+ * reversed for a minimum graph (flags = EG_MINIMA), passed as doubles (exact
+ * for every sample type except 64-bit integers of magnitude above 2^53).  All pointers are host
  * memory.  Inputs: the graph as eg_build returns it (ascending maxima and
  * saddles, CSR arcs of maxima ids) and the field value at every maximum and
  * saddle.  Outputs:
@@ -253,10 +255,10 @@ typedef struct eg_graph_host {
     uint32_t flags;
     int64_t nmax;
     const int32_t* maxima;
-    const float* max_values;
+    const double* max_values;
     int64_t nsad;
     const int32_t* saddles;
-    const float* sad_values;
+    const double* sad_values;
     const int32_t* arc_offsets;
     const int32_t* arc_maxima;
 } eg_graph_host;
@@ -298,6 +300,68 @@ eg_status eg_batch_plan(int count, const float* const* fields, const int* ndims,
                         const eg_out* outs, void* batch_ws, size_t batch_ws_bytes, void* host_plan,
                         size_t host_plan_bytes);
 eg_status eg_build_batched(const void* host_plan, void* stream);
+
+/*
+ * Sample types (Sec. 4: the input may hold 8- to 64-bit signed or unsigned
+ * integers, or 32- or 64-bit floats).  The graph depends on the samples only
+ * through the simulated-perturbation order (Sec. 3.3: u below v iff f[u] <
+ * f[v] compared in the sample type, or equal and u < v), so a field of any
+ * type is first turned into a float32 field with exactly the same order, its
+ * order surrogate, and eg_build then runs unchanged on that:
+ *
+ *   EG_F32                  a copy
+ *   EG_I8, EG_U8, EG_I16,   the value converted to float32 (exact, ties kept)
+ *   EG_U16
+ *   EG_I32, EG_U32, EG_I64, the rank of (value, index) in the order, encoded
+ *   EG_U64, EG_F64          as a strictly increasing float32 (no ties left):
+ *                           a stable LSD radix sort of order-preserving
+ *                           integer keys of the values
+ *
+ * For float types -0 equals +0 and infinities order normally; a NaN in the
+ * field leaves NaN in the surrogate (every entry, for EG_F64), so eg_build then
+ * reports EG_ERR_NAN.
+ */
+typedef enum eg_dtype {
+    EG_F32 = 0,
+    EG_F64 = 1,
+    EG_I8 = 2,
+    EG_U8 = 3,
+    EG_I16 = 4,
+    EG_U16 = 5,
+    EG_I32 = 6,
+    EG_U32 = 7,
+    EG_I64 = 8,
+    EG_U64 = 9
+} eg_dtype;
+
+/*
+ * Workspace bytes eg_order_field needs for n samples of the given type: 0 for
+ * EG_F32 and the 8- and 16-bit types; about 2(sizeof key + 4) bytes per sample
+ * for the ranked types (the key is 4 bytes for 32-bit types, 8 for 64-bit
+ * ones) plus a fixed part.  Host-only; 0 also for invalid arguments (unknown
+ * dtype, n < 1 or n >= 2^31).
+ */
+size_t eg_order_workspace_bytes(int dtype, int64_t n);
+
+/*
+ * Order surrogate of a field of n samples (any shape: the order does not
+ * depend on it).
+ *
+ *   dtype      an eg_dtype
+ *   field      device, n samples of that type, read-only
+ *   out        device, float32[n]: for all u, v, (out[u], u) is below
+ *              (out[v], v) in the simulated-perturbation order iff (field[u],
+ *              u) is below (field[v], v); may not overlap field
+ *   workspace  device, 256-byte aligned, eg_order_workspace_bytes(dtype, n)
+ *              bytes (may be NULL when that is 0)
+ *   stream     hipStream_t (as void*) on which the work is queued
+ *
+ * Host errors: EG_ERR_ARG (unknown dtype, NULL field/out, n < 1, out
+ * overlapping field), EG_ERR_TOO_LARGE (n >= 2^31), EG_ERR_WORKSPACE, EG_ERR_HIP.
+ * Never allocates or synchronises.
+ */
+eg_status eg_order_field(int dtype, const void* field, int64_t n, float* out, void* workspace, size_t ws_bytes,
+                         void* stream);
 
 /* Human-readable name of a status code (static string). */
 const char* eg_status_string(int status);

@@ -5,7 +5,8 @@ every step of the computation runs in the library's HIP kernels.  There is
 no CPU path: if the library is missing or no HIP device is present, the
 calls raise.
 
-    res = eg.build(field)                # field: float32 CUDA tensor, n = 1..5 axes
+    res = eg.build(field)                # field: CUDA tensor, n = 1..5 axes
+                                         # (float32; other types via eg_order_field)
     res.maxima, res.saddles, res.arc_offsets, res.arc_maxima, res.labels
 
 ``Builder`` keeps the buffers of one shape allocated so that repeated calls
@@ -17,6 +18,7 @@ import ctypes
 import os
 from dataclasses import dataclass, field as dc_field
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -124,6 +126,10 @@ def lib():
     L.eg_build_batched.restype = ctypes.c_int
     L.eg_status_string.argtypes = [ctypes.c_int]
     L.eg_status_string.restype = ctypes.c_char_p
+    L.eg_order_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_int64]
+    L.eg_order_workspace_bytes.restype = ctypes.c_size_t
+    L.eg_order_field.argtypes = [ctypes.c_int, vp, ctypes.c_int64, vp, vp, ctypes.c_size_t, vp]
+    L.eg_order_field.restype = ctypes.c_int
     L.eg_link_table.argtypes = [ctypes.c_int, vp, vp]
     L.eg_link_table.restype = ctypes.c_int
     _lib = L
@@ -188,6 +194,48 @@ class EGPaths:
     vertices: torch.Tensor
 
 
+# eg_dtype codes of the sample types eg_order_field accepts
+DTYPES = {torch.float32: 0, torch.float64: 1, torch.int8: 2, torch.uint8: 3, torch.int16: 4, torch.uint16: 5,
+          torch.int32: 6, torch.uint32: 7, torch.int64: 8, torch.uint64: 9}
+
+
+def order_workspace_bytes(dtype: torch.dtype, n: int) -> int:
+    if dtype not in DTYPES:
+        raise EGError(EG_ERR_ARG, f"unsupported sample type {dtype}")
+    return int(lib().eg_order_workspace_bytes(DTYPES[dtype], int(n)))
+
+
+class Order:
+    """Buffers of eg_order_field for fields of one type and size: the float32
+    order surrogate and the sort workspace, allocated once."""
+
+    def __init__(self, dtype: torch.dtype, n: int, device):
+        self.dtype, self.n = dtype, int(n)
+        self.out = torch.empty(self.n, dtype=torch.float32, device=device)
+        self.ws_bytes = order_workspace_bytes(dtype, self.n)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device) if self.ws_bytes else None
+
+    def launch(self, field: torch.Tensor, stream=None) -> torch.Tensor:
+        """Queue eg_order_field on ``stream``; returns the surrogate (flat)."""
+        if field.dtype != self.dtype or field.numel() != self.n or not field.is_cuda or not field.is_contiguous():
+            raise EGError(EG_ERR_ARG, "field does not match this Order's type and size")
+        s = stream if stream is not None else torch.cuda.current_stream(field.device)
+        ws = ((self.ws.data_ptr() + 255) & ~255) if self.ws is not None else None
+        st = lib().eg_order_field(DTYPES[self.dtype], ctypes.c_void_p(field.data_ptr()), self.n,
+                                  ctypes.c_void_p(self.out.data_ptr()), ws, self.ws_bytes,
+                                  ctypes.c_void_p(s.cuda_stream))
+        if st != EG_OK:
+            raise EGError(st, "eg_order_field")
+        return self.out
+
+
+def order_field(field: torch.Tensor, stream=None) -> torch.Tensor:
+    """Float32 field with the same simulated-perturbation order as ``field``
+    (any eg_dtype), in ``field``'s shape."""
+    field = field.contiguous()
+    return Order(field.dtype, field.numel(), field.device).launch(field, stream).view(field.shape)
+
+
 class Builder:
     """Device buffers for repeated extremum-graph builds of one grid shape.
 
@@ -248,15 +296,28 @@ class Builder:
         self.out = o
         self._dims = _dims(self.shape)
 
+    def _float_field(self, field: torch.Tensor, s) -> torch.Tensor:
+        """``field`` itself for float32, else its order surrogate (queued on s)."""
+        if not field.is_cuda or not field.is_contiguous():
+            raise EGError(EG_ERR_ARG, "field must be a contiguous device tensor")
+        if field.numel() != self.n:
+            raise EGError(EG_ERR_ARG, f"field has {field.numel()} values, builder expects {self.n}")
+        if field.dtype == torch.float32:
+            return field
+        if field.dtype not in DTYPES:
+            raise EGError(EG_ERR_ARG, f"unsupported sample type {field.dtype}")
+        o = getattr(self, "_order", None)
+        if o is None or o.dtype != field.dtype:
+            o = self._order = Order(field.dtype, self.n, self.device)
+        return o.launch(field, s)
+
     def launch(self, field: torch.Tensor, stream=None, stage: str = "all"):
         """Queue the whole path (``stage="all"``, eg_build) or one stage
         (``"classify"``, ``"label"``, ``"arcs"``) on ``stream`` (default: the
-        current stream)."""
-        if field.dtype != torch.float32 or not field.is_cuda or not field.is_contiguous():
-            raise EGError(EG_ERR_ARG, "field must be a contiguous float32 device tensor")
-        if field.numel() != self.n:
-            raise EGError(EG_ERR_ARG, f"field has {field.numel()} values, builder expects {self.n}")
+        current stream).  Fields of other sample types than float32 are first
+        replaced by their order surrogate (eg_order_field)."""
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        field = self._float_field(field, s)
         fn = {"all": lib().eg_build, "classify": lib().eg_classify, "label": lib().eg_label,
               "arcs": lib().eg_arcs}[stage]
         st = fn(ctypes.c_void_p(field.data_ptr()), len(self.shape), self._dims,
@@ -321,6 +382,7 @@ class Builder:
         if self.ptr is None:
             raise EGError(EG_ERR_ARG, "paths need the steepest-ascent pointers: Builder(..., want_ptr=True)")
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        field = self._float_field(field, s)
         st = lib().eg_paths(ctypes.c_void_p(field.data_ptr()), len(self.shape), self._dims,
                             ctypes.c_void_p(s.cuda_stream), ctypes.byref(self.out), ctypes.byref(self.pout))
         if st != EG_OK:
@@ -491,7 +553,8 @@ def build_paths(field: torch.Tensor, minima: bool = False, tuning: int = 0, **ca
 
 def build(field: torch.Tensor, minima: bool = False, want_ptr: bool = False, tuning: int = 0,
           **caps) -> EGResult:
-    """Extremum graph of ``field`` (float32 device tensor, 1..5 axes)."""
+    """Extremum graph of ``field`` (device tensor, 1..5 axes; float32, or any
+    other type of DTYPES through its order surrogate)."""
     b = Builder(field.shape, minima=minima, want_ptr=want_ptr, device=field.device, tuning=tuning, **caps)
     return b.run(field.contiguous())
 
@@ -507,9 +570,9 @@ def simplify_graph(maxima, max_values, saddles, sad_values, arc_offsets, arc_max
 
     arr = {
         "maxima": np.ascontiguousarray(maxima, dtype=np.int32),
-        "max_values": np.ascontiguousarray(max_values, dtype=np.float32),
+        "max_values": np.ascontiguousarray(max_values, dtype=np.float64),
         "saddles": np.ascontiguousarray(saddles, dtype=np.int32),
-        "sad_values": np.ascontiguousarray(sad_values, dtype=np.float32),
+        "sad_values": np.ascontiguousarray(sad_values, dtype=np.float64),
         "arc_offsets": np.ascontiguousarray(arc_offsets, dtype=np.int32),
         "arc_maxima": np.ascontiguousarray(arc_maxima, dtype=np.int32),
     }
@@ -542,7 +605,15 @@ def simplify(result: "EGResult", field: "torch.Tensor", ops: int = SIMPLIFY_BUND
     critical points are gathered on the device, the graph operations run on
     the host (eg_simplify)."""
     flat = field.reshape(-1)
-    mv = flat[result.maxima.long()].cpu().numpy()
-    sv = flat[result.saddles.long()].cpu().numpy()
+    unsigned = {torch.uint16: (torch.int16, np.uint16), torch.uint32: (torch.int32, np.uint32),
+                torch.uint64: (torch.int64, np.uint64)}
+    if flat.dtype in unsigned:  # gather the bits through the signed type of the same width
+        signed, host = unsigned[flat.dtype]
+        flat = flat.view(signed)
+        mv = flat[result.maxima.long()].cpu().numpy().view(host).astype(np.float64)
+        sv = flat[result.saddles.long()].cpu().numpy().view(host).astype(np.float64)
+    else:
+        mv = flat[result.maxima.long()].cpu().numpy().astype(np.float64)
+        sv = flat[result.saddles.long()].cpu().numpy().astype(np.float64)
     return simplify_graph(result.maxima.cpu().numpy(), mv, result.saddles.cpu().numpy(), sv,
                           result.arc_offsets.cpu().numpy(), result.arc_maxima.cpu().numpy(), ops, threshold, minima)

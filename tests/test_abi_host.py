@@ -218,3 +218,31 @@ def test_paths_rejects_bad_arguments_on_host():
     assert L.eg_paths(fake, 2, dims, None, ctypes.byref(o), ctypes.byref(po)) == eg.EG_ERR_ARG
     # the field and workspace checks of eg_build come first
     assert L.eg_paths(None, 2, dims, None, ctypes.byref(o), ctypes.byref(po)) == eg.EG_ERR_ARG
+
+
+def test_order_field_host_checks():
+    L = eg.lib()
+    fake, out = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x900000)
+    # workspace sizes: none for copies and conversions, keys + indices for ranks
+    for dt in (0, 2, 3, 4, 5):
+        assert L.eg_order_workspace_bytes(dt, 1000) == 0
+    for dt, kb in ((6, 4), (7, 4), (1, 8), (8, 8), (9, 8)):
+        n = 1 << 20
+        b = L.eg_order_workspace_bytes(dt, n)
+        assert b >= 2 * (kb + 4) * n
+        assert b < 2 * (kb + 4) * n + (4 << 20)
+    for dt, n in ((10, 5), (-1, 5), (1, 0), (1, 1 << 31)):
+        assert L.eg_order_workspace_bytes(dt, n) == 0
+    ws = ctypes.c_void_p(0x4000000)
+    assert L.eg_order_field(10, fake, 100, out, ws, 1 << 30, None) == eg.EG_ERR_ARG
+    assert L.eg_order_field(1, None, 100, out, ws, 1 << 30, None) == eg.EG_ERR_ARG
+    assert L.eg_order_field(1, fake, 100, None, ws, 1 << 30, None) == eg.EG_ERR_ARG
+    assert L.eg_order_field(1, fake, 0, out, ws, 1 << 30, None) == eg.EG_ERR_ARG
+    assert L.eg_order_field(1, fake, 1 << 31, out, ws, 1 << 30, None) == eg.EG_ERR_TOO_LARGE
+    # out overlapping the field
+    assert L.eg_order_field(1, fake, 100, ctypes.c_void_p(0x100000 + 400), ws, 1 << 30, None) == eg.EG_ERR_ARG
+    # ranked types need an aligned workspace of the queried size
+    need = L.eg_order_workspace_bytes(1, 100)
+    assert L.eg_order_field(1, fake, 100, out, None, need, None) == eg.EG_ERR_WORKSPACE
+    assert L.eg_order_field(1, fake, 100, out, ctypes.c_void_p(0x4000010), need, None) == eg.EG_ERR_WORKSPACE
+    assert L.eg_order_field(1, fake, 100, out, ws, need - 1, None) == eg.EG_ERR_WORKSPACE
