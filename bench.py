@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--stage-reps", type=int, default=20, help="repetitions for the per-stage timings")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-paths", action="store_true", help="skip the gradient-path geometry measurement")
+    ap.add_argument("--no-typed", action="store_true", help="skip the other-sample-type measurement")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (library default tile shape and links per pass)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -130,6 +131,47 @@ def measure_paths(args, f, t, tuning):
     del b, p
     torch.cuda.empty_cache()
     return res
+
+
+def measure_typed(args, t, tuning):
+    """Other sample types (eg_order_field, then the float32 path): the same
+    field as float64 (the order surrogate sorts all 64 key bits), quantised to
+    int32 (2^20 steps per unit) and to int16 (2^10 steps per unit).  HIP-event
+    times of the surrogate alone and of surrogate plus build."""
+    import torch
+
+    from paper_2303_02724_amd import eg
+
+    variants = {"f64": t.double(), "i32": torch.round(t.double() * 2.0 ** 20).to(torch.int32),
+                "i16": torch.clamp(torch.round(t * 2.0 ** 10), -32768, 32767).to(torch.int16)}
+    b = eg.Builder(t.shape, minima=args.minima, device=t.device, tuning=tuning)
+    s = torch.cuda.current_stream()
+    reps = max(3, args.stage_reps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {}
+    for name, x in variants.items():
+        o = eg.Order(x.dtype, x.numel(), x.device)
+        o.launch(x, s)
+        e0.record(s)
+        for _ in range(reps):
+            o.launch(x, s)
+        e1.record(s)
+        e1.synchronize()
+        order_ms = e0.elapsed_time(e1) / reps
+        b.run(x)
+        e0.record(s)
+        for _ in range(reps):
+            b.launch(x, stream=s)
+        e1.record(s)
+        e1.synchronize()
+        total_ms = e0.elapsed_time(e1) / reps
+        out[name] = {"order_ms": round(order_ms, 3), "build_ms": round(total_ms, 3),
+                     "G_vertices_per_s": round(x.numel() / (total_ms * 1e-3) / 1e9, 2),
+                     "order_workspace_MB": round(o.ws_bytes / 2 ** 20, 1)}
+        del o
+    del b, variants
+    torch.cuda.empty_cache()
+    return out
 
 
 def measure_simplify(res, t, minima):
@@ -523,6 +565,8 @@ def main():
     if not args.no_paths:
         out["paths"] = measure_paths(args, f, t, tuning)
     out["simplify"] = measure_simplify(res, t, args.minima)
+    if not args.no_typed:
+        out["typed"] = measure_typed(args, t, tuning)
     if args.profile_stage:
         torch.cuda.synchronize()
         if args.profile_stage != "classify":

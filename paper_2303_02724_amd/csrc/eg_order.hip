@@ -21,7 +21,9 @@
 // first, the host never waits).  Each pass: per-block digit histograms, a
 // scan of each digit's row over the blocks, and a stable scatter in which a
 // block ranks a tile of 2048 keys by wave ballots, sorts the tile by digit in
-// LDS and writes each digit's run contiguously.
+// LDS and writes each digit's run contiguously.  The last pass that runs
+// writes no keys: each element's final position is its rank, stored straight
+// into the surrogate (one 4-byte store per vertex, at no particular place).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -34,7 +36,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kItems = 8;
 constexpr int kTile = kThreads * kItems;  // keys per scatter round
-constexpr int kMaxBlocks = 2048;          // histogram columns
+constexpr int kMaxBlocks = 1024;          // histogram columns: every block resident at once
 constexpr int kDigits = 256;
 static_assert(kThreads == kDigits, "one thread per digit");
 
@@ -211,6 +213,15 @@ __global__ __launch_bounds__(kThreads) void k_range(const uint64_t* __restrict__
     }
 }
 
+// The p-th float of a strictly increasing sequence of normal floats, p < 2^31:
+// negative normals for p < 2^30, positive ones above.
+__device__ __forceinline__ float rank_float(uint32_t p)
+{
+    const int64_t t = int64_t(p) - (int64_t(1) << 30);
+    const uint32_t bits = t >= 0 ? 0x00800000u + (uint32_t)t : 0x80800000u + (uint32_t)(-t - 1);
+    return __uint_as_float(bits);
+}
+
 template <typename K>
 __device__ __forceinline__ uint32_t digit(K k, K kmin, int shift)
 {
@@ -280,7 +291,8 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const K* __restrict__ kin,
                                                       K* __restrict__ kout, uint32_t* __restrict__ iout, uint32_t n,
                                                       uint32_t per, int shift, const Ctl* __restrict__ ctl,
                                                       const uint32_t* __restrict__ hist,
-                                                      const uint32_t* __restrict__ rows, bool first)
+                                                      const uint32_t* __restrict__ rows, bool first,
+                                                      float* __restrict__ out)
 {
     __shared__ uint32_t run[kDigits];   // next output position of each digit
     __shared__ uint32_t tcnt[kDigits];  // digit counts of the tile
@@ -294,6 +306,8 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const K* __restrict__ kin,
     chunk(n, per, blockIdx.x, lo, hi);
     if (lo >= hi) return;
     const K kmin = (K)ctl->kmin;
+    const bool last = (uint32_t)shift + 8u >= ctl->nbits;
+    const bool nan = ctl->nnan != 0;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
 
     // digit bases: exclusive scan of the row totals, plus this block's column
@@ -374,8 +388,12 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const K* __restrict__ kin,
             const K k = skey[p];
             const uint32_t d = digit(k, kmin, shift);
             const uint32_t g = run[d] + (p - toff[d]);
-            kout[g] = k;
-            iout[g] = sidx[p];
+            if (last) {
+                out[sidx[p]] = nan ? __uint_as_float(0x7FC00000u) : rank_float(g);
+            } else {
+                kout[g] = k;
+                iout[g] = sidx[p];
+            }
         }
         __syncthreads();
         run[tid] += tcnt[tid];
@@ -384,28 +402,14 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const K* __restrict__ kin,
     }
 }
 
-// The p-th float of a strictly increasing sequence of normal floats, p < 2^31:
-// negative normals for p < 2^30, positive ones above.
-__device__ __forceinline__ float rank_float(uint32_t p)
+// Keys that are all equal (no pass runs): index order is the sorted order.
+// A NaN anywhere makes every entry NaN.
+__global__ __launch_bounds__(kThreads) void k_fill(uint32_t n, const Ctl* __restrict__ ctl, float* __restrict__ out)
 {
-    const int64_t t = int64_t(p) - (int64_t(1) << 30);
-    const uint32_t bits = t >= 0 ? 0x00800000u + (uint32_t)t : 0x80800000u + (uint32_t)(-t - 1);
-    return __uint_as_float(bits);
-}
-
-// out[vertex at sorted position p] = rank_float(p).  The sorted indices are in
-// buffer (passes & 1); with no pass run the identity order is the sorted one.
-__global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ idxA,
-                                                   const uint32_t* __restrict__ idxB, uint32_t n,
-                                                   const Ctl* __restrict__ ctl, float* __restrict__ out)
-{
-    const uint32_t passes = (ctl->nbits + 7u) / 8u;
+    if (ctl->nbits != 0) return;
     const bool nan = ctl->nnan != 0;
-    const uint32_t* idx = (passes & 1u) ? idxB : idxA;
-    for (uint32_t p = blockIdx.x * kThreads + threadIdx.x; p < n; p += gridDim.x * kThreads) {
-        const uint32_t v = passes == 0 ? p : idx[p];
-        out[v] = nan ? __uint_as_float(0x7FC00000u) : rank_float(p);
-    }
+    for (uint32_t p = blockIdx.x * kThreads + threadIdx.x; p < n; p += gridDim.x * kThreads)
+        out[p] = nan ? __uint_as_float(0x7FC00000u) : rank_float(p);
 }
 
 template <typename T>
@@ -505,10 +509,11 @@ hipError_t rank_field(const T* f, uint32_t n, float* out, char* ws, const Layout
         uint32_t* io = (p & 1) ? iA : iB;
         hipLaunchKernelGGL(k_hist<K>, G, B, 0, s, ki, n, L.per, shift, ctl, hist);
         hipLaunchKernelGGL(k_scan_row, dim3(kDigits), dim3(1024), 0, s, hist, L.G, shift, ctl, rows);
-        hipLaunchKernelGGL(k_scatter<K>, G, B, 0, s, ki, ii, ko, io, n, L.per, shift, ctl, hist, rows, p == 0);
+        hipLaunchKernelGGL(k_scatter<K>, G, B, 0, s, ki, ii, ko, io, n, L.per, shift, ctl, hist, rows, p == 0,
+                           out);
     }
     const uint32_t eb = (uint32_t)std::min<uint64_t>((n + kThreads - 1) / kThreads, 4096);
-    hipLaunchKernelGGL(k_emit, dim3(eb), B, 0, s, iA, iB, n, ctl, out);
+    hipLaunchKernelGGL(k_fill, dim3(eb), B, 0, s, n, ctl, out);
     return hipGetLastError();
 }
 
