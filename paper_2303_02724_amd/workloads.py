@@ -115,6 +115,28 @@ def field_3d_grf(side: int = 512, seed: int = 1) -> np.ndarray:
     return gaussian_random_field((side, side, side), seed, corr_len=8.0)
 
 
+def schwefel(shape) -> np.ndarray:
+    """The Schwefel function 418.9829 n - sum_i x_i sin(sqrt|x_i|) sampled on
+    x_i = -500 + 1000 j_i / (d_i - 1), in float64, rounded to float32 once.
+    The paper's higher-dimensional timings (Table 4) use samples of it; the
+    published formula is evaluated here.  On a cube grid it is symmetric under
+    axis permutations, so equal values (resolved by the index tie-break) are
+    common."""
+    shape = tuple(int(s) for s in shape)
+    n = len(shape)
+    out = np.full(shape, 418.9829 * n, dtype=np.float64)
+    for i, d in enumerate(shape):
+        x = -500.0 + 1000.0 * _axis_coords(d) if d > 1 else np.zeros(1)
+        term = x * np.sin(np.sqrt(np.abs(x)))
+        out -= term.reshape((1,) * i + (d,) + (1,) * (n - i - 1))
+    return out.astype(np.float32)
+
+
+def field_6d(side: int = 16) -> np.ndarray:
+    """6D side^6 Schwefel samples (Table 4's 6D grids are 16^6, 24^6, 32^6)."""
+    return schwefel((side,) * 6)
+
+
 def field_5d_32(seed: int = 2, side: int = 32) -> np.ndarray:
     """5D side^5: 16 Gaussians + U[0,1e-4) noise (maxima graph)."""
     return gaussian_mixture((side,) * 5, seed, n_gauss=16, noise=1e-4)

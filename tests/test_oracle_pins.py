@@ -52,7 +52,7 @@ def test_golden_worked_examples(name):
 
 def test_neighbour_counts_and_link_fvectors():
     g = _load("link_counts.json")
-    for n in range(1, 6):
+    for n in range(1, 7):
         shape = (3,) * n
         centre = (3 ** n - 1) // 2
         nb = O.neighbours(shape, centre)
@@ -77,6 +77,31 @@ def test_neighbour_counts_and_link_fvectors():
         assert euler == (0 if n % 2 == 0 else 2)
 
 
+def test_link_fvectors_follow_the_ordered_partition_rule():
+    """The golden f-vectors equal (k+1)! S(n+1, k+1): the link faces of a vertex
+    of the Freudenthal tessellation are the ordered partitions of {0..n}."""
+    from math import factorial
+
+    def stirling2(n, k):
+        if n == k:
+            return 1
+        if k == 0 or k > n:
+            return 0
+        return k * stirling2(n - 1, k) + stirling2(n - 1, k - 1)
+
+    g = _load("link_counts.json")
+    for n in range(2, 7):
+        assert g["fvector"][str(n)] == [factorial(j) * stirling2(n + 1, j) for j in range(2, n + 2)]
+
+
+@pytest.mark.parametrize("shape", [(7,) * 6, (9, 8, 7, 6, 5, 4)])
+def test_schwefel_6d_invariants(shape):
+    """Schwefel samples (symmetric, so rich in exact ties) on 6D grids."""
+    f = W.schwefel(shape)
+    for minima in (False, True):
+        check_invariants(f, O.extremum_graph(f, minima), minima)
+
+
 def test_beta_histogram_3d():
     g = _load("link_counts.json")["beta_histogram_3d"]
     nb = O.neighbours((3, 3, 3), 13)
@@ -95,7 +120,8 @@ def test_beta_histogram_3d():
 # ------------------------------------------------------------------ brute force
 
 BRUTE_SHAPES = [(9,), (1,), (2,), (6, 7), (1, 5), (2, 2), (5, 4, 3), (2, 3, 4), (1, 3, 1),
-                (3, 3, 2, 3), (2, 2, 2, 2), (3, 2, 3, 2, 2), (3, 3, 3, 3, 3), (2, 2, 2, 2, 2)]
+                (3, 3, 2, 3), (2, 2, 2, 2), (3, 2, 3, 2, 2), (3, 3, 3, 3, 3), (2, 2, 2, 2, 2),
+                (2, 2, 2, 2, 2, 2), (3, 2, 2, 3, 2, 2), (1, 2, 3, 1, 2, 2)]
 
 
 @pytest.mark.parametrize("shape", BRUTE_SHAPES, ids=lambda s: "x".join(map(str, s)))
@@ -286,7 +312,7 @@ def test_banchoff_2d_from_beta():
         assert total == 1
 
 
-@pytest.mark.parametrize("shape", [(7, 6, 5), (4, 3, 4, 3), (3, 3, 2, 3, 2)])
+@pytest.mark.parametrize("shape", [(7, 6, 5), (4, 3, 4, 3), (3, 3, 2, 3, 2), (2, 3, 2, 2, 3, 2)])
 def test_banchoff_nd(shape):
     """Sum over vertices of 1 - chi(upper link) = chi(box) = 1, with the upper
     link's faces counted as cliques of pairwise-adjacent upper neighbours (the
@@ -412,7 +438,7 @@ def check_invariants(f, g, minima=False):
         assert np.all(np.diff(r) > 0)
 
 
-@pytest.mark.parametrize("shape", [(64, 48), (20, 18, 16), (9, 8, 7, 6), (6, 5, 6, 5, 4)])
+@pytest.mark.parametrize("shape", [(64, 48), (20, 18, 16), (9, 8, 7, 6), (6, 5, 6, 5, 4), (5, 4, 5, 4, 4, 5)])
 def test_invariants_on_gaussian_mixtures(shape):
     f = W.gaussian_mixture(shape, 5, n_gauss=6, noise=1e-3)
     for minima in (False, True):
