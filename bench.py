@@ -6,7 +6,7 @@ pointer-jumping labels, saddle reps, arc sort / de-duplication, CSR) over one
 field that is already resident in HBM.  Default workload: the 512^3 float32
 Gaussian random field (seed 1, correlation length 8 voxels), maxima graph.
 
-    python bench.py [--steps K] [--warmup W] [--workload grf512|2d256|5d32]
+    python bench.py [--steps K] [--warmup W] [--workload grf512|2d256|5d32|6d16]
 
 Prints one JSON line.  Besides the contract fields it carries
   roofline      the dominant kernel against the HBM peak (algorithmic bytes /
@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="grf512", choices=["grf512", "2d256", "5d32", "batched", "serving"])
+    ap.add_argument("--workload", default="grf512", choices=["grf512", "2d256", "5d32", "6d16", "batched", "serving"])
     ap.add_argument("--requests", type=int, default=2000, help="serving workload: number of requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serving workload: Poisson arrival rate (1/s)")
     ap.add_argument("--sat-rate", type=float, default=50000.0,
@@ -204,6 +204,11 @@ def make_field(args):
         side = args.side or 256
         f = W.gaussian_mixture((side, side), 0, n_gauss=8, noise=1e-3)
         cfg = {"workload": f"gauss2d_{side}", "shape": [side] * 2, "seed": 0, "gaussians": 8, "noise": 1e-3}
+    elif args.workload == "6d16":
+        side = args.side or 16
+        f = W.field_6d(side)
+        cfg = {"workload": f"schwefel6d_{side}", "shape": [side] * 6,
+               "field": "Schwefel function on [-500, 500]^6 (Table 4's 6D grids)"}
     else:
         side = args.side or 32
         f = W.field_5d_32(seed=2, side=side)
@@ -581,7 +586,8 @@ def main():
     if not args.no_cpu_baseline:
         planes = args.cpu_planes
         if planes is None:
-            planes = {"grf512": max(1, f.shape[0] // 4), "2d256": f.shape[0], "5d32": max(1, f.shape[0] // 4)}[
+            planes = {"grf512": max(1, f.shape[0] // 4), "2d256": f.shape[0], "5d32": max(1, f.shape[0] // 4),
+                      "6d16": max(1, f.shape[0] // 4)}[
                 args.workload]
         out["cpu_baseline"] = cpu_baseline(f, planes)
     print(json.dumps(out), flush=True)

@@ -2,7 +2,7 @@
  * eg.h -- C ABI of the MI355X extremum-graph library (libeg_hip.so).
  *
  * Computes the extremum graph of a piecewise-linear scalar field sampled on an
- * n-dimensional grid (n = 1..5; float32 samples, other sample types through
+ * n-dimensional grid (n = 1..6; float32 samples, other sample types through
  * eg_order_field), following Ande, Subhash and Natarajan,
  * "TACHYON: Efficient Shared Memory Parallel Computation of Extremum Graphs":
  *
@@ -63,7 +63,7 @@ typedef enum eg_status {
 /* eg_out.flags */
 #define EG_MINIMA 0x1u /* build the minimum graph instead of the maximum graph */
 
-#define EG_MAX_NDIM 5
+#define EG_MAX_NDIM 6
 
 /* Slots of the device header (int32 each, EG_H_SLOTS in total). */
 #define EG_H_STATUS 0 /* eg_status of the device-side work */
@@ -125,7 +125,7 @@ typedef struct eg_out {
  * Workspace bytes that eg_build needs for a field of the given shape and the
  * given saddle capacity (eg_out.cap_sad; the other capacities do not enter):
  * about 4.25 bytes per vertex (more when the last axis is much shorter than
- * 64; 4 more for 1D, 4D and 5D grids) plus 16 bytes per saddle slot.  Pure,
+ * 64; 4 more for 1D, 4D, 5D and 6D grids) plus 16 bytes per saddle slot.  Pure,
  * host-only.  Returns 0 on invalid arguments (ndim outside [1, EG_MAX_NDIM],
  * a dim < 1, N >= 2^31, a capacity outside [0, 2^31)).
  */
@@ -370,9 +370,11 @@ const char* eg_status_string(int status);
  * Host-only: the neighbour table the kernels use for an n-dimensional grid
  * (Alg. 1).  Writes k = 2(2^n - 1) rows sorted so that, for any in-bounds
  * neighbours, row order equals linear-index order: offsets[j * ndim + i] in
- * {-1,0,1} is the coordinate difference on axis i, adjacency[j] bit l is set
- * iff neighbours j and l are adjacent to each other (a link edge).  Returns k,
- * or -1 for ndim outside [1, EG_MAX_NDIM].  Buffers may be NULL to query k.
+ * {-1,0,1} is the coordinate difference on axis i; the adjacency of row j is
+ * W = (k + 63) / 64 words (1 up to n = 5, 2 for n = 6), adjacency[j * W + l / 64]
+ * bit l % 64 set iff neighbours j and l are adjacent to each other (a link
+ * edge).  Returns k, or -1 for ndim outside [1, EG_MAX_NDIM].  Buffers may be
+ * NULL to query k.
  */
 int eg_link_table(int ndim, int8_t* offsets, uint64_t* adjacency);
 

@@ -1,7 +1,7 @@
 """MI355X-native extremum graphs of piecewise-linear scalar fields on grids.
 
 The HIP library (``csrc/``, built into ``libeg_hip.so``) computes, for a
-float32 field on an n-D grid (n = 1..5) with the Freudenthal tessellation:
+float32 field on an n-D grid (n = 1..6) with the Freudenthal tessellation:
 steepest-ascent pointers, per-vertex labels (the maximum of each vertex's
 descending manifold), maxima, (n-1)-saddles with their upper-link component
 counts, and the de-duplicated saddle-maximum arcs in CSR form.

@@ -313,13 +313,15 @@ const char* eg_status_string(int status)
 int eg_link_table(int ndim, int8_t* offsets, uint64_t* adjacency)
 {
     int8_t off[kMaxNb][EG_MAX_NDIM];
-    uint64_t adj[kMaxNb];
+    uint64_t adj[kMaxNb * 2];
     const int k = make_rows(ndim, off, adj);
     if (k < 0) return -1;
+    const int W = (k + 63) / 64;
     for (int j = 0; j < k; ++j) {
         if (offsets)
             for (int i = 0; i < ndim; ++i) offsets[j * ndim + i] = off[j][i];
-        if (adjacency) adjacency[j] = adj[j];
+        if (adjacency)
+            for (int w = 0; w < W; ++w) adjacency[j * W + w] = adj[j * W + w];
     }
     return k;
 }

@@ -26,34 +26,6 @@
 
 namespace eg {
 
-template <int NDIM>
-struct AdjTable {
-    uint64_t adj[Rows<NDIM>::K];
-};
-template <int NDIM>
-constexpr AdjTable<NDIM> make_adj()
-{
-    constexpr Rows<NDIM> r = make_rows_ce<NDIM>();
-    AdjTable<NDIM> t{};
-    for (int j = 0; j < Rows<NDIM>::K; ++j) t.adj[j] = r.adj[j];
-    return t;
-}
-__constant__ AdjTable<1> c_adj1 = make_adj<1>();
-__constant__ AdjTable<2> c_adj2 = make_adj<2>();
-__constant__ AdjTable<3> c_adj3 = make_adj<3>();
-__constant__ AdjTable<4> c_adj4 = make_adj<4>();
-__constant__ AdjTable<5> c_adj5 = make_adj<5>();
-
-template <int NDIM>
-__device__ __forceinline__ const uint64_t* adj_table()
-{
-    if constexpr (NDIM == 1) return c_adj1.adj;
-    else if constexpr (NDIM == 2) return c_adj2.adj;
-    else if constexpr (NDIM == 3) return c_adj3.adj;
-    else if constexpr (NDIM == 4) return c_adj4.adj;
-    else return c_adj5.adj;
-}
-
 // ------------------------------------------------------------------ selectors
 
 struct OneField {
@@ -287,7 +259,7 @@ struct Nbhd {
     static constexpr int K = Rows<NDIM>::K;
     uint32_t us[K];
     int offs[K];
-    uint64_t up;
+    Mask<NDIM> up;
 };
 
 template <int NDIM, bool MINMODE>
@@ -328,7 +300,7 @@ __device__ __forceinline__ void load_nbhd(const ArcArgs& A, int v, Nbhd<NDIM, MI
         const uint32_t u = !in ? 0u : stored ? A.keys[v + off] : mode_key<MINMODE>(A.f[v + off]);
         nb.us[j] = u;
         const bool wins_tie = (j >= K / 2) != MINMODE;
-        nb.up |= uint64_t(wins_tie ? (u >= uv) : (u > uv)) << j;
+        nb.up |= Mask<NDIM>(wins_tie ? (u >= uv) : (u > uv)) << j;
     }
 }
 
@@ -339,18 +311,18 @@ __device__ __forceinline__ void load_nbhd(const ArcArgs& A, int v, Nbhd<NDIM, MI
 // row; rows are in linear-index order, so components come in ascending order
 // of their smallest vertex.
 template <int NDIM, bool MINMODE, class F>
-__device__ __forceinline__ void for_each_rep(int v, const Nbhd<NDIM, MINMODE>& nb, const uint64_t* s_adj, F&& f)
+__device__ __forceinline__ void for_each_rep(int v, const Nbhd<NDIM, MINMODE>& nb, const Mask<NDIM>* s_adj, F&& f)
 {
     constexpr int K = Rows<NDIM>::K;
-    for (uint64_t rem = nb.up; rem;) {
-        const uint64_t comp = closure(rem & (~rem + 1), rem, s_adj);
+    for (Mask<NDIM> rem = nb.up; rem != 0;) {
+        const Mask<NDIM> comp = closure(rem & (~rem + 1), rem, s_adj);
         rem &= ~comp;
         uint32_t best_u = 0;
         int best_off = 0;
 #pragma unroll
         for (int s = 0; s < K; ++s) {
             const int j = MINMODE ? K - 1 - s : s;
-            if (((comp >> j) & 1ull) && nb.us[j] >= best_u) {
+            if ((uint32_t)(comp >> j) & 1u && nb.us[j] >= best_u) {
                 best_u = nb.us[j];
                 best_off = nb.offs[j];
             }
@@ -362,7 +334,7 @@ __device__ __forceinline__ void for_each_rep(int v, const Nbhd<NDIM, MINMODE>& n
 // f(label) for every component: the label its rep reaches.
 template <int NDIM, bool MINMODE, class F>
 __device__ __forceinline__ void for_each_arc_label(const ArcArgs& A, int v, const Nbhd<NDIM, MINMODE>& nb,
-                                                   const uint64_t* s_adj, F&& f)
+                                                   const Mask<NDIM>* s_adj, F&& f)
 {
     for_each_rep<NDIM, MINMODE>(v, nb, s_adj, [&](int rep) { f((uint32_t)A.lab[rep]); });
 }
@@ -380,7 +352,7 @@ struct ArcList {
 
 template <int NDIM, bool MINMODE>
 __device__ __forceinline__ ArcList<NDIM> first_arcs(const ArcArgs& A, int v, const Nbhd<NDIM, MINMODE>& nb,
-                                                    const uint64_t* s_adj, int& beta)
+                                                    const Mask<NDIM>* s_adj, int& beta)
 {
     constexpr int S = ArcList<NDIM>::S;
     ArcList<NDIM> r;
@@ -417,7 +389,7 @@ __device__ __forceinline__ ArcList<NDIM> first_arcs(const ArcArgs& A, int v, con
 // emit(k, label) for the k-th of them and returns their number.
 template <int NDIM, bool MINMODE, class E>
 __device__ __forceinline__ uint32_t labels_above(const ArcArgs& A, int v, const Nbhd<NDIM, MINMODE>& nb,
-                                                 const uint64_t* s_adj, uint32_t last, E&& emit)
+                                                 const Mask<NDIM>* s_adj, uint32_t last, E&& emit)
 {
     uint32_t k = 0;
     for (;;) {
@@ -433,10 +405,10 @@ __device__ __forceinline__ uint32_t labels_above(const ArcArgs& A, int v, const 
 }
 
 template <int NDIM>
-__device__ __forceinline__ void load_adj(uint64_t* s_adj)
+__device__ __forceinline__ void load_adj(Mask<NDIM>* s_adj)
 {
     constexpr int K = Rows<NDIM>::K;
-    const uint64_t* t = adj_table<NDIM>();
+    const Mask<NDIM>* t = adj_table<NDIM>();
     for (int i = threadIdx.x; i < K; i += blockDim.x) s_adj[i] = t[i];
     __syncthreads();
 }
@@ -444,7 +416,7 @@ __device__ __forceinline__ void load_adj(uint64_t* s_adj)
 // Distinct-arc count, beta and the first four arcs of every saddle of the
 // block's chunk; the block's sums of both counts go to rows 2 and 3.
 template <int NDIM, bool MINMODE>
-__device__ __forceinline__ void arc_count_body(const ArcArgs& A, uint32_t blk, uint32_t nb, uint64_t* s_adj,
+__device__ __forceinline__ void arc_count_body(const ArcArgs& A, uint32_t blk, uint32_t nb, Mask<NDIM>* s_adj,
                                                uint32_t* tmp)
 {
     load_adj<NDIM>(s_adj);
@@ -480,7 +452,7 @@ __device__ __forceinline__ void arc_count_body(const ArcArgs& A, uint32_t blk, u
 }
 
 template <int NDIM, bool MINMODE>
-__device__ __forceinline__ void arc_write_body(const ArcArgs& A, uint32_t blk, uint32_t nb, uint64_t* s_adj,
+__device__ __forceinline__ void arc_write_body(const ArcArgs& A, uint32_t blk, uint32_t nb, Mask<NDIM>* s_adj,
                                                uint32_t* tmp)
 {
     load_adj<NDIM>(s_adj);
@@ -531,7 +503,7 @@ __device__ __forceinline__ void arc_write_body(const ArcArgs& A, uint32_t blk, u
 template <int NDIM, bool MINMODE>
 __global__ __launch_bounds__(256) void k_arc_count(OneField sel)
 {
-    __shared__ uint64_t s_adj[Rows<NDIM>::K];
+    __shared__ Mask<NDIM> s_adj[Rows<NDIM>::K];
     __shared__ uint32_t tmp[4];
     uint32_t blk, nb;
     const ArcArgs A = sel.locate(blk, nb);  // a copy: loop loads cannot alias it
@@ -541,7 +513,7 @@ __global__ __launch_bounds__(256) void k_arc_count(OneField sel)
 template <int NDIM, bool MINMODE>
 __global__ __launch_bounds__(256) void k_arc_write(OneField sel)
 {
-    __shared__ uint64_t s_adj[Rows<NDIM>::K];
+    __shared__ Mask<NDIM> s_adj[Rows<NDIM>::K];
     __shared__ uint32_t tmp[4];
     uint32_t blk, nb;
     const ArcArgs A = sel.locate(blk, nb);  // a copy: loop loads cannot alias it
@@ -612,7 +584,7 @@ __global__ void k_path_reset(OneField sel)
 template <int NDIM, bool MINMODE>
 __global__ __launch_bounds__(256) void k_path_count(OneField sel, PathArgs P)
 {
-    __shared__ uint64_t s_adj[Rows<NDIM>::K];
+    __shared__ Mask<NDIM> s_adj[Rows<NDIM>::K];
     __shared__ uint32_t tmp[4];
     uint32_t blk, nb;
     const ArcArgs A = sel.locate(blk, nb);  // a copy: loop loads cannot alias it
@@ -651,7 +623,7 @@ __global__ __launch_bounds__(256) void k_path_count(OneField sel, PathArgs P)
 template <int NDIM, bool MINMODE>
 __global__ __launch_bounds__(256) void k_path_write(OneField sel, PathArgs P)
 {
-    __shared__ uint64_t s_adj[Rows<NDIM>::K];
+    __shared__ Mask<NDIM> s_adj[Rows<NDIM>::K];
     __shared__ uint32_t tmp[4];
     uint32_t blk, nb;
     const ArcArgs A = sel.locate(blk, nb);  // a copy: loop loads cannot alias it
@@ -734,6 +706,7 @@ hipError_t launch_paths(const ArcArgs& a, const PathArgs& p, hipStream_t s)
         EG_CASE(3)
         EG_CASE(4)
         EG_CASE(5)
+        EG_CASE(6)
         default:
             return hipErrorInvalidValue;
     }
@@ -837,6 +810,7 @@ hipError_t launch_arcs(const ArcArgs& a, hipStream_t s)
         EG_CASE(3)
         EG_CASE(4)
         EG_CASE(5)
+        EG_CASE(6)
         default:
             return hipErrorInvalidValue;
     }

@@ -1,6 +1,6 @@
 // eg_classify.hip -- per-vertex classification, labels and saddle reps.
 //
-// k_classify_generic  stages (a) and (c) of the method for any n = 1..5: one
+// k_classify_generic  stages (a) and (c) of the method for n = 1, 4, 5, 6: one
 //   thread per vertex reads its closed neighbourhood, forms the upper-link
 //   mask (Sec. 3.3), the steepest-ascent pointer (highest upper-link vertex,
 //   Sec. 3.3) and decides maximum (empty upper link) / saddle (>= 2
@@ -8,6 +8,7 @@
 // k_exit_*, k_final  stage (b): pointer jumping until every vertex names its
 //   maximum (the end of the walk of Alg. 2).
 #include "eg_internal.h"
+#include "eg_rows.h"
 
 namespace eg {
 
@@ -25,20 +26,31 @@ hipError_t launch_init(uint32_t* ctr, int32_t* header, hipStream_t s)
 }
 
 // Visit the closed neighbourhood of v in the order in which later vertices
-// win ties; fills the upper-link mask and the steepest-ascent target.
+// win ties; fills the upper-link mask and the steepest-ascent target.  Up to
+// 5D the rows are unrolled, one load per row under the row's own branch; a
+// row's linear offset and the boundary bits that rule it out follow from the
+// compile-time rows and the grid strides st[] (uniform, scalar work).
 template <int NDIM, bool MINMODE>
-__device__ __forceinline__ void scan_neighbourhood(const uint32_t* __restrict__ keys, const LinkTable& t, int v,
-                                                   uint32_t bits, uint32_t uv, uint64_t& up, int& best)
+__device__ __forceinline__ void scan_unrolled(const uint32_t* __restrict__ keys, const int* st, int v,
+                                              uint32_t bits, uint32_t uv, Mask<NDIM>& up, int& best)
 {
-    constexpr int K = 2 * ((1 << NDIM) - 1);
+    constexpr Rows<NDIM> R = make_rows_ce<NDIM>();
+    constexpr int K = Rows<NDIM>::K;
     uint32_t best_u = 0;
     best = v;
     auto visit = [&](int j) {
-        if ((bits & t.forb[j]) == 0) {
-            const int u_id = v + t.lin[j];
+        int lin = 0;
+        uint32_t forb = 0;
+#pragma unroll
+        for (int i = 0; i < NDIM; ++i) {
+            lin += R.d[j][i] * st[i];
+            forb |= R.d[j][i] < 0 ? 1u << (2 * i) : R.d[j][i] > 0 ? 1u << (2 * i + 1) : 0u;
+        }
+        if ((bits & forb) == 0) {
+            const int u_id = v + lin;
             const uint32_t u = keys[u_id];
             const bool above = row_wins_tie<MINMODE>(j, K) ? (u >= uv) : (u > uv);
-            up |= uint64_t(above) << j;
+            up |= Mask<NDIM>(above) << j;
             if (u >= best_u) {
                 best_u = u;
                 best = u_id;
@@ -63,6 +75,54 @@ __device__ __forceinline__ void scan_neighbourhood(const uint32_t* __restrict__ 
         self();
 #pragma unroll
         for (int j = K / 2 - 1; j >= 0; --j) visit(j);
+    }
+}
+
+// The same for 6D (126 rows): unrolled, the rows' offsets and boundary bits
+// would not fit the scalar registers, and the loads would run one after
+// another.  Here rows go eight at a time: their keys are loaded without branches (a row outside
+// the grid reads v's own key and then counts as key 0, below every vertex),
+// so the eight loads are in flight together, while the chunk loop itself
+// stays rolled to keep registers, and with them waves, free.  Row offsets and
+// boundary bits come from LDS (s_lin, s_forb).
+template <int NDIM, bool MINMODE>
+__device__ __forceinline__ void scan_chunked(const uint32_t* __restrict__ keys, const int32_t* s_lin,
+                                             const uint32_t* s_forb, int v, uint32_t bits, uint32_t uv,
+                                             Mask<NDIM>& up, int& best)
+{
+    constexpr int K = 2 * ((1 << NDIM) - 1);
+    constexpr int CH = K < 8 ? K : 8;
+    uint32_t best_u = 0;
+    best = v;
+#pragma unroll 1
+    for (int c0 = 0; c0 < K; c0 += CH) {
+        uint32_t us[CH];
+        int lin[CH];
+#pragma unroll
+        for (int s = 0; s < CH; ++s) {
+            const int idx = c0 + s;
+            const int j = idx < K ? (MINMODE ? K - 1 - idx : idx) : 0;
+            const bool in = idx < K && (bits & s_forb[j]) == 0;
+            lin[s] = s_lin[j];
+            const uint32_t u = keys[in ? v + lin[s] : v];
+            us[s] = in ? u : 0u;
+        }
+#pragma unroll
+        for (int s = 0; s < CH; ++s) {
+            const int idx = c0 + s;
+            if (idx == K / 2 && uv >= best_u) {  // v itself sits between the two halves
+                best_u = uv;
+                best = v;
+            }
+            const int j = MINMODE ? K - 1 - idx : idx;
+            const uint32_t u = us[s];
+            const bool above = row_wins_tie<MINMODE>(j, K) ? (u >= uv) : (u > uv);
+            if (above) up |= Mask<NDIM>(1) << j;
+            if (u != 0 && u >= best_u) {
+                best_u = u;
+                best = v + lin[s];
+            }
+        }
     }
 }
 
@@ -130,8 +190,18 @@ __global__ __launch_bounds__(256) void k_classify_generic(const uint32_t* __rest
                                                           uint64_t* __restrict__ mmask, uint64_t* __restrict__ smask)
 {
     constexpr int K = 2 * ((1 << NDIM) - 1);
-    __shared__ uint64_t s_adj[K];
-    for (int i = threadIdx.x; i < K; i += blockDim.x) s_adj[i] = t.adj[i];
+    constexpr bool chunked = NDIM >= 6;
+    __shared__ Mask<NDIM> s_adj[K];
+    __shared__ int32_t s_lin[chunked ? K : 1];
+    __shared__ uint32_t s_forb[chunked ? K : 1];
+    const Mask<NDIM>* adj = adj_table<NDIM>();
+    for (int i = threadIdx.x; i < K; i += blockDim.x) {
+        s_adj[i] = adj[i];
+        if constexpr (chunked) {  // a runtime index into the table, only where it is used
+            s_lin[i] = t.lin[i];
+            s_forb[i] = t.forb[i];
+        }
+    }
     __syncthreads();
 
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -139,9 +209,17 @@ __global__ __launch_bounds__(256) void k_classify_generic(const uint32_t* __rest
     if (v < g.N) {
         const uint32_t bits = boundary_bits<NDIM>(g, v);
         const uint32_t uv = keys[v];
-        uint64_t up = 0;
+        Mask<NDIM> up = 0;
         int best;
-        scan_neighbourhood<NDIM, MINMODE>(keys, t, v, bits, uv, up, best);
+        if constexpr (chunked) {
+            scan_chunked<NDIM, MINMODE>(keys, s_lin, s_forb, v, bits, uv, up, best);
+        } else {
+            int st[NDIM];
+            st[NDIM - 1] = 1;
+#pragma unroll
+            for (int i = NDIM - 2; i >= 0; --i) st[i] = st[i + 1] * g.dims[i + 1];
+            scan_unrolled<NDIM, MINMODE>(keys, st, v, bits, uv, up, best);
+        }
         is_max = up == 0;
         if (!is_max) is_sad = closure(up & (~up + 1), up, s_adj) != up;
         lab[v] = is_max ? v : -(best + 1);  // final label, or "same as best"
@@ -187,6 +265,7 @@ hipError_t launch_classify(const float* f, const Grid& g, const LinkTable& t, bo
         EG_CASE(3)
         EG_CASE(4)
         EG_CASE(5)
+        EG_CASE(6)
         default:
             return hipErrorInvalidValue;
     }

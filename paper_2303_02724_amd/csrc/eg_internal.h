@@ -22,7 +22,7 @@
 
 namespace eg {
 
-constexpr int kMaxNb = 62;          // 2(2^5 - 1)
+constexpr int kMaxNb = 126;         // 2(2^6 - 1)
 constexpr int kJumpHops = 64;       // default links per pointer-jumping pass
 constexpr int kMaxPasses = 8;       // flag slots per pass sequence
 constexpr int kArcBlocks = 8192;    // most blocks per field of the stage (d) kernels
@@ -68,12 +68,12 @@ enum : int {
     C_SLOTS = 64,
 };
 
-// Neighbour table for one grid, passed by value as a kernel argument.
+// Neighbour table for one grid, passed by value as a kernel argument (the
+// rows' mutual adjacency is a compile-time table, eg_rows.h).
 struct LinkTable {
     int32_t k;                 // number of rows, 2(2^n - 1)
     int32_t lin[kMaxNb];       // linear index offset of row j
     uint32_t forb[kMaxNb];     // boundary bits that rule row j out (see boundary_bits)
-    uint64_t adj[kMaxNb];      // bit l set iff rows j and l are adjacent (link edge)
 };
 
 struct Grid {
@@ -191,7 +191,8 @@ struct BatchPlan {
     int64_t plan_bytes;
 };
 
-// Host: table rows for ndim (Alg. 1), independent of dims.  Returns k.
+// Host: table rows for ndim (Alg. 1), independent of dims.  Returns k.  The
+// adjacency of row j is adj[j * W .. j * W + W), W = (k + 63) / 64 words.
 int make_rows(int ndim, int8_t (*off)[EG_MAX_NDIM], uint64_t* adj);
 // Host: full kernel table for a grid.
 void make_table(const Grid& g, LinkTable* t);
@@ -245,20 +246,6 @@ template <bool MINMODE>
 __device__ __forceinline__ bool row_wins_tie(int j, int k)
 {
     return (j >= k / 2) != MINMODE;
-}
-
-// Component of `seed` inside `mask` (BFS over link edges, bit-parallel).
-__device__ __forceinline__ uint64_t closure(uint64_t seed, uint64_t mask, const uint64_t* adj)
-{
-    uint64_t comp = seed, frontier = seed;
-    while (frontier) {
-        int j = __ffsll((unsigned long long)frontier) - 1;
-        frontier &= frontier - 1;
-        uint64_t nb = adj[j] & mask & ~comp;
-        comp |= nb;
-        frontier |= nb;
-    }
-    return comp;
 }
 
 // ------------------------------------------------------------------ launchers

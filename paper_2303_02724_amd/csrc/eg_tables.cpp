@@ -15,12 +15,14 @@ template <int NDIM>
 static int copy_rows(int8_t (*off)[EG_MAX_NDIM], uint64_t* adj)
 {
     constexpr Rows<NDIM> r = make_rows_ce<NDIM>();
-    for (int j = 0; j < Rows<NDIM>::K; ++j) {
+    constexpr int K = Rows<NDIM>::K, W = (K + 63) / 64;
+    for (int j = 0; j < K; ++j) {
         if (off)
             for (int i = 0; i < EG_MAX_NDIM; ++i) off[j][i] = (int8_t)(i < NDIM ? r.d[j][i] : 0);
-        if (adj) adj[j] = r.adj[j];
+        if (adj)
+            for (int w = 0; w < W; ++w) adj[j * W + w] = (uint64_t)(r.adj[j] >> (64 * w));
     }
-    return Rows<NDIM>::K;
+    return K;
 }
 
 int make_rows(int ndim, int8_t (*off)[EG_MAX_NDIM], uint64_t* adj)
@@ -31,6 +33,7 @@ int make_rows(int ndim, int8_t (*off)[EG_MAX_NDIM], uint64_t* adj)
         case 3: return copy_rows<3>(off, adj);
         case 4: return copy_rows<4>(off, adj);
         case 5: return copy_rows<5>(off, adj);
+        case 6: return copy_rows<6>(off, adj);
         default: return -1;
     }
 }
@@ -38,9 +41,8 @@ int make_rows(int ndim, int8_t (*off)[EG_MAX_NDIM], uint64_t* adj)
 void make_table(const Grid& g, LinkTable* t)
 {
     int8_t off[kMaxNb][EG_MAX_NDIM];
-    uint64_t adj[kMaxNb];
     std::memset(t, 0, sizeof(*t));
-    const int k = make_rows(g.ndim, off, adj);
+    const int k = make_rows(g.ndim, off, nullptr);
     int64_t stride[EG_MAX_NDIM];
     int64_t s = 1;
     for (int i = g.ndim - 1; i >= 0; --i) {
@@ -58,7 +60,6 @@ void make_table(const Grid& g, LinkTable* t)
         }
         t->lin[j] = (int32_t)lin;
         t->forb[j] = forb;
-        t->adj[j] = adj[j];
     }
 }
 

@@ -5,7 +5,7 @@ every step of the computation runs in the library's HIP kernels.  There is
 no CPU path: if the library is missing or no HIP device is present, the
 calls raise.
 
-    res = eg.build(field)                # field: CUDA tensor, n = 1..5 axes
+    res = eg.build(field)                # field: CUDA tensor, n = 1..6 axes
                                          # (float32; other types via eg_order_field)
     res.maxima, res.saddles, res.arc_offsets, res.arc_maxima, res.labels
 
@@ -31,7 +31,7 @@ def tuning(tile3: int = 0, tile2: int = 0, hops: int = 0) -> int:
     """eg_out.tuning value (EG_TUNE_TILE3 | EG_TUNE_TILE2 | EG_TUNE_HOPS)."""
     return (tile3 & 0xF) | ((tile2 & 0xF) << 4) | ((hops & 0xFF) << 8)
 EG_MINIMA = 0x1
-EG_MAX_NDIM = 5
+EG_MAX_NDIM = 6
 H_STATUS, H_NMAX, H_NSAD, H_NARC, H_NPAIRS, H_PASSES, H_EXITS = range(7)
 H_SLOTS = 8
 
@@ -153,15 +153,20 @@ def workspace_bytes(shape, cap_sad: int) -> int:
 
 
 def link_table(ndim: int):
-    """Host-only neighbour table of the library: (offsets[k, ndim], adjacency[k])."""
+    """Host-only neighbour table of the library: (offsets[k, ndim], adjacency):
+    adjacency[j] is a Python int whose bit l is set iff rows j and l are
+    adjacent."""
     import numpy as np
 
     k = lib().eg_link_table(ndim, None, None)
     if k < 0:
         raise EGError(EG_ERR_ARG, f"ndim={ndim}")
+    words = (k + 63) // 64
     off = np.zeros((k, ndim), dtype=np.int8)
-    adj = np.zeros(k, dtype=np.uint64)
-    lib().eg_link_table(ndim, off.ctypes.data_as(ctypes.c_void_p), adj.ctypes.data_as(ctypes.c_void_p))
+    raw = np.zeros(k * words, dtype=np.uint64)
+    lib().eg_link_table(ndim, off.ctypes.data_as(ctypes.c_void_p), raw.ctypes.data_as(ctypes.c_void_p))
+    # one Python int per row (rows of a 6D grid need two words)
+    adj = [sum(int(raw[j * words + w]) << (64 * w) for w in range(words)) for j in range(k)]
     return off, adj
 
 
@@ -553,7 +558,7 @@ def build_paths(field: torch.Tensor, minima: bool = False, tuning: int = 0, **ca
 
 def build(field: torch.Tensor, minima: bool = False, want_ptr: bool = False, tuning: int = 0,
           **caps) -> EGResult:
-    """Extremum graph of ``field`` (device tensor, 1..5 axes; float32, or any
+    """Extremum graph of ``field`` (device tensor, 1..6 axes; float32, or any
     other type of DTYPES through its order surrogate)."""
     b = Builder(field.shape, minima=minima, want_ptr=want_ptr, device=field.device, tuning=tuning, **caps)
     return b.run(field.contiguous())

@@ -39,7 +39,7 @@ def test_workspace_bytes():
     # bitmask rows are padded to 64 vertices: a short last axis costs more
     assert eg.workspace_bytes((4096, 4), 0) > eg.workspace_bytes((4, 4096), 0)
     L = eg.lib()
-    bad = [((), 1), ((0, 4), 1), ((2,) * 6, 1), ((1 << 16, 1 << 16), 1), ((4, 4), -1), ((4, 4), 1 << 31)]
+    bad = [((), 1), ((0, 4), 1), ((2,) * 7, 1), ((1 << 16, 1 << 16), 1), ((4, 4), -1), ((4, 4), 1 << 31)]
     for shape, c in bad:
         dims = (ctypes.c_int64 * max(1, len(shape)))(*shape)
         assert L.eg_workspace_bytes(len(shape), dims, c) == 0, shape
@@ -53,7 +53,7 @@ def test_build_rejects_bad_arguments_on_host():
     assert L.eg_build(None, 2, dims, None, ctypes.byref(o)) == eg.EG_ERR_ARG
     fake = ctypes.c_void_p(0x1000)
     assert L.eg_build(fake, 0, dims, None, ctypes.byref(o)) == eg.EG_ERR_ARG
-    assert L.eg_build(fake, 6, dims, None, ctypes.byref(o)) == eg.EG_ERR_ARG
+    assert L.eg_build(fake, 7, dims, None, ctypes.byref(o)) == eg.EG_ERR_ARG
     big = (ctypes.c_int64 * 2)(1 << 16, 1 << 16)
     assert L.eg_build(fake, 2, big, None, ctypes.byref(o)) == eg.EG_ERR_TOO_LARGE
     zero = (ctypes.c_int64 * 2)(0, 8)
@@ -91,7 +91,7 @@ def _alg1(d):
     return any(x != 0 for x in d) and (s <= {0, 1} or s <= {0, -1})
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
 def test_link_table_follows_alg1(n):
     off, adj = eg.link_table(n)
     k = 2 * (2 ** n - 1)
@@ -113,7 +113,7 @@ def test_link_table_follows_alg1(n):
 
 def test_link_table_fvectors_and_3d_histogram():
     gold = json.load(open(os.path.join(ROOT, "tests", "golden", "link_counts.json")))
-    for n in range(2, 6):
+    for n in range(2, 7):
         off, adj = eg.link_table(n)
         k = len(off)
         nb = [{l for l in range(k) if (int(adj[j]) >> l) & 1} for j in range(k)]
@@ -160,7 +160,9 @@ def test_batch_plan_validation_on_host():
     assert L.eg_batch_plan_bytes(3) > L.eg_batch_plan_bytes(1) > 0
     n = 2
     ndims = (ctypes.c_int * n)(2, 3)
-    dims = (ctypes.c_int64 * (n * eg.EG_MAX_NDIM))(16, 16, 0, 0, 0, 8, 8, 8, 0, 0)
+    M = eg.EG_MAX_NDIM
+    dims = (ctypes.c_int64 * (n * M))()
+    dims[0], dims[1], dims[M], dims[M + 1], dims[M + 2] = 16, 16, 8, 8, 8
     outs = (eg.eg_out * n)(_fake_out(), _fake_out())
     wsb = L.eg_batch_workspace_bytes(n, ndims, dims, outs)
     assert wsb > 0
@@ -171,7 +173,10 @@ def test_batch_plan_validation_on_host():
     assert ok == eg.EG_OK
     # 4D fields are not batched
     nd4 = (ctypes.c_int * n)(2, 4)
-    dims4 = (ctypes.c_int64 * (n * eg.EG_MAX_NDIM))(16, 16, 0, 0, 0, 4, 4, 4, 4, 0)
+    dims4 = (ctypes.c_int64 * (n * M))()
+    dims4[0], dims4[1] = 16, 16
+    for i in range(4):
+        dims4[M + i] = 4
     assert L.eg_batch_workspace_bytes(n, nd4, dims4, outs) == 0
     assert L.eg_batch_plan(n, fields, nd4, dims4, outs, ctypes.c_void_p(0x200000), wsb, host, pb) == eg.EG_ERR_ARG
     # workspace missing, misaligned, short

@@ -11,7 +11,8 @@ from tests.gpu_util import KEYS, assert_same, gpu_graph
 pytestmark = pytest.mark.gpu
 
 SMALL = [(1,), (2,), (37,), (1, 1), (5, 1), (1, 7), (6, 7), (33, 65), (3, 1, 4), (5, 4, 3), (17, 9, 70),
-         (3, 3, 2, 3), (6, 5, 7, 4), (2, 2, 2, 2, 2), (3, 4, 3, 2, 3), (5, 6, 4, 5, 3)]
+         (3, 3, 2, 3), (6, 5, 7, 4), (2, 2, 2, 2, 2), (3, 4, 3, 2, 3), (5, 6, 4, 5, 3),
+         (2, 2, 2, 2, 2, 2), (1, 3, 2, 1, 2, 3), (4, 3, 5, 3, 4, 3)]
 
 
 @pytest.mark.parametrize("shape", SMALL, ids=lambda s: "x".join(map(str, s)))
@@ -43,6 +44,30 @@ def test_grf_3d(shape, corr):
 def test_gaussian_mixture_5d():
     f = W.gaussian_mixture((12, 11, 10, 9, 8), 2, n_gauss=16, noise=1e-4)
     assert_same(gpu_graph(f), O.extremum_graph(f), KEYS + ["ptr"], "5d")
+
+
+def test_6d_mixture_white_noise_and_schwefel():
+    """6D grids: 126 neighbours, 128-bit upper-link masks."""
+    f = W.gaussian_mixture((10, 9, 8, 8, 7, 6), 3, n_gauss=8, noise=1e-3)
+    for minima in (False, True):
+        assert_same(gpu_graph(f, minima), O.extremum_graph(f, minima), KEYS + ["ptr"], f"6d mix minima={minima}")
+    g = W.random_field((7,) * 6, 5, "uniform")
+    want = O.extremum_graph(g)
+    assert np.diff(want["arc_offsets"]).max() == 8  # a full eight-entry arc list
+    assert_same(gpu_graph(g), want, KEYS + ["ptr"], "6d noise")
+    s = W.schwefel((12,) * 6)  # exact ties from the symmetric formula
+    assert_same(gpu_graph(s), O.extremum_graph(s), KEYS + ["ptr"], "6d schwefel")
+
+
+def test_6d_saddle_with_twenty_arcs():
+    from tests.test_oracle_pins import twenty_arc_saddle
+    f, centre, ids = twenty_arc_saddle()
+    for minima in (False, True):
+        want = O.extremum_graph(f, minima)
+        assert_same(gpu_graph(f, minima), want, KEYS + ["ptr"], f"twenty arcs minima={minima}")
+    g = gpu_graph(f)
+    i = int(np.searchsorted(g["saddles"], centre))
+    assert list(g["arc_maxima"][g["arc_offsets"][i]:g["arc_offsets"][i + 1]]) == ids
 
 
 def test_gaussian_mixture_4d():
@@ -295,7 +320,8 @@ def _assert_paths(f, minima, ctx="", **caps):
                                  f"sizes {a.size} {b.size}")
 
 
-@pytest.mark.parametrize("shape", [(40,), (17, 23), (9, 10, 11), (7, 6, 5, 4), (5, 4, 5, 3, 4), (1, 1), (3, 2, 1)])
+@pytest.mark.parametrize("shape", [(40,), (17, 23), (9, 10, 11), (7, 6, 5, 4), (5, 4, 5, 3, 4), (4, 3, 3, 4, 3, 3),
+                                   (1, 1), (3, 2, 1)])
 @pytest.mark.parametrize("kind", ["uniform", "ties"])
 def test_paths_equal_oracle(shape, kind):
     f = W.random_field(shape, 61, kind)

@@ -102,6 +102,31 @@ def test_schwefel_6d_invariants(shape):
         check_invariants(f, O.extremum_graph(f, minima), minima)
 
 
+def twenty_arc_saddle():
+    """A 3^6 grid whose centre has an upper link of the 20 neighbours at
+    offsets with exactly three +1 entries: no two of them are adjacent (their
+    difference has both signs), each is a maximum, so the centre is a saddle
+    with beta = 20 and 20 arcs.  Returns (field, centre, the 20 ids)."""
+    shape = (3,) * 6
+    f = np.zeros(shape, np.float32)
+    c = (1,) * 6
+    f[c] = 1.0
+    ids = []
+    for k, ones in enumerate(itertools.combinations(range(6), 3)):
+        p = tuple(2 if i in ones else 1 for i in range(6))
+        f[p] = 2.0 + 0.01 * k
+        ids.append(int(np.ravel_multi_index(p, shape)))
+    return f, int(np.ravel_multi_index(c, shape)), sorted(ids)
+
+
+def test_6d_saddle_with_twenty_arcs():
+    f, centre, ids = twenty_arc_saddle()
+    g = O.extremum_graph(f)
+    i = int(np.searchsorted(g["saddles"], centre))
+    assert g["saddles"][i] == centre and g["saddle_beta"][i] == 20
+    assert list(g["arc_maxima"][g["arc_offsets"][i]:g["arc_offsets"][i + 1]]) == ids
+
+
 def test_beta_histogram_3d():
     g = _load("link_counts.json")["beta_histogram_3d"]
     nb = O.neighbours((3, 3, 3), 13)
