@@ -498,6 +498,9 @@ def main():
     res = b.run(t)  # sizes the buffers (untimed)
     counts = dict(res.counts)
     counts["jump_passes"] = res.passes
+    # saddles whose arcs reach at least two distinct maxima (the others have
+    # beta >= 2 components that all end at one maximum)
+    counts["separating_saddles"] = int((res.arc_offsets[1:] - res.arc_offsets[:-1] >= 2).sum().item())
 
     s = torch.cuda.current_stream()
     for _ in range(args.warmup):

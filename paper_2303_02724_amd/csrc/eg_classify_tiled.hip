@@ -343,6 +343,27 @@ __device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u,
 //   bits 6..16  tile-local index offset (signed, 11 bits)
 //   bit 31      the vertex itself (a maximum)
 constexpr uint32_t kSelfPack = 1u << 31;
+
+// Halo positions outside the grid read one of these words instead of the
+// field: NaN bit patterns whose key (bits_key, computed on the bits, so no
+// float operation can rewrite them) is 1 in the maximum and in the minimum
+// graph, below the key of every number.  The halo loads then need no
+// validity flag after they are issued.
+__device__ const uint32_t c_outside[2] = {0xFFFFFFFFu, 0x7FFFFFFFu};
+
+// mode_key on the bit pattern: -0 folded into +0 by an integer test, the same
+// order-preserving flip and clamp.
+template <bool MINMODE>
+__device__ __forceinline__ uint32_t bits_key(uint32_t b)
+{
+    b = b == 0x80000000u ? 0u : b;
+    const uint32_t k = min(max(b ^ ((uint32_t)((int32_t)b >> 31) | 0x80000000u), 1u), 0xFFFFFFFEu);
+    return MINMODE ? ~k : k;
+}
+
+// Keys of numbers lie in [0x007FFFFF, 0xFF800000] in both graphs (-inf and
+// +inf at the ends); keys outside come from NaN patterns.
+__device__ __forceinline__ bool nan_key(uint32_t k) { return k < 0x007FFFFFu || k > 0xFF800000u; }
 template <int TY, int HY, int HX>
 __device__ __forceinline__ constexpr uint32_t succ_pack(int dz, int dy, int dx)
 {
@@ -409,22 +430,24 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
     {
         // every load of this thread is issued before the first one is used:
         // rows of 64 aligned values (one per lane), then the two edge columns
-        // of every row (one value per thread)
+        // of every row (one value per thread); positions outside the grid
+        // read the outside word
         constexpr int ROWS = HY * HZ;
         constexpr int RPW = (ROWS + 3) / 4;
         constexpr int EDGES = 2 * ROWS;
         static_assert(EDGES <= 256, "one edge value per thread");
+        const uint32_t* __restrict__ fb = reinterpret_cast<const uint32_t*>(f);
+        const uint32_t* outside = &c_outside[MINMODE ? 1 : 0];
         const int gx = x0 + lx;
         const bool xin = gx < X;
-        float vals[RPW];
-        bool vin[RPW];
+        uint32_t vals[RPW];
 #pragma unroll
         for (int i = 0; i < RPW; ++i) {
             const int row = wv + 4 * i;
             const int hy = row % HY, hz = row / HY;
             const int gy = y0 + hy - 1, gz = z0 + hz - 1;
-            vin[i] = row < ROWS && xin && (unsigned)gy < (unsigned)Y && (unsigned)gz < (unsigned)Z;
-            vals[i] = vin[i] ? f[gz * SZ + gy * SY + gx] : 0.0f;
+            const bool vin = row < ROWS && xin && (unsigned)gy < (unsigned)Y && (unsigned)gz < (unsigned)Z;
+            vals[i] = *(vin ? fb + (gz * SZ + gy * SY + gx) : outside);
         }
         // edge value of this thread: row tid >> 1, left (x0 - 1) or right (x0 + 64)
         const int erow = tid >> 1;
@@ -433,21 +456,16 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
         const int egy = y0 + ehy - 1, egz = z0 + ehz - 1;
         const bool ein = tid < EDGES && (unsigned)egx < (unsigned)X && (unsigned)egy < (unsigned)Y &&
                          (unsigned)egz < (unsigned)Z;
-        const float eval = ein ? f[egz * SZ + egy * SY + egx] : 0.0f;
+        const uint32_t eval = *(ein ? fb + (egz * SZ + egy * SY + egx) : outside);
         const uint32_t conn_a = c_conn3.w[tid], conn_b = c_conn3.w[tid + 256];
         s_conn[tid] = conn_a;
         s_conn[tid + 256] = conn_b;
 #pragma unroll
         for (int i = 0; i < RPW; ++i) {
             const int row = wv + 4 * i;
-            if (row < ROWS) {
-                const int hy = row % HY, hz = row / HY;
-                const float val = vals[i];
-                s_u[row * HX + lx + 1] = vin[i] ? mode_key<MINMODE>(val) : 0u;
-                nan |= vin[i] && (hy >= 1 && hy <= TY && hz >= 1 && hz <= TZ) && (val != val);
-            }
+            if (row < ROWS) s_u[row * HX + lx + 1] = bits_key<MINMODE>(vals[i]);
         }
-        if (tid < EDGES) s_u[erow * HX + ((tid & 1) ? HX - 1 : 0)] = ein ? mode_key<MINMODE>(eval) : 0u;
+        if (tid < EDGES) s_u[erow * HX + ((tid & 1) ? HX - 1 : 0)] = bits_key<MINMODE>(eval);
     }
     __syncthreads();
 
@@ -482,6 +500,7 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
             const int gz = z0 + lz;
             const bool in = gx < X && gy < Y && gz < Z;
             const uint32_t uv = win[(lz + 1) % 3][3];
+            nan |= in && nan_key(uv);
             // upper-link mask in two 7-row halves (bit constants stay inline)
             uint32_t up_lo = 0, up_hi = 0, best_u = 0;
             int best_j = K;  // the steepest candidate so far; K is the vertex itself
