@@ -193,7 +193,8 @@ __device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u,
     int32_t* __restrict__ ptr = a.ptr;
     uint32_t* __restrict__ ctr = a.ctr;
 
-    const int tid = threadIdx.x, lx = tid & 63, wv = tid >> 6;
+    // the wave index is uniform: keep it (and every row quantity) scalar
+    const int tid = threadIdx.x, lx = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int tx = b % a.tiles_x;
     const int rr = b / a.tiles_x;
     const int ty = rr % a.tiles_y;
@@ -404,7 +405,8 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
     uint32_t* s_pack = s_tmp + 8;
     int32_t* s_gdel = reinterpret_cast<int32_t*>(s_tmp + 8 + 16);
 
-    const int tid = threadIdx.x, lx = tid & 63, wv = tid >> 6;
+    // the wave index is uniform: keep it (and every row quantity) scalar
+    const int tid = threadIdx.x, lx = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int tx = b % a.tiles_x;
     const int rr = b / a.tiles_x;
     const int ty = rr % a.tiles_y;
@@ -472,14 +474,17 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
     static_assert(VPT <= 32, "one mask word per lane");
     int nxt[VPT];
     uint64_t word = 0;  // this lane's parked mask word
+    // x faces of the tile this lane's columns lie on (bit 0: lx = 0, bit 1:
+    // lx = 63), by shifts rather than compares, so that no lane mask has to
+    // stay alive across the unrolled loop
+    const uint32_t bx = ((uint32_t)(lx - 1) >> 31) | (((uint32_t)(lx + 1) >> 6) << 1);
 #pragma unroll
     for (int c = 0; c < YPT; ++c) {
         const int ly = wv + 4 * c;
         const int gy = y0 + ly;
         const int gx = x0 + lx;
         // tile faces this column lies on (see succ_pack)
-        const uint32_t bb_xy = (lx == 0 ? 1u : 0u) | (lx == TX - 1 ? 2u : 0u) | (ly == 0 ? 4u : 0u) |
-                               (ly == TY - 1 ? 8u : 0u);
+        const uint32_t bb_xy = bx | (ly == 0 ? 4u : 0u) | (ly == TY - 1 ? 8u : 0u);
         // window[p][q]: plane hz = lz + p, position q
         uint32_t win[3][7];
         auto load_plane = [&](uint32_t* w, int hz) {
@@ -601,7 +606,8 @@ __device__ __forceinline__ void final_tile(const TileArgs& a, int b, const int32
     const int N = X * Y * Z;
     const int SY = X, SZ = X * Y;
     int32_t* lab = a.lab;
-    const int tid = threadIdx.x, lx = tid & 63, wv = tid >> 6;
+    // the wave index is uniform: keep it (and every row quantity) scalar
+    const int tid = threadIdx.x, lx = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int tx = b % a.tiles_x;
     const int rr = b / a.tiles_x;
     const int ty = rr % a.tiles_y;
