@@ -125,7 +125,8 @@ typedef struct eg_out {
  * Workspace bytes that eg_build needs for a field of the given shape and the
  * given saddle capacity (eg_out.cap_sad; the other capacities do not enter):
  * about 4.25 bytes per vertex (more when the last axis is much shorter than
- * 64; 4 more for 1D, 4D, 5D and 6D grids) plus 16 bytes per saddle slot.  Pure,
+ * 64; 4 more for 1D, 4D, 5D and 6D grids) plus 16 bytes per saddle slot (32
+ * for 4D, 5D and 6D grids).  Pure,
  * host-only.  Returns 0 on invalid arguments (ndim outside [1, EG_MAX_NDIM],
  * a dim < 1, N >= 2^31, a capacity outside [0, 2^31)).
  */

@@ -254,13 +254,29 @@ __global__ __launch_bounds__(256) void k_mask_emit(Sel sel)
 // The neighbourhood of saddle v: order keys (0 outside the grid, below every
 // vertex) and linear offsets of the K Freudenthal rows, and the upper-link
 // mask (Alg. 1, Sec. 3.3).
+// From 4D on (30 to 126 rows) only the mask is kept: holding every row's key
+// and offset in registers costs more registers, and waves, than reloading the
+// few keys of one component when its rep is sought (they are in cache).
+template <int NDIM>
+constexpr bool kLazyNbhd = NDIM >= 4;
+
 template <int NDIM, bool MINMODE>
 struct Nbhd {
     static constexpr int K = Rows<NDIM>::K;
-    uint32_t us[K];
-    int offs[K];
+    static constexpr int KS = kLazyNbhd<NDIM> ? 1 : K;
+    uint32_t us[KS];
+    int offs[KS];
     Mask<NDIM> up;
+    EG_GPTR(const uint32_t) keys;  // the order keys (lazy neighbourhoods)
 };
+
+// Linear offset of every row, per block (lazy neighbourhoods).
+template <int NDIM>
+__device__ __forceinline__ int* row_offsets()
+{
+    __shared__ int s_off[Rows<NDIM>::K];
+    return s_off;
+}
 
 template <int NDIM, bool MINMODE>
 __device__ __forceinline__ void load_nbhd(const ArcArgs& A, int v, Nbhd<NDIM, MINMODE>& nb)
@@ -284,6 +300,7 @@ __device__ __forceinline__ void load_nbhd(const ArcArgs& A, int v, Nbhd<NDIM, MI
     const bool stored = A.keys != nullptr;
     const uint32_t uv = stored ? A.keys[v] : mode_key<MINMODE>(A.f[v]);
     nb.up = 0;
+    nb.keys = A.keys;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         bool in = true;
@@ -296,9 +313,11 @@ __device__ __forceinline__ void load_nbhd(const ArcArgs& A, int v, Nbhd<NDIM, MI
                 off += d * st[i];
             }
         }
-        nb.offs[j] = off;
         const uint32_t u = !in ? 0u : stored ? A.keys[v + off] : mode_key<MINMODE>(A.f[v + off]);
-        nb.us[j] = u;
+        if constexpr (!kLazyNbhd<NDIM>) {
+            nb.offs[j] = off;
+            nb.us[j] = u;
+        }
         const bool wins_tie = (j >= K / 2) != MINMODE;
         nb.up |= Mask<NDIM>(wins_tie ? (u >= uv) : (u > uv)) << j;
     }
@@ -319,12 +338,28 @@ __device__ __forceinline__ void for_each_rep(int v, const Nbhd<NDIM, MINMODE>& n
         rem &= ~comp;
         uint32_t best_u = 0;
         int best_off = 0;
+        if constexpr (kLazyNbhd<NDIM>) {
+            // the component's rows in scan order: ascending rows, descending in
+            // the minimum graph; every row of the mask lies in the grid
+            const int* s_off = row_offsets<NDIM>();
+            for (Mask<NDIM> c = comp; c != 0;) {
+                const int j = MINMODE ? highest_bit(c) : lowest_bit(c);
+                c &= ~(Mask<NDIM>(1) << j);
+                const int off = s_off[j];
+                const uint32_t u = nb.keys[v + off];
+                if (u >= best_u) {
+                    best_u = u;
+                    best_off = off;
+                }
+            }
+        } else {
 #pragma unroll
-        for (int s = 0; s < K; ++s) {
-            const int j = MINMODE ? K - 1 - s : s;
-            if ((uint32_t)(comp >> j) & 1u && nb.us[j] >= best_u) {
-                best_u = nb.us[j];
-                best_off = nb.offs[j];
+            for (int s = 0; s < K; ++s) {
+                const int j = MINMODE ? K - 1 - s : s;
+                if ((uint32_t)(comp >> j) & 1u && nb.us[j] >= best_u) {
+                    best_u = nb.us[j];
+                    best_off = nb.offs[j];
+                }
             }
         }
         f(v + best_off);
@@ -405,11 +440,25 @@ __device__ __forceinline__ uint32_t labels_above(const ArcArgs& A, int v, const 
 }
 
 template <int NDIM>
-__device__ __forceinline__ void load_adj(Mask<NDIM>* s_adj)
+__device__ __forceinline__ void load_adj(const ArcArgs& A, Mask<NDIM>* s_adj)
 {
     constexpr int K = Rows<NDIM>::K;
     const Mask<NDIM>* t = adj_table<NDIM>();
     for (int i = threadIdx.x; i < K; i += blockDim.x) s_adj[i] = t[i];
+    if constexpr (kLazyNbhd<NDIM>) {
+        constexpr Rows<NDIM> R = make_rows_ce<NDIM>();
+        int* s_off = row_offsets<NDIM>();
+        int st[NDIM];
+        st[NDIM - 1] = 1;
+#pragma unroll
+        for (int i = NDIM - 2; i >= 0; --i) st[i] = st[i + 1] * A.dims[i + 1];
+        for (int j = threadIdx.x; j < K; j += blockDim.x) {
+            int off = 0;
+#pragma unroll
+            for (int i = 0; i < NDIM; ++i) off += R.d[j][i] * st[i];
+            s_off[j] = off;
+        }
+    }
     __syncthreads();
 }
 
@@ -419,7 +468,7 @@ template <int NDIM, bool MINMODE>
 __device__ __forceinline__ void arc_count_body(const ArcArgs& A, uint32_t blk, uint32_t nb, Mask<NDIM>* s_adj,
                                                uint32_t* tmp)
 {
-    load_adj<NDIM>(s_adj);
+    load_adj<NDIM>(A, s_adj);
     uint32_t lo, hi;
     chunk(saddle_count(A), nb, blk, lo, hi);
     const int tid = threadIdx.x;
@@ -440,6 +489,7 @@ __device__ __forceinline__ void arc_count_body(const ArcArgs& A, uint32_t blk, u
         if (A.beta) A.beta[i] = beta;
         A.offsets[i + 1] = (int32_t)n;  // the count until k_arc_write turns it into an offset
         A.atmp[i] = make_uint4(r.lo[0], r.lo[1], r.lo[2], r.lo[3]);
+        if constexpr (S > 4) A.atmp[A.cap_sad + i] = make_uint4(r.lo[4], r.lo[5], r.lo[6], r.lo[7]);
         sc += n;
         sb += (uint32_t)beta;
     }
@@ -455,7 +505,7 @@ template <int NDIM, bool MINMODE>
 __device__ __forceinline__ void arc_write_body(const ArcArgs& A, uint32_t blk, uint32_t nb, Mask<NDIM>* s_adj,
                                                uint32_t* tmp)
 {
-    load_adj<NDIM>(s_adj);
+    load_adj<NDIM>(A, s_adj);
     uint32_t lo, hi;
     chunk(saddle_count(A), nb, blk, lo, hi);
     const int tid = threadIdx.x;
@@ -473,26 +523,27 @@ __device__ __forceinline__ void arc_write_body(const ArcArgs& A, uint32_t blk, u
 #pragma unroll
             for (uint32_t k = 0; k < 4; ++k)
                 if (k < n && pos + k < A.cap_arc) A.arcs[pos + k] = (int32_t)a4[k];
-            if (n > 4) {
-                // past the four stored arcs: the list again, then (beyond
-                // its S entries) ascending selection
+            constexpr int S = ArcList<NDIM>::S;
+            uint32_t last = t.w;
+            if constexpr (S > 4) {
+                // the next four stored arcs
+                if (n > 4) {
+                    const uint4 u = A.atmp[A.cap_sad + i];
+                    const uint32_t b4[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                    for (uint32_t k = 0; k < 4; ++k)
+                        if (4 + k < n && pos + 4 + k < A.cap_arc) A.arcs[pos + 4 + k] = (int32_t)b4[k];
+                    last = u.w;
+                }
+            }
+            if (n > (uint32_t)S) {
+                // past the stored arcs: ascending selection over the components
                 const int v = min(max(A.saddles[i], 0), A.N - 1);
                 Nbhd<NDIM, MINMODE> h;
                 load_nbhd<NDIM, MINMODE>(A, v, h);
-                constexpr int S = ArcList<NDIM>::S;
-                uint32_t last = t.w;
-                if constexpr (S > 4) {
-                    int beta;
-                    const ArcList<NDIM> r = first_arcs<NDIM, MINMODE>(A, v, h, s_adj, beta);
-#pragma unroll
-                    for (uint32_t k = 4; k < (uint32_t)S; ++k)
-                        if (k < n && pos + k < A.cap_arc) A.arcs[pos + k] = (int32_t)r.lo[k];
-                    last = r.lo[S - 1];
-                }
-                if (n > (uint32_t)S)
-                    labels_above<NDIM, MINMODE>(A, v, h, s_adj, last, [&](uint32_t k, uint32_t L) {
-                        if (pos + S + k < A.cap_arc) A.arcs[pos + S + k] = (int32_t)L;
-                    });
+                labels_above<NDIM, MINMODE>(A, v, h, s_adj, last, [&](uint32_t k, uint32_t L) {
+                    if (pos + S + k < A.cap_arc) A.arcs[pos + S + k] = (int32_t)L;
+                });
             }
             A.offsets[i + 1] = (int32_t)(pos + n);
         }
@@ -588,7 +639,7 @@ __global__ __launch_bounds__(256) void k_path_count(OneField sel, PathArgs P)
     __shared__ uint32_t tmp[4];
     uint32_t blk, nb;
     const ArcArgs A = sel.locate(blk, nb);  // a copy: loop loads cannot alias it
-    load_adj<NDIM>(s_adj);
+    load_adj<NDIM>(A, s_adj);
     uint32_t lo, hi;
     chunk(saddle_count(A), nb, blk, lo, hi);
     uint32_t sp = 0, sv = 0;
@@ -627,7 +678,7 @@ __global__ __launch_bounds__(256) void k_path_write(OneField sel, PathArgs P)
     __shared__ uint32_t tmp[4];
     uint32_t blk, nb;
     const ArcArgs A = sel.locate(blk, nb);  // a copy: loop loads cannot alias it
-    load_adj<NDIM>(s_adj);
+    load_adj<NDIM>(A, s_adj);
     uint32_t lo, hi;
     chunk(saddle_count(A), nb, blk, lo, hi);
     uint32_t runp = A.bsum[blk], runv = A.bsum[kArcBlocks + blk];

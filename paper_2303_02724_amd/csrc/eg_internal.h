@@ -96,7 +96,7 @@ struct Work {
     uint64_t* mmask;  // [words] maxima
     uint64_t* smask;  // [words] saddles
     uint32_t* bsum;   // [4 * kArcBlocks] per-block counts of stage (d)
-    uint4* atmp;      // [cap_sad] the first four arcs of every saddle
+    uint4* atmp;      // [cap_sad] the first four arcs of every saddle ([2 cap_sad], eight, from 4D on)
     uint32_t* exits;  // [cap_exit] exit vertices published by the tiles
     int32_t* exres;   // [cap_exit] their labels while being resolved
     uint32_t* keys;   // [N] order keys of the untiled grids (1D, 4D, 5D); else null

@@ -154,6 +154,14 @@ __device__ __forceinline__ int lowest_bit(unsigned __int128 m)
     return lo ? __ffsll((unsigned long long)lo) - 1 : 64 + __ffsll((unsigned long long)(uint64_t)(m >> 64)) - 1;
 }
 
+// Index of the highest set bit of a non-empty mask.
+__device__ __forceinline__ int highest_bit(uint64_t m) { return 63 - __clzll((long long)m); }
+__device__ __forceinline__ int highest_bit(unsigned __int128 m)
+{
+    const uint64_t hi = (uint64_t)(m >> 64);
+    return hi ? 127 - __clzll((long long)hi) : 63 - __clzll((long long)(uint64_t)m);
+}
+
 // Component of `seed` inside `mask` (BFS over link edges, bit-parallel).
 template <class M>
 __device__ __forceinline__ M closure(M seed, M mask, const M* adj)

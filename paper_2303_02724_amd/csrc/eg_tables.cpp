@@ -108,7 +108,10 @@ Work carve(void* base, int ndim, int64_t N, int64_t X, int64_t cap_sad)
     const size_t o_mm = take(sizeof(uint64_t) * (size_t)w.words);
     const size_t o_sm = take(sizeof(uint64_t) * (size_t)w.words);
     const size_t o_bs = take(sizeof(uint32_t) * 4 * kArcBlocks);
-    const size_t o_at = take(sizeof(uint4) * (size_t)std::max<int64_t>(cap_sad, 1));
+    // the first four arcs of every saddle; 4D and up keep eight (a second
+    // block of cap_sad entries)
+    const size_t at_rows = ndim >= 4 ? 2 : 1;
+    const size_t o_at = take(sizeof(uint4) * at_rows * (size_t)std::max<int64_t>(cap_sad, 1));
     const size_t o_ex = take(sizeof(uint32_t) * (size_t)std::max<int64_t>(w.cap_exit, 1));
     const size_t o_er = take(sizeof(int32_t) * (size_t)std::max<int64_t>(w.cap_exit, 1));
     // grids without LDS tiles read every neighbour from memory: their order
