@@ -1,5 +1,6 @@
 // eg_api.cpp -- the C ABI: argument checks, workspace carving and the kernel
 // sequence on the caller's stream.  Nothing here allocates or synchronises.
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -103,6 +104,7 @@ eg_status run_stages(int stages, const float* field, int ndim, const int64_t* di
     make_table(g, &t);
     Tuning tu;
     decode_tuning(out->tuning, &tu);
+    tu.passes = passes_for(tu, g.N);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipSuccess;
     if (stages & S_CLASSIFY) e = stage_classify(field, g, t, *out, w, tu, s);
@@ -228,6 +230,9 @@ eg_status eg_batch_plan(int count, const float* const* fields, const int* ndims,
         ++cls;
     }
     P->class_tile[0] = 0;
+    int64_t max_n = 1;
+    for (int i = 0; i < count; ++i) max_n = std::max<int64_t>(max_n, F[i].N);
+    P->tuning.passes = passes_for(P->tuning, max_n);
     P->total_tiles = tiles;
     P->total_arc_blocks = arc_blocks_total;
     return EG_OK;

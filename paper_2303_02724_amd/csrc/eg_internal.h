@@ -38,6 +38,10 @@ struct Tuning {
     int passes; // passes that cover any path of fewer than 2^31 links
 };
 bool decode_tuning(uint32_t t, Tuning* out);
+// Label passes for a grid of n vertices: a steepest-ascent path has fewer
+// than n links and pass p leaves every entry hops^(p+1) links further on or
+// final, so the smallest p with hops^p >= n suffices (at most t.passes).
+int passes_for(const Tuning& t, int64_t n);
 inline void tile_shape(const Tuning& t, int ndim, int* ty, int* tz)
 {
     if (ndim == 3) {

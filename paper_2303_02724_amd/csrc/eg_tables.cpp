@@ -38,6 +38,13 @@ int make_rows(int ndim, int8_t (*off)[EG_MAX_NDIM], uint64_t* adj)
     }
 }
 
+int passes_for(const Tuning& t, int64_t n)
+{
+    int p = 1;
+    for (int64_t reach = t.hops; reach < n && p < t.passes; reach *= t.hops) ++p;
+    return p;
+}
+
 void make_table(const Grid& g, LinkTable* t)
 {
     int8_t off[kMaxNb][EG_MAX_NDIM];
