@@ -21,6 +21,8 @@
 // Every kernel is written against a field selector: OneField (the field is
 // the kernel argument, blocks are blockIdx.x) or BatchFields (the plan lists
 // the fields; a flat grid is split over them in proportion to their size).
+#include <algorithm>
+
 #include "eg_internal.h"
 #include "eg_rows.h"
 
@@ -795,10 +797,13 @@ __global__ void k_finalize(Sel sel)
 
 // ------------------------------------------------------------------ launchers
 
-// Blocks per field of the stage (d) kernels: one per kArcVertsPerBlock vertices.
+// Blocks per field of the stage (d) kernels: one per kArcVertsPerBlock
+// vertices; a small field still gets up to 64 blocks (one per 1024 vertices),
+// so that its saddles spread over the GPU instead of queueing in a few blocks.
 uint32_t arc_blocks(int64_t N)
 {
-    const int64_t b = (N + kArcVertsPerBlock - 1) / kArcVertsPerBlock;
+    int64_t b = (N + kArcVertsPerBlock - 1) / kArcVertsPerBlock;
+    if (b < 64) b = std::min<int64_t>(64, (N + 1023) / 1024);
     return (uint32_t)(b < 1 ? 1 : b > kArcBlocks ? kArcBlocks : b);
 }
 
