@@ -9,11 +9,12 @@
 //   2. k_arc_count: for every saddle, the highest vertex of each upper-link
 //      component (UpperLinkRep, Sec. 3.4), the label it reaches, and the
 //      number of distinct labels: the saddle's arcs (arcs form a set,
-//      Sec. 2); the smallest are kept in registers (four are stored);
+//      Sec. 2); the smallest are kept in registers and stored (four in 2D
+//      and 3D, eight from 4D on);
 //   3. k_scan_rows / k_arc_write: the CSR offsets from a scan of the counts,
-//      then the arcs (a saddle with more distinct arcs than the register
-//      list holds, rare, finds the rest in ascending order by one more pass
-//      over its components per arc);
+//      then the arcs (a saddle with more distinct arcs than were stored,
+//      rare, finds the rest in ascending order by one more pass over its
+//      components per arc);
 //   4. k_finalize: status and counts into the header.
 // No step uses an atomic: every position comes from a scan, so results do
 // not depend on scheduling.
@@ -379,7 +380,7 @@ __device__ __forceinline__ void for_each_arc_label(const ArcArgs& A, int v, cons
 // The S smallest distinct arc labels of a saddle, ascending (unused entries
 // ~0u; labels are vertex ids below 2^31).  `more` is set when the saddle has
 // further distinct labels above lo[S-1].  S = 4 in 2D/3D (at most 3 and 6
-// components), 8 in 4D/5D, where more components are common.
+// components), 8 from 4D on, where more components are common.
 template <int NDIM>
 struct ArcList {
     static constexpr int S = NDIM >= 4 ? 8 : 4;
@@ -464,7 +465,7 @@ __device__ __forceinline__ void load_adj(const ArcArgs& A, Mask<NDIM>* s_adj)
     __syncthreads();
 }
 
-// Distinct-arc count, beta and the first four arcs of every saddle of the
+// Distinct-arc count, beta and the first four (eight from 4D on) arcs of every saddle of the
 // block's chunk; the block's sums of both counts go to rows 2 and 3.
 template <int NDIM, bool MINMODE>
 __device__ __forceinline__ void arc_count_body(const ArcArgs& A, uint32_t blk, uint32_t nb, Mask<NDIM>* s_adj,

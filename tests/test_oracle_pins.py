@@ -1,7 +1,7 @@
 """Pins for the CPU oracle: it is checked against things other than itself.
 
 * golden worked examples computed by hand (tests/golden/*.json),
-* the literal all-pairs brute force (oracle/brute.py) on tiny grids, n = 1..5,
+* the literal all-pairs brute force (oracle/brute.py) on tiny grids, n = 1..6,
 * neighbour counts, link f-vectors and the 3D upper-link histogram,
 * closed forms (constant, linear, concave quadratic, 1D peaks and valleys),
 * the Banchoff / Euler sum, which holds for any field on a triangulated box,
