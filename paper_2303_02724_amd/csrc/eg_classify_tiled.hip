@@ -68,14 +68,6 @@ struct Pack {
 // a later vertex of the steepest-ascent path.  The jump kernel resolves the
 // negative entries.
 
-// Tile-local successor index -> global id (TX = 64).
-template <int TY>
-__device__ __forceinline__ int tile_to_global(int n, int x0, int y0, int z0, int SY, int SZ)
-{
-    const int lx = n & 63, ly = (n >> 6) % TY, lz = (n >> 6) / TY;
-    return (z0 + lz) * SZ + (y0 + ly) * SY + x0 + lx;
-}
-
 // Resolve the tile's successor array by pointer jumping.  cur[k] holds the
 // successor of this thread's k-th vertex (s_idx(k) is its tile index): >= 0 a
 // tile index (a maximum is its own successor), < 0 the exit code of the first
@@ -319,14 +311,20 @@ __device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u,
 #pragma unroll
     for (int k = 0; k < VPT; ++k) s_nxt[s_idx(k)] = nxt[k];
     __syncthreads();
+    // global offset of every tile row from the tile's first vertex (one LDS
+    // read per vertex instead of quarter-rate multiplies)
+    __shared__ int s_rowoff[TY * TZ];
+    if (tid < TY * TZ) s_rowoff[tid] = (tid / TY) * SZ + (tid % TY) * SY;
     double_tile_chains<VPT>(nxt, s_nxt, s_idx);
+    const int tile0 = z0 * SZ + y0 * SY + x0;
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
         const int ly = wv + 4 * (k % YPT);
         const int lz = k / YPT;
         const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
         const int n = nxt[k];
-        if (gx < X && gy < Y && gz < Z) lab[gz * SZ + gy * SY + gx] = n >= 0 ? tile_to_global<TY>(n, x0, y0, z0, SY, SZ) : n;
+        if (gx < X && gy < Y && gz < Z)
+            lab[tile0 + s_rowoff[lz * TY + ly] + lx] = n >= 0 ? tile0 + s_rowoff[n >> 6] + (n & 63) : n;
     }
 }
 
