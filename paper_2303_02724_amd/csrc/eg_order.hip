@@ -20,8 +20,8 @@
 // in which the keys differ are skipped on the device (the range is reduced
 // first, the host never waits).  Each pass: per-block digit histograms, a
 // scan of each digit's row over the blocks, and a stable scatter in which a
-// block ranks a tile of 2048 keys by wave ballots, sorts the tile by digit in
-// LDS and writes each digit's run contiguously.  The last pass that runs
+// block ranks a tile of 2048 keys by wave ballots (each wave its own quarter),
+// sorts the tile by digit in LDS and writes each digit's run contiguously.  The last pass that runs
 // writes no keys: each element's final position is its rank, stored straight
 // into the surrogate (one 4-byte store per vertex, at no particular place).
 #include <hip/hip_runtime.h>
@@ -286,6 +286,11 @@ __global__ __launch_bounds__(1024) void k_scan_row(uint32_t* __restrict__ hist, 
 
 // Stable scatter of block b's chunk.  first: the input indices are the
 // positions themselves (the pass that reads the keys in index order).
+// A tile of 2048 keys is split into four contiguous quarters, one per wave;
+// a wave ranks its keys by digit with ballots against its own running digit
+// counts (wave-private, so no barrier is needed), then one block-wide step
+// turns the four waves' counts into tile offsets.  Tile order is index order,
+// so the ranks are stable.
 template <typename K>
 __global__ __launch_bounds__(kThreads) void k_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ iin,
                                                       K* __restrict__ kout, uint32_t* __restrict__ iout, uint32_t n,
@@ -294,11 +299,12 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const K* __restrict__ kin,
                                                       const uint32_t* __restrict__ rows, bool first,
                                                       float* __restrict__ out)
 {
-    __shared__ uint32_t run[kDigits];   // next output position of each digit
-    __shared__ uint32_t tcnt[kDigits];  // digit counts of the tile
-    __shared__ uint32_t toff[kDigits];  // their exclusive scan
-    __shared__ uint32_t wcnt[kThreads / 64][kDigits];
-    __shared__ uint32_t wsum[kThreads / 64];
+    constexpr int W = kThreads / 64;
+    __shared__ uint32_t run[kDigits];      // next output position of each digit
+    __shared__ uint32_t toff[kDigits];     // tile offset of each digit
+    __shared__ uint32_t wcnt[W][kDigits];  // each wave's digit counts in the tile
+    __shared__ uint32_t wpre[W][kDigits];  // digit counts of the waves before it
+    __shared__ uint32_t wsum[W];
     __shared__ K skey[kTile];
     __shared__ uint32_t sidx[kTile];
     if ((uint32_t)shift >= ctl->nbits) return;
@@ -320,8 +326,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const K* __restrict__ kin,
         for (int k = 0; k < w; ++k) pre += wsum[k];
         run[tid] = pre + inc - x + hist[tid * gridDim.x + blockIdx.x];
     }
-    tcnt[tid] = 0;
-    for (int k = 0; k < kThreads / 64; ++k) wcnt[k][tid] = 0;
+    for (int k = 0; k < W; ++k) wcnt[k][tid] = 0;
     __syncthreads();
     const uint64_t lt = (uint64_t(1) << lane) - 1;
 
@@ -330,12 +335,14 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const K* __restrict__ kin,
         uint32_t id[kItems], dg[kItems], rk[kItems];
 #pragma unroll
         for (int j = 0; j < kItems; ++j) {
-            const uint32_t i = base + j * kThreads + tid;
+            const uint32_t i = base + (w * kItems + j) * 64 + lane;
             const bool valid = i < hi;
             key[j] = valid ? kin[i] : K(0);
             id[j] = valid ? (first ? i : iin[i]) : 0u;
             dg[j] = valid ? digit(key[j], kmin, shift) : (uint32_t)kDigits;
         }
+        // ranks within the wave: lanes read the running count, then the first
+        // lane of each digit group adds the group (in program order)
 #pragma unroll
         for (int j = 0; j < kItems; ++j) {
             const bool valid = dg[j] < (uint32_t)kDigits;
@@ -347,37 +354,32 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const K* __restrict__ kin,
                 peers &= on ? bm : ~bm;
             }
             const uint32_t r = (uint32_t)__popcll(peers & lt);
-            if (valid && r == 0) wcnt[w][dg[j]] = (uint32_t)__popcll(peers);
-            __syncthreads();
-            if (valid) {
-                uint32_t pre = tcnt[dg[j]];
-                for (int k = 0; k < w; ++k) pre += wcnt[k][dg[j]];
-                rk[j] = pre + r;
-            }
-            __syncthreads();
-            uint32_t add = 0;
-            for (int k = 0; k < kThreads / 64; ++k) {
-                add += wcnt[k][tid];
-                wcnt[k][tid] = 0;
-            }
-            tcnt[tid] += add;
-            __syncthreads();
+            const uint32_t before = valid ? wcnt[w][dg[j]] : 0u;
+            rk[j] = before + r;
+            if (valid && r == 0) wcnt[w][dg[j]] = before + (uint32_t)__popcll(peers);
         }
-        // tile-local digit offsets
+        __syncthreads();
+        // per digit (thread = digit): the waves' prefixes and the tile offsets
+        uint32_t tcnt = 0;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            wpre[k][tid] = tcnt;
+            tcnt += wcnt[k][tid];
+            wcnt[k][tid] = 0;
+        }
         {
-            const uint32_t x = tcnt[tid];
-            const uint32_t inc = wave_incl_scan(x);
+            const uint32_t inc = wave_incl_scan(tcnt);
             if (lane == 63) wsum[w] = inc;
             __syncthreads();
             uint32_t pre = 0;
             for (int k = 0; k < w; ++k) pre += wsum[k];
-            toff[tid] = pre + inc - x;
+            toff[tid] = pre + inc - tcnt;
         }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kItems; ++j) {
             if (dg[j] < (uint32_t)kDigits) {
-                const uint32_t p = toff[dg[j]] + rk[j];
+                const uint32_t p = toff[dg[j]] + wpre[w][dg[j]] + rk[j];
                 skey[p] = key[j];
                 sidx[p] = id[j];
             }
@@ -396,9 +398,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const K* __restrict__ kin,
             }
         }
         __syncthreads();
-        run[tid] += tcnt[tid];
-        tcnt[tid] = 0;
-        __syncthreads();
+        run[tid] += tcnt;
     }
 }
 
