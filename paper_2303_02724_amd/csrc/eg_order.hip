@@ -21,9 +21,10 @@
 // first, the host never waits).  Each pass: per-block digit histograms, a
 // scan of each digit's row over the blocks, and a stable scatter in which a
 // block ranks a tile of 2048 keys by wave ballots (each wave its own quarter),
-// sorts the tile by digit in LDS and writes each digit's run contiguously.  The last pass that runs
-// writes no keys: each element's final position is its rank, stored straight
-// into the surrogate (one 4-byte store per vertex, at no particular place).
+// sorts the tile by digit in LDS and writes each digit's run contiguously.
+// The last pass that runs writes no keys: each element's final position is
+// its rank, stored straight into the surrogate (one 4-byte store per vertex,
+// at no particular place).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
