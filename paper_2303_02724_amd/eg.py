@@ -478,11 +478,16 @@ class BatchBuilder:
         return ndims, dims, outs
 
     def plan(self, fields, stream=None):
+        """Fields of other sample types than float32 are planned through their
+        order surrogates (eg_order_field, one buffer per builder), which every
+        launch() recomputes before the batch."""
         if len(fields) != self.count:
             raise EGError(EG_ERR_ARG, "one field per builder")
         for f, b in zip(fields, self.builders):
-            if f.dtype != torch.float32 or not f.is_cuda or not f.is_contiguous() or f.numel() != b.n:
-                raise EGError(EG_ERR_ARG, "fields must be contiguous float32 device tensors of the builders' shapes")
+            if f.dtype not in DTYPES or not f.is_cuda or not f.is_contiguous() or f.numel() != b.n:
+                raise EGError(EG_ERR_ARG, "fields must be contiguous device tensors of the builders' shapes")
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        flo = [b._float_field(f, s) for f, b in zip(fields, self.builders)]
         L = lib()
         ndims, dims, outs = self._arrays()
         wsb = int(L.eg_batch_workspace_bytes(self.count, ndims, dims, outs))
@@ -497,13 +502,12 @@ class BatchBuilder:
             pinned = torch.empty(max(pb, 1 << 16), dtype=torch.uint8).pin_memory()
             self._pinned = pinned
         host = pinned[:pb]
-        fptrs = (ctypes.c_void_p * self.count)(*[f.data_ptr() for f in fields])
+        fptrs = (ctypes.c_void_p * self.count)(*[f.data_ptr() for f in flo])
         st = L.eg_batch_plan(self.count, fptrs, ndims, dims, outs, ctypes.c_void_p(base), wsb,
                              ctypes.c_void_p(host.data_ptr()), pb)
         if st != EG_OK:
             raise EGError(st, "eg_batch_plan")
         off = base - self._ws.data_ptr()
-        s = stream if stream is not None else torch.cuda.current_stream(self.device)
         with torch.cuda.stream(s):
             self._ws[off:off + pb].copy_(host, non_blocking=True)
         self._plan_host = host
@@ -515,6 +519,10 @@ class BatchBuilder:
         if self._plan_host is None:
             raise EGError(EG_ERR_ARG, "plan() first")
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # typed fields: refresh their order surrogates (the plan points at them)
+        for f, b in zip(self._fields, self.builders):
+            if f.dtype != torch.float32:
+                b._order.launch(f, s)
         st = lib().eg_build_batched(ctypes.c_void_p(self._plan_host.data_ptr()), ctypes.c_void_p(s.cuda_stream))
         if st != EG_OK:
             raise EGError(st, "eg_build_batched")
@@ -543,7 +551,8 @@ class BatchBuilder:
 
 
 def build_batched(fields, minima=False, **kw):
-    """Extremum graphs of a list of 2D/3D float32 device tensors in one batch."""
+    """Extremum graphs of a list of 2D/3D device tensors (float32, or any type of
+    DTYPES through its order surrogate) in one batch."""
     bb = BatchBuilder([f.shape for f in fields], minima=minima, device=fields[0].device, **kw)
     return bb.run([f.contiguous() for f in fields])
 

@@ -120,3 +120,29 @@ def test_typed_paths_and_simplify():
         lo, la = lib["arc_offsets"], lib["arc_maxima"]
         assert {i: la[lo[i]:lo[i + 1]].tolist() for i in range(len(lo) - 1) if lo[i + 1] > lo[i]} == \
             dict(zip(ss, rows))
+
+
+def test_typed_fields_in_a_batch():
+    """A batch mixing sample types: each field goes through its order
+    surrogate, recomputed at every launch; results equal the oracle's."""
+    dts = ["int16", "float64", "uint32", "int64", "uint8", "int32"]
+    shapes = [(50, 61), (18, 17, 19), (33, 70), (12, 23, 16), (64, 9), (21, 20, 22)]
+    fields = [W.typed_field(sh, 300 + i, dt) for i, (sh, dt) in enumerate(zip(shapes, dts))]
+    ts = [_dev(f) for f in fields]
+    bb = eg.BatchBuilder([f.shape for f in fields], minima=[False, True, False, True, False, True])
+    res = bb.run(ts)
+    for i, (f, r) in enumerate(zip(fields, res)):
+        minima = i % 2 == 1
+        got = {"labels": r.labels.reshape(-1).cpu().numpy(), "maxima": r.maxima.cpu().numpy(),
+               "saddles": r.saddles.cpu().numpy(), "saddle_beta": r.saddle_beta.cpu().numpy(),
+               "arc_offsets": r.arc_offsets.cpu().numpy(), "arc_maxima": r.arc_maxima.cpu().numpy()}
+        assert_same(got, O.extremum_graph(f, minima), KEYS, f"field {i} {dts[i]} {f.shape}")
+    # new values in the same tensors: a relaunch of the same plan refreshes the surrogates
+    for i, t in enumerate(ts):
+        g = W.typed_field(fields[i].shape, 400 + i, dts[i])
+        t.copy_(_dev(g))
+        fields[i] = g
+    bb.launch()
+    for i, (f, r) in enumerate(zip(fields, bb.finish())):
+        minima = i % 2 == 1
+        assert np.array_equal(r.labels.reshape(-1).cpu().numpy(), O.extremum_graph(f, minima)["labels"]), i
