@@ -302,6 +302,38 @@ def test_batched_graph_replays_match_eager():
             assert_same(_result_np(b.finish()), e, KEYS, f"replay {rep} {f.shape}")
 
 
+@pytest.mark.parametrize("shape", [(48, 40, 36), (23, 21, 19, 17), (30, 300)])
+def test_single_field_graph_replays_match_eager(shape):
+    """eg_build of one field captured in a HIP graph (3D tiles, the untiled
+    4D path, 2D tiles): every replay, with the outputs scribbled over and
+    synchronisation between replays, gives the eager result."""
+    import torch
+    from paper_2303_02724_amd import eg
+    f = W.gaussian_mixture(shape, 41, n_gauss=6, noise=1e-3)
+    t = torch.from_numpy(f).cuda()
+    b = eg.Builder(f.shape, want_ptr=True)
+    eager = _result_np(b.run(t))
+    assert_same(eager, O.extremum_graph(f), KEYS, f"eager {shape}")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        b.launch(t, stream=side)  # warm the capture stream
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        b.launch(t, stream=side)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        b.labels.fill_(-7)
+        b.arcs.fill_(-7)
+        b.header.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        b._stream = torch.cuda.current_stream()
+        assert_same(_result_np(b.finish()), eager, KEYS, f"replay {rep} {shape}")
+
+
 def _gpu_paths(f, minima=False, **caps):
     import torch
     from paper_2303_02724_amd import eg
