@@ -1,14 +1,17 @@
 // eg_classify.hip -- per-vertex classification, labels and saddle reps.
 //
-// k_classify_generic  stages (a) and (c) of the method for n = 1, 4, 5, 6: one
+// k_classify_generic  stages (a) and (c) of the method for n = 1 and 6: one
 //   thread per vertex reads its closed neighbourhood, forms the upper-link
 //   mask (Sec. 3.3), the steepest-ascent pointer (highest upper-link vertex,
 //   Sec. 3.3) and decides maximum (empty upper link) / saddle (>= 2
-//   components, Table 1) with a bit-parallel BFS over the link edges.
+//   components, Table 1) by set algebra on the link's rows (eg_link.h).
+// k_classify_slab  the same for n = 4 and 5, reading the neighbourhood from
+//   planes of keys staged in LDS.
 // k_exit_*, k_final  stage (b): pointer jumping until every vertex names its
 //   maximum (the end of the walk of Alg. 2).
 #include "eg_internal.h"
 #include "eg_rows.h"
+#include "eg_link.h"
 
 namespace eg {
 
@@ -26,8 +29,8 @@ hipError_t launch_init(uint32_t* ctr, int32_t* header, hipStream_t s)
 }
 
 // Visit the closed neighbourhood of v in the order in which later vertices
-// win ties; fills the upper-link mask and the steepest-ascent target.  Up to
-// 5D the rows are unrolled, one load per row under the row's own branch; a
+// win ties; fills the upper-link mask and the steepest-ascent target.  Below
+// 6D the rows are unrolled, one load per row under the row's own branch; a
 // row's linear offset and the boundary bits that rule it out follow from the
 // compile-time rows and the grid strides st[] (uniform, scalar work).
 template <int NDIM, bool MINMODE>
@@ -191,18 +194,15 @@ __global__ __launch_bounds__(256) void k_classify_generic(const uint32_t* __rest
 {
     constexpr int K = 2 * ((1 << NDIM) - 1);
     constexpr bool chunked = NDIM >= 6;
-    __shared__ Mask<NDIM> s_adj[K];
     __shared__ int32_t s_lin[chunked ? K : 1];
     __shared__ uint32_t s_forb[chunked ? K : 1];
-    const Mask<NDIM>* adj = adj_table<NDIM>();
-    for (int i = threadIdx.x; i < K; i += blockDim.x) {
-        s_adj[i] = adj[i];
-        if constexpr (chunked) {  // a runtime index into the table, only where it is used
+    if constexpr (chunked) {  // a runtime index into the table, only where it is used
+        for (int i = threadIdx.x; i < K; i += blockDim.x) {
             s_lin[i] = t.lin[i];
             s_forb[i] = t.forb[i];
         }
+        __syncthreads();
     }
-    __syncthreads();
 
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     bool is_max = false, is_sad = false;
@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256) void k_classify_generic(const uint32_t* __rest
             scan_unrolled<NDIM, MINMODE>(keys, st, v, bits, uv, up, best);
         }
         is_max = up == 0;
-        if (!is_max) is_sad = closure(up & (~up + 1), up, s_adj) != up;
+        if (!is_max) is_sad = !link_connected<NDIM>(up);
         lab[v] = is_max ? v : -(best + 1);  // final label, or "same as best"
         if (ptr) ptr[v] = best;
     }
@@ -231,6 +231,211 @@ __global__ __launch_bounds__(256) void k_classify_generic(const uint32_t* __rest
     const int64_t word = v < g.N ? (int64_t)row * ((X + 63) >> 6) + (x >> 6) : -1;
     mask_or(is_max, word, x & 63, mmask);
     mask_or(is_sad, word, x & 63, smask);
+}
+
+// ------------------------------------------------------- 4D and 5D slab tiles
+//
+// k_classify_slab  the same outputs as k_classify_generic for n = 4 and 5,
+//   with the neighbourhood read from LDS instead of through the caches (62
+//   gathers per vertex in 5D leave the generic kernel bound by the memory
+//   pipeline, not by arithmetic).  A block owns a tile of the hyperplanes
+//   orthogonal to axis 0 (2x4x32 vertices in 4D, 2x2x2x32 in 5D, one per
+//   thread) and a run of zc consecutive planes along axis 0.  It keeps three
+//   consecutive planes of the tile plus a one-vertex halo in a ring in LDS
+//   (positions outside the grid hold key 0, below every vertex, so every row
+//   of the table may be read), and slides it along axis 0: while one plane is
+//   classified, the loads of the plane after next are in flight.
+template <int NDIM>
+__host__ __device__ constexpr int slab_e(int i)  // interior extent along axis i (1..n-1)
+{
+    return i == NDIM - 1 ? 32 : (NDIM == 4 && i == 2) ? 4 : 2;
+}
+template <int NDIM>
+__host__ __device__ constexpr int slab_hs(int i)  // LDS stride of axis i in a halo plane
+{
+    int s = 1;
+    for (int k = NDIM - 1; k > i; --k) s *= slab_e<NDIM>(k) + 2;
+    return s;
+}
+template <int NDIM>
+__host__ __device__ constexpr int slab_size()  // keys per halo plane
+{
+    return slab_hs<NDIM>(0);
+}
+template <int NDIM>
+__host__ __device__ constexpr int slab_inner()  // vertices per tile plane
+{
+    int s = 1;
+    for (int k = 1; k < NDIM; ++k) s *= slab_e<NDIM>(k);
+    return s;
+}
+
+struct SlabArgs {
+    int32_t zc;                  // planes along axis 0 per block
+    int32_t zblocks;             // blocks along axis 0: ceil(dims[0] / zc)
+    int32_t nt[EG_MAX_NDIM];     // tiles along axes 1..n-1
+    int32_t st[EG_MAX_NDIM];     // grid strides (st[n-1] = 1)
+    int32_t rows_per_plane;      // rows of X vertices in one plane (st[0] / X)
+};
+
+template <int NDIM, bool MINMODE>
+__global__ __launch_bounds__(256) void k_classify_slab(const uint32_t* __restrict__ keys, Grid g, LinkTable t,
+                                                       SlabArgs a, int32_t* __restrict__ lab,
+                                                       int32_t* __restrict__ ptr, uint64_t* __restrict__ mmask,
+                                                       uint64_t* __restrict__ smask)
+{
+    constexpr int K = Rows<NDIM>::K;
+    constexpr Rows<NDIM> R = make_rows_ce<NDIM>();
+    constexpr int S = slab_size<NDIM>();
+    constexpr int PER = (S + 255) / 256;
+    static_assert(slab_inner<NDIM>() == 256, "one interior vertex per thread");
+    static_assert(slab_e<NDIM>(NDIM - 1) == 32, "half a wave per row of the tile");
+    // halo index of interior position (0,..,0), the smallest a row may reach
+    constexpr int B = [] {
+        int b = 0;
+        for (int i = 1; i < NDIM; ++i) b += slab_hs<NDIM>(i);
+        return b;
+    }();
+    __shared__ uint32_t s_ring[3 * S];
+    __shared__ int32_t s_glin[K];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < K; i += blockDim.x) s_glin[i] = t.lin[i];
+
+    int rest = blockIdx.x;
+    const int zb = rest % a.zblocks;
+    rest /= a.zblocks;
+    int t0[NDIM];  // first coordinate of the tile along axes 1..n-1
+#pragma unroll
+    for (int i = NDIM - 1; i >= 1; --i) {
+        const int q = rest % a.nt[i];
+        rest /= a.nt[i];
+        t0[i] = q * slab_e<NDIM>(i);
+    }
+    const int z0 = zb * a.zc;
+    const int z1 = min(z0 + a.zc, g.dims[0]);
+
+    // the halo positions this thread loads: offset inside a plane of the
+    // grid, or -1 outside the grid
+    int goff[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        int h = tid + 256 * k;
+        bool in = h < S;
+        int off = 0;
+#pragma unroll
+        for (int i = NDIM - 1; i >= 1; --i) {
+            const int he = slab_e<NDIM>(i) + 2;
+            const int c = t0[i] + h % he - 1;
+            h /= he;
+            in &= (c >= 0) & (c < g.dims[i]);
+            off += c * a.st[i];
+        }
+        goff[k] = in ? off : -1;
+    }
+    // this thread's interior vertex: its halo index minus B, and its offset
+    // inside a plane of the grid
+    int center = 0, vin = 0;
+    bool mine = true;
+    {
+        int r = tid;
+#pragma unroll
+        for (int i = NDIM - 1; i >= 1; --i) {
+            const int e = r % slab_e<NDIM>(i);
+            r /= slab_e<NDIM>(i);
+            const int c = t0[i] + e;
+            mine &= c < g.dims[i];
+            center += e * slab_hs<NDIM>(i);
+            vin += c * a.st[i];
+        }
+    }
+    const int X = g.dims[NDIM - 1];
+    const int x = t0[NDIM - 1] + (tid & 31);
+    const int rin = mine ? (vin - x) / X : 0;  // row of the vertex inside its plane
+    const int XW = (X + 63) >> 6;
+
+    uint32_t r[PER];
+    auto fetch = [&](int z) {
+        const bool zok = z >= 0 && z < g.dims[0];
+        const int zoff = zok ? z * a.st[0] : 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const bool ok = zok && goff[k] >= 0;
+            const uint32_t u = keys[ok ? zoff + goff[k] : 0];
+            r[k] = ok ? u : 0u;
+        }
+    };
+    auto put = [&](int slot) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k)
+            if (tid + 256 * k < S) s_ring[slot * S + tid + 256 * k] = r[k];
+    };
+    fetch(z0 - 1);
+    put(0);
+    fetch(z0);
+    put(1);
+    fetch(z0 + 1);
+    int sp = 0;  // slot of plane z-1; plane z is in the next slot, z+1 in the one after
+    for (int z = z0; z < z1; ++z) {
+        const int s1 = sp == 2 ? 0 : sp + 1;
+        const int s2 = s1 == 2 ? 0 : s1 + 1;
+        __syncthreads();  // slot s2 (plane z-2) is no longer read
+        put(s2);
+        __syncthreads();
+        if (z + 1 < z1) fetch(z + 2);  // in flight during this plane
+
+        const int v = z * a.st[0] + vin;
+        bool is_max = false, is_sad = false;
+        if (mine) {
+            const uint32_t* p0 = s_ring + sp * S + center;
+            const uint32_t* p1 = s_ring + s1 * S + center;
+            const uint32_t* p2 = s_ring + s2 * S + center;
+            const uint32_t uv = p1[B];
+            Mask<NDIM> up = 0;
+            uint32_t best_u = 0;
+            int best_j = -1;
+            auto visit = [&](int j) {
+                int d = B;
+#pragma unroll
+                for (int i = 1; i < NDIM; ++i) d += R.d[j][i] * slab_hs<NDIM>(i);
+                const uint32_t* p = R.d[j][0] < 0 ? p0 : R.d[j][0] > 0 ? p2 : p1;
+                const uint32_t u = p[d];
+                const bool above = row_wins_tie<MINMODE>(j, K) ? (u >= uv) : (u > uv);
+                up |= Mask<NDIM>(above) << j;
+                if (u >= best_u) {  // rows outside the grid (key 0) lose to v itself below
+                    best_u = u;
+                    best_j = j;
+                }
+            };
+            auto self = [&]() {
+                if (uv >= best_u) {
+                    best_u = uv;
+                    best_j = -1;
+                }
+            };
+            if (!MINMODE) {
+#pragma unroll
+                for (int j = 0; j < K / 2; ++j) visit(j);
+                self();
+#pragma unroll
+                for (int j = K / 2; j < K; ++j) visit(j);
+            } else {
+#pragma unroll
+                for (int j = K - 1; j >= K / 2; --j) visit(j);
+                self();
+#pragma unroll
+                for (int j = K / 2 - 1; j >= 0; --j) visit(j);
+            }
+            is_max = up == 0;
+            if (!is_max) is_sad = !link_connected<NDIM>(up);
+            const int best = best_j < 0 ? v : v + s_glin[best_j];
+            lab[v] = is_max ? v : -(best + 1);
+            if (ptr) ptr[v] = best;
+        }
+        const int64_t word = mine ? (int64_t)(z * a.rows_per_plane + rin) * XW + (x >> 6) : -1;
+        mask_or(is_max, word, x & 63, mmask);
+        mask_or(is_sad, word, x & 63, smask);
+        sp = s1;
+    }
 }
 
 template <int NDIM, bool MINMODE>
@@ -243,9 +448,29 @@ static void launch_classify_t(const float* f, const Grid& g, const LinkTable& t,
     const int64_t kwant = ((int64_t)g.N + 255) / 256;
     const int kblocks = (int)(kwant < 8192 ? kwant : 8192);
     hipLaunchKernelGGL(k_keys<MINMODE>, dim3(kblocks), dim3(256), 0, s, f, g.N, w.keys, w.ctr);
-    const int blocks = (int)((g.N + 255) / 256);
-    hipLaunchKernelGGL((k_classify_generic<NDIM, MINMODE>), dim3(blocks), dim3(256), 0, s, w.keys, g, t, lab, ptr,
-                       w.mmask, w.smask);
+    if constexpr (NDIM == 4 || NDIM == 5) {
+        SlabArgs a{};
+        a.st[NDIM - 1] = 1;
+        for (int i = NDIM - 2; i >= 0; --i) a.st[i] = a.st[i + 1] * g.dims[i + 1];
+        int64_t tiles = 1;
+        for (int i = 1; i < NDIM; ++i) {
+            a.nt[i] = (g.dims[i] + slab_e<NDIM>(i) - 1) / slab_e<NDIM>(i);
+            tiles *= a.nt[i];
+        }
+        // about 8192 blocks, each over as many planes as that allows
+        const int64_t D0 = g.dims[0];
+        const int64_t zc = std::min<int64_t>(D0, std::max<int64_t>(1, (D0 * tiles + 8191) / 8192));
+        a.zc = (int)zc;
+        a.zblocks = (int)((D0 + zc - 1) / zc);
+        a.rows_per_plane = a.st[0] / g.dims[NDIM - 1];
+        const int64_t blocks = tiles * a.zblocks;
+        hipLaunchKernelGGL((k_classify_slab<NDIM, MINMODE>), dim3((unsigned)blocks), dim3(256), 0, s, w.keys, g, t,
+                           a, lab, ptr, w.mmask, w.smask);
+    } else {
+        const int blocks = (int)((g.N + 255) / 256);
+        hipLaunchKernelGGL((k_classify_generic<NDIM, MINMODE>), dim3(blocks), dim3(256), 0, s, w.keys, g, t, lab,
+                           ptr, w.mmask, w.smask);
+    }
 }
 
 hipError_t launch_classify(const float* f, const Grid& g, const LinkTable& t, bool minima, int32_t* lab,
