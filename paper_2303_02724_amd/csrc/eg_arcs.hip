@@ -26,6 +26,7 @@
 
 #include "eg_internal.h"
 #include "eg_rows.h"
+#include "eg_link.h"
 
 namespace eg {
 
@@ -257,18 +258,20 @@ __global__ __launch_bounds__(256) void k_mask_emit(Sel sel)
 // The neighbourhood of saddle v: order keys (0 outside the grid, below every
 // vertex) and linear offsets of the K Freudenthal rows, and the upper-link
 // mask (Alg. 1, Sec. 3.3).
-// From 4D on (30 to 126 rows) only the mask is kept: holding every row's key
-// and offset in registers costs more registers, and waves, than reloading the
-// few keys of one component when its rep is sought (they are in cache).
+// From 4D on (30 to 126 rows) the rows' offsets come from a per-block table
+// in LDS when a rep is found (only the rep's offset is needed).  In 6D (126
+// rows) the keys are not kept either: holding them costs more registers, and
+// waves, than reloading the few keys of one component when its rep is sought.
 template <int NDIM>
-constexpr bool kLazyNbhd = NDIM >= 4;
+constexpr bool kLazyNbhd = NDIM >= 6;
+template <int NDIM>
+constexpr bool kOffsInLds = NDIM >= 4;
 
 template <int NDIM, bool MINMODE>
 struct Nbhd {
     static constexpr int K = Rows<NDIM>::K;
-    static constexpr int KS = kLazyNbhd<NDIM> ? 1 : K;
-    uint32_t us[KS];
-    int offs[KS];
+    uint32_t us[kLazyNbhd<NDIM> ? 1 : K];
+    int offs[kOffsInLds<NDIM> ? 1 : K];
     Mask<NDIM> up;
     EG_GPTR(const uint32_t) keys;  // the order keys (lazy neighbourhoods)
 };
@@ -316,11 +319,17 @@ __device__ __forceinline__ void load_nbhd(const ArcArgs& A, int v, Nbhd<NDIM, MI
                 off += d * st[i];
             }
         }
-        const uint32_t u = !in ? 0u : stored ? A.keys[v + off] : mode_key<MINMODE>(A.f[v + off]);
-        if constexpr (!kLazyNbhd<NDIM>) {
-            nb.offs[j] = off;
-            nb.us[j] = u;
+        uint32_t u;
+        if constexpr (NDIM >= 4 && !kLazyNbhd<NDIM>) {
+            // no branch around the load: every row's load is in flight at once
+            const int w = in ? v + off : v;
+            const uint32_t x = stored ? A.keys[w] : mode_key<MINMODE>(A.f[w]);
+            u = in ? x : 0u;
+        } else {
+            u = !in ? 0u : stored ? A.keys[v + off] : mode_key<MINMODE>(A.f[v + off]);
         }
+        if constexpr (!kLazyNbhd<NDIM>) nb.us[j] = u;
+        if constexpr (!kOffsInLds<NDIM>) nb.offs[j] = off;
         const bool wins_tie = (j >= K / 2) != MINMODE;
         nb.up |= Mask<NDIM>(wins_tie ? (u >= uv) : (u > uv)) << j;
     }
@@ -328,16 +337,21 @@ __device__ __forceinline__ void load_nbhd(const ArcArgs& A, int v, Nbhd<NDIM, MI
 
 // Calls f(rep) for every upper-link component of saddle v, with rep the
 // component's highest vertex (UpperLinkRep, Sec. 3.4), found by scanning in
-// the order in which the later of two equal vertices wins.  Components come
-// from a bit-parallel BFS over the link edges seeded at the lowest remaining
-// row; rows are in linear-index order, so components come in ascending order
-// of their smallest vertex.
+// the order in which the later of two equal vertices wins.  Components are
+// grown from the lowest remaining row (a bit-parallel BFS over the link
+// edges; from 4D on by set algebra on the link's rows, eg_link.h); rows are
+// in linear-index order, so components come in ascending order of their
+// smallest vertex.
 template <int NDIM, bool MINMODE, class F>
 __device__ __forceinline__ void for_each_rep(int v, const Nbhd<NDIM, MINMODE>& nb, const Mask<NDIM>* s_adj, F&& f)
 {
     constexpr int K = Rows<NDIM>::K;
     for (Mask<NDIM> rem = nb.up; rem != 0;) {
-        const Mask<NDIM> comp = closure(rem & (~rem + 1), rem, s_adj);
+        Mask<NDIM> comp;
+        if constexpr (NDIM >= 4)
+            comp = link_component<NDIM>(rem);
+        else
+            comp = closure(rem & (~rem + 1), rem, s_adj);
         rem &= ~comp;
         uint32_t best_u = 0;
         int best_off = 0;
@@ -355,6 +369,17 @@ __device__ __forceinline__ void for_each_rep(int v, const Nbhd<NDIM, MINMODE>& n
                     best_off = off;
                 }
             }
+        } else if constexpr (kOffsInLds<NDIM>) {
+            int best_j = 0;
+#pragma unroll
+            for (int s = 0; s < K; ++s) {
+                const int j = MINMODE ? K - 1 - s : s;
+                if ((uint32_t)(comp >> j) & 1u && nb.us[j] >= best_u) {
+                    best_u = nb.us[j];
+                    best_j = j;
+                }
+            }
+            best_off = row_offsets<NDIM>()[best_j];
         } else {
 #pragma unroll
             for (int s = 0; s < K; ++s) {
@@ -446,9 +471,11 @@ template <int NDIM>
 __device__ __forceinline__ void load_adj(const ArcArgs& A, Mask<NDIM>* s_adj)
 {
     constexpr int K = Rows<NDIM>::K;
-    const Mask<NDIM>* t = adj_table<NDIM>();
-    for (int i = threadIdx.x; i < K; i += blockDim.x) s_adj[i] = t[i];
-    if constexpr (kLazyNbhd<NDIM>) {
+    if constexpr (NDIM < 4) {  // from 4D on components come from set algebra
+        const Mask<NDIM>* t = adj_table<NDIM>();
+        for (int i = threadIdx.x; i < K; i += blockDim.x) s_adj[i] = t[i];
+    }
+    if constexpr (kOffsInLds<NDIM>) {
         constexpr Rows<NDIM> R = make_rows_ce<NDIM>();
         int* s_off = row_offsets<NDIM>();
         int st[NDIM];

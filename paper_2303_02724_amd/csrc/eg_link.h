@@ -73,16 +73,29 @@ __host__ __device__ inline typename SubsetWord<NDIM>::type complements(typename 
         return __builtin_bitreverse32(a) >> (32 - (1 << NDIM));
 }
 
-// Whether the rows in `up` (a non-empty mask over the 2(2^n - 1) rows) form
-// one connected piece of the link.
+// the highest set bit of a non-empty word
+__host__ __device__ inline uint32_t top_bit(uint32_t a) { return 1u << (31 - __builtin_clz(a)); }
+__host__ __device__ inline uint64_t top_bit(uint64_t a) { return 1ull << (63 - __builtin_clzll(a)); }
+
+// Rows of the link as the two subset words: ml holds the b of the rows -b,
+// mu the a of the rows a.
 template <int NDIM, class M>
-__host__ __device__ inline bool link_connected(M up)
+__host__ __device__ inline void to_subsets(M rows, typename SubsetWord<NDIM>::type& ml,
+                                           typename SubsetWord<NDIM>::type& mu)
 {
     using W = typename SubsetWord<NDIM>::type;
     constexpr int H = (1 << NDIM) - 1;  // rows per half
-    const W ml = complements<NDIM>((W)(up & ((M(1) << H) - 1)));  // the b of the rows -b
-    const W mu = (W)(up >> H) << 1;                               // the a of the rows a
-    W cl = ml & (~ml + 1), cu = ml ? W(0) : mu & (~mu + 1);       // one row
+    ml = complements<NDIM>((W)(rows & ((M(1) << H) - 1)));
+    mu = (W)(rows >> H) << 1;
+}
+
+// The component, within the rows ml/mu, of the lowest row among them: in
+// place of the seed (cl, cu), grown one edge per round until it stops.
+template <int NDIM, class W>
+__host__ __device__ inline void grow(W ml, W mu, W& cl, W& cu)
+{
+    cl = ml ? top_bit(ml) : W(0);  // the lowest row of the -b half has the largest b
+    cu = ml ? W(0) : mu & (~mu + 1);
     while (true) {
         const W nu = (supersets<NDIM>(cu) | subsets<NDIM>(cu | complements<NDIM>(cl))) & mu;
         const W nl = (supersets<NDIM>(cl) | subsets<NDIM>(cl | complements<NDIM>(cu))) & ml;
@@ -90,7 +103,30 @@ __host__ __device__ inline bool link_connected(M up)
         cu = nu;
         cl = nl;
     }
+}
+
+// Whether the rows in `up` (a non-empty mask over the 2(2^n - 1) rows) form
+// one connected piece of the link.
+template <int NDIM, class M>
+__host__ __device__ inline bool link_connected(M up)
+{
+    typename SubsetWord<NDIM>::type ml, mu, cl, cu;
+    to_subsets<NDIM>(up, ml, mu);
+    grow<NDIM>(ml, mu, cl, cu);
     return cu == mu && cl == ml;
+}
+
+// The component of the lowest row of `rows` (a non-empty mask) within
+// `rows`, as a row mask.
+template <int NDIM, class M>
+__host__ __device__ inline M link_component(M rows)
+{
+    using W = typename SubsetWord<NDIM>::type;
+    constexpr int H = (1 << NDIM) - 1;
+    W ml, mu, cl, cu;
+    to_subsets<NDIM>(rows, ml, mu);
+    grow<NDIM>(ml, mu, cl, cu);
+    return M(complements<NDIM>(cl)) | (M(cu >> 1) << H);
 }
 
 }  // namespace eg

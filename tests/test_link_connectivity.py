@@ -4,7 +4,8 @@ it is checked, on the host, against the definition: the link vertices are
 the rows of Alg. 1 (the non-zero offsets in {0,1}^n or {0,-1}^n), two of
 them joined iff their difference is again such an offset, and a mask is
 connected iff a breadth-first search from one of its rows reaches all of
-them.  Masks: every mask for n <= 3, random masks of every density, and
+them; the component that the stage (d) kernels take apart is the one the
+search reaches from the lowest row.  Masks: every mask for n <= 3, random masks of every density, and
 the upper links of every interior vertex of random fields (n = 2..6)."""
 import itertools
 import os
@@ -34,8 +35,9 @@ def adjacency(n):
     return nz & (((diff >= 0) & (diff <= 1)).all(-1) | ((diff <= 0) & (diff >= -1)).all(-1))
 
 
-def connected(n, masks):
-    """BFS from the lowest row of each mask, all masks at once."""
+def component(n, masks):
+    """BFS from the lowest row of each mask, all masks at once: the rows
+    reached."""
     A = adjacency(n).astype(np.float32)
     first = np.argmax(masks, axis=1)
     comp = np.zeros_like(masks)
@@ -43,7 +45,7 @@ def connected(n, masks):
     while True:
         grown = comp | (((comp.astype(np.float32) @ A) > 0) & masks)
         if np.array_equal(grown, comp):
-            return (comp == masks).all(1)
+            return comp
         comp = grown
 
 
@@ -89,15 +91,22 @@ def checker(tmp_path_factory):
 def test_link_connected_matches_bfs(checker, n):
     rng = np.random.default_rng(n)
     ms = masks_for(n, rng)
-    want = connected(n, ms)
-    w = (ms.astype(object) * (1 << np.arange(ms.shape[1], dtype=object))).sum(1)
+    comp = component(n, ms)
+    want = (comp == ms).all(1)
+    bits = 1 << np.arange(ms.shape[1], dtype=object)
+    w = (ms.astype(object) * bits).sum(1)
+    wc = (comp.astype(object) * bits).sum(1)
     lines = "".join(f"{n} {int(x) >> 64:x} {int(x) & ((1 << 64) - 1):x}\n" for x in w)
     r = subprocess.run([checker], input=lines, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
-    got = np.array([c == "1" for c in r.stdout.split()])
-    assert got.shape == want.shape
+    out = r.stdout.split()
+    got = np.array([c == "1" for c in out[0::3]])
+    got_comp = np.array([(int(h, 16) << 64) | int(l, 16) for h, l in zip(out[1::3], out[2::3])], dtype=object)
+    assert got.shape == want.shape and got_comp.shape == wc.shape
     bad = np.flatnonzero(got != want)
-    assert bad.size == 0, f"n={n}: {bad.size} of {len(ms)} masks differ, first {w[bad[0]]:#x}"
+    assert bad.size == 0, f"n={n}: connectivity of {bad.size} of {len(ms)} masks differs, first {w[bad[0]]:#x}"
+    bad = np.flatnonzero(got_comp != wc)
+    assert bad.size == 0, f"n={n}: component of {bad.size} of {len(ms)} masks differs, first {w[bad[0]]:#x}"
     # both kinds occur (except n = 1, where a single row is always connected)
     if n >= 2:
         assert want.any() and (~want).any()
