@@ -1,12 +1,12 @@
 // eg_classify.hip -- per-vertex classification, labels and saddle reps.
 //
-// k_classify_generic  stages (a) and (c) of the method for n = 1 and 6: one
+// k_classify_generic  stages (a) and (c) of the method for n = 1: one
 //   thread per vertex reads its closed neighbourhood, forms the upper-link
 //   mask (Sec. 3.3), the steepest-ascent pointer (highest upper-link vertex,
 //   Sec. 3.3) and decides maximum (empty upper link) / saddle (>= 2
 //   components, Table 1) by set algebra on the link's rows (eg_link.h).
-// k_classify_slab  the same for n = 4 and 5, reading the neighbourhood from
-//   planes of keys staged in LDS.
+// k_classify_slab  the same for n = 4, 5 and 6, reading the neighbourhood
+//   from planes of keys staged in LDS.
 // k_exit_*, k_final  stage (b): pointer jumping until every vertex names its
 //   maximum (the end of the walk of Alg. 2).
 #include "eg_internal.h"
@@ -29,9 +29,9 @@ hipError_t launch_init(uint32_t* ctr, int32_t* header, hipStream_t s)
 }
 
 // Visit the closed neighbourhood of v in the order in which later vertices
-// win ties; fills the upper-link mask and the steepest-ascent target.  Below
-// 6D the rows are unrolled, one load per row under the row's own branch; a
-// row's linear offset and the boundary bits that rule it out follow from the
+// win ties; fills the upper-link mask and the steepest-ascent target.  The
+// rows are unrolled, one load per row under the row's own branch; a row's
+// linear offset and the boundary bits that rule it out follow from the
 // compile-time rows and the grid strides st[] (uniform, scalar work).
 template <int NDIM, bool MINMODE>
 __device__ __forceinline__ void scan_unrolled(const uint32_t* __restrict__ keys, const int* st, int v,
@@ -78,54 +78,6 @@ __device__ __forceinline__ void scan_unrolled(const uint32_t* __restrict__ keys,
         self();
 #pragma unroll
         for (int j = K / 2 - 1; j >= 0; --j) visit(j);
-    }
-}
-
-// The same for 6D (126 rows): unrolled, the rows' offsets and boundary bits
-// would not fit the scalar registers, and the loads would run one after
-// another.  Here rows go eight at a time: their keys are loaded without branches (a row outside
-// the grid reads v's own key and then counts as key 0, below every vertex),
-// so the eight loads are in flight together, while the chunk loop itself
-// stays rolled to keep registers, and with them waves, free.  Row offsets and
-// boundary bits come from LDS (s_lin, s_forb).
-template <int NDIM, bool MINMODE>
-__device__ __forceinline__ void scan_chunked(const uint32_t* __restrict__ keys, const int32_t* s_lin,
-                                             const uint32_t* s_forb, int v, uint32_t bits, uint32_t uv,
-                                             Mask<NDIM>& up, int& best)
-{
-    constexpr int K = 2 * ((1 << NDIM) - 1);
-    constexpr int CH = K < 8 ? K : 8;
-    uint32_t best_u = 0;
-    best = v;
-#pragma unroll 1
-    for (int c0 = 0; c0 < K; c0 += CH) {
-        uint32_t us[CH];
-        int lin[CH];
-#pragma unroll
-        for (int s = 0; s < CH; ++s) {
-            const int idx = c0 + s;
-            const int j = idx < K ? (MINMODE ? K - 1 - idx : idx) : 0;
-            const bool in = idx < K && (bits & s_forb[j]) == 0;
-            lin[s] = s_lin[j];
-            const uint32_t u = keys[in ? v + lin[s] : v];
-            us[s] = in ? u : 0u;
-        }
-#pragma unroll
-        for (int s = 0; s < CH; ++s) {
-            const int idx = c0 + s;
-            if (idx == K / 2 && uv >= best_u) {  // v itself sits between the two halves
-                best_u = uv;
-                best = v;
-            }
-            const int j = MINMODE ? K - 1 - idx : idx;
-            const uint32_t u = us[s];
-            const bool above = row_wins_tie<MINMODE>(j, K) ? (u >= uv) : (u > uv);
-            if (above) up |= Mask<NDIM>(1) << j;
-            if (u != 0 && u >= best_u) {
-                best_u = u;
-                best = v + lin[s];
-            }
-        }
     }
 }
 
@@ -192,18 +144,6 @@ __global__ __launch_bounds__(256) void k_classify_generic(const uint32_t* __rest
                                                           int32_t* __restrict__ lab, int32_t* __restrict__ ptr,
                                                           uint64_t* __restrict__ mmask, uint64_t* __restrict__ smask)
 {
-    constexpr int K = 2 * ((1 << NDIM) - 1);
-    constexpr bool chunked = NDIM >= 6;
-    __shared__ int32_t s_lin[chunked ? K : 1];
-    __shared__ uint32_t s_forb[chunked ? K : 1];
-    if constexpr (chunked) {  // a runtime index into the table, only where it is used
-        for (int i = threadIdx.x; i < K; i += blockDim.x) {
-            s_lin[i] = t.lin[i];
-            s_forb[i] = t.forb[i];
-        }
-        __syncthreads();
-    }
-
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     bool is_max = false, is_sad = false;
     if (v < g.N) {
@@ -211,15 +151,11 @@ __global__ __launch_bounds__(256) void k_classify_generic(const uint32_t* __rest
         const uint32_t uv = keys[v];
         Mask<NDIM> up = 0;
         int best;
-        if constexpr (chunked) {
-            scan_chunked<NDIM, MINMODE>(keys, s_lin, s_forb, v, bits, uv, up, best);
-        } else {
-            int st[NDIM];
-            st[NDIM - 1] = 1;
+        int st[NDIM];
+        st[NDIM - 1] = 1;
 #pragma unroll
-            for (int i = NDIM - 2; i >= 0; --i) st[i] = st[i + 1] * g.dims[i + 1];
-            scan_unrolled<NDIM, MINMODE>(keys, st, v, bits, uv, up, best);
-        }
+        for (int i = NDIM - 2; i >= 0; --i) st[i] = st[i + 1] * g.dims[i + 1];
+        scan_unrolled<NDIM, MINMODE>(keys, st, v, bits, uv, up, best);
         is_max = up == 0;
         if (!is_max) is_sad = !link_connected<NDIM>(up);
         lab[v] = is_max ? v : -(best + 1);  // final label, or "same as best"
@@ -233,14 +169,15 @@ __global__ __launch_bounds__(256) void k_classify_generic(const uint32_t* __rest
     mask_or(is_sad, word, x & 63, smask);
 }
 
-// ------------------------------------------------------- 4D and 5D slab tiles
+// -------------------------------------------------------- 4D-6D slab tiles
 //
-// k_classify_slab  the same outputs as k_classify_generic for n = 4 and 5,
+// k_classify_slab  the same outputs as k_classify_generic for n = 4, 5 and 6,
 //   with the neighbourhood read from LDS instead of through the caches (62
-//   gathers per vertex in 5D leave the generic kernel bound by the memory
-//   pipeline, not by arithmetic).  A block owns a tile of the hyperplanes
-//   orthogonal to axis 0 (2x4x32 vertices in 4D, 2x2x2x32 in 5D, one per
-//   thread) and a run of zc consecutive planes along axis 0.  It keeps three
+//   gathers per vertex in 5D, 126 in 6D, leave a kernel that reads them from
+//   memory bound by the memory pipeline, not by arithmetic).  A block owns a
+//   tile of the hyperplanes orthogonal to axis 0 (2x4x32 vertices in 4D,
+//   2x2x2x32 in 5D, 2x2x2x2x16 in 6D, one per thread) and a run of zc
+//   consecutive planes along axis 0.  It keeps three
 //   consecutive planes of the tile plus a one-vertex halo in a ring in LDS
 //   (positions outside the grid hold key 0, below every vertex, so every row
 //   of the table may be read), and slides it along axis 0: while one plane is
@@ -248,7 +185,7 @@ __global__ __launch_bounds__(256) void k_classify_generic(const uint32_t* __rest
 template <int NDIM>
 __host__ __device__ constexpr int slab_e(int i)  // interior extent along axis i (1..n-1)
 {
-    return i == NDIM - 1 ? 32 : (NDIM == 4 && i == 2) ? 4 : 2;
+    return i == NDIM - 1 ? (NDIM == 6 ? 16 : 32) : (NDIM == 4 && i == 2) ? 4 : 2;
 }
 template <int NDIM>
 __host__ __device__ constexpr int slab_hs(int i)  // LDS stride of axis i in a halo plane
@@ -288,8 +225,9 @@ __global__ __launch_bounds__(256) void k_classify_slab(const uint32_t* __restric
     constexpr Rows<NDIM> R = make_rows_ce<NDIM>();
     constexpr int S = slab_size<NDIM>();
     constexpr int PER = (S + 255) / 256;
+    constexpr int EX = slab_e<NDIM>(NDIM - 1);
     static_assert(slab_inner<NDIM>() == 256, "one interior vertex per thread");
-    static_assert(slab_e<NDIM>(NDIM - 1) == 32, "half a wave per row of the tile");
+    static_assert(64 % EX == 0, "a wave holds whole rows of the tile");
     // halo index of interior position (0,..,0), the smallest a row may reach
     constexpr int B = [] {
         int b = 0;
@@ -349,7 +287,7 @@ __global__ __launch_bounds__(256) void k_classify_slab(const uint32_t* __restric
         }
     }
     const int X = g.dims[NDIM - 1];
-    const int x = t0[NDIM - 1] + (tid & 31);
+    const int x = t0[NDIM - 1] + tid % EX;
     const int rin = mine ? (vin - x) / X : 0;  // row of the vertex inside its plane
     const int XW = (X + 63) >> 6;
 
@@ -448,7 +386,7 @@ static void launch_classify_t(const float* f, const Grid& g, const LinkTable& t,
     const int64_t kwant = ((int64_t)g.N + 255) / 256;
     const int kblocks = (int)(kwant < 8192 ? kwant : 8192);
     hipLaunchKernelGGL(k_keys<MINMODE>, dim3(kblocks), dim3(256), 0, s, f, g.N, w.keys, w.ctr);
-    if constexpr (NDIM == 4 || NDIM == 5) {
+    if constexpr (NDIM >= 4) {
         SlabArgs a{};
         a.st[NDIM - 1] = 1;
         for (int i = NDIM - 2; i >= 0; --i) a.st[i] = a.st[i + 1] * g.dims[i + 1];
