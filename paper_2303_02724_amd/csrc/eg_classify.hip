@@ -328,27 +328,32 @@ __global__ __launch_bounds__(256) void k_classify_slab(const uint32_t* __restric
             const uint32_t* p1 = s_ring + s1 * S + center;
             const uint32_t* p2 = s_ring + s2 * S + center;
             const uint32_t uv = p1[B];
-            Mask<NDIM> up = 0;
-            uint32_t best_u = 0;
-            int best_j = -1;
-            auto visit = [&](int j) {
+            auto key = [&](int j) {
                 int d = B;
 #pragma unroll
                 for (int i = 1; i < NDIM; ++i) d += R.d[j][i] * slab_hs<NDIM>(i);
                 const uint32_t* p = R.d[j][0] < 0 ? p0 : R.d[j][0] > 0 ? p2 : p1;
-                const uint32_t u = p[d];
+                return p[d];
+            };
+            // the upper-link mask, and the highest key of the closed
+            // neighbourhood (rows outside the grid hold key 0 < uv)
+            Mask<NDIM> up = 0;
+            uint32_t top = uv;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const uint32_t u = key(j);
                 const bool above = row_wins_tie<MINMODE>(j, K) ? (u >= uv) : (u > uv);
                 up |= Mask<NDIM>(above) << j;
-                if (u >= best_u) {  // rows outside the grid (key 0) lose to v itself below
-                    best_u = u;
-                    best_j = j;
-                }
+                top = max(top, u);
+            }
+            // the steepest target: the last vertex holding `top` in the order
+            // in which later vertices win ties (v itself between the halves)
+            int best_j = -1;
+            auto visit = [&](int j) {
+                if (key(j) == top) best_j = j;
             };
             auto self = [&]() {
-                if (uv >= best_u) {
-                    best_u = uv;
-                    best_j = -1;
-                }
+                if (uv == top) best_j = -1;
             };
             if (!MINMODE) {
 #pragma unroll

@@ -10,9 +10,9 @@
 // So a half of an upper-link mask is a 2^n-bit word (bit s for subset s), and
 // the neighbours of a set of rows follow from its superset and subset
 // closures (n shift-and-mask steps each) and from complementing every subset
-// (a reversal of the word).  The component of one row grows by one edge per
-// round, in registers; a saddle (Table 1) is an upper link that the component
-// of any one of its rows does not cover.
+// (a reversal of the word).  The component of one row grows in registers,
+// one closure after another until it stops; a saddle (Table 1) is an upper
+// link that the component of any one of its rows does not cover.
 //
 // Row order is the one of the row table (eg_rows.h): all offsets of
 // {-1,0,1}^n in lexicographic order, axis 0 first, so the first 2^n - 1 rows
@@ -97,11 +97,18 @@ __host__ __device__ inline void grow(W ml, W mu, W& cl, W& cu)
     cl = ml ? top_bit(ml) : W(0);  // the lowest row of the -b half has the largest b
     cu = ml ? W(0) : mu & (~mu + 1);
     while (true) {
-        const W nu = (supersets<NDIM>(cu) | subsets<NDIM>(cu | complements<NDIM>(cl))) & mu;
-        const W nl = (supersets<NDIM>(cl) | subsets<NDIM>(cl | complements<NDIM>(cu))) & ml;
-        if (nu == cu && nl == cl) break;
+        // each closure starts from the rows the previous one reached, so a
+        // round follows several edges (superset, then subset or across, ...)
+        W nu = supersets<NDIM>(cu) & mu;
+        nu = subsets<NDIM>(nu | complements<NDIM>(cl)) & mu;
+        W nl = supersets<NDIM>(cl) & ml;
+        nl = subsets<NDIM>(nl | complements<NDIM>(nu)) & ml;
+        // stop when nothing grows, or at once when every row is reached (the
+        // usual case: most upper links are connected)
+        const bool done = (nu == cu && nl == cl) || (nu == mu && nl == ml);
         cu = nu;
         cl = nl;
+        if (done) break;
     }
 }
 
