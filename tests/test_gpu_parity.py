@@ -76,6 +76,19 @@ def test_gaussian_mixture_4d():
         assert_same(gpu_graph(f, minima), O.extremum_graph(f, minima), KEYS + ["ptr"], "4d")
 
 
+@pytest.mark.parametrize("shape", [(301, 20, 20, 40), (45, 16, 16, 16, 33), (21, 8, 8, 8, 8, 20)])
+def test_slab_tiles_several_planes_per_block(shape):
+    """4D-6D grids large enough that each block of the slab classification
+    runs over several planes along axis 0 (4, 6 and 2), the last block over
+    fewer (1, 3 and 1), with ragged tiles along the other axes; white noise
+    with ties (about 12 % saddles), both graphs."""
+    f = W.random_field(shape, 90 + len(shape), "ties5")
+    for minima in (False, True):
+        ctx = f"slab {shape} minima={minima}"
+        print(ctx, flush=True)
+        assert_same(gpu_graph(f, minima), O.extremum_graph(f, minima), KEYS + ["ptr"], ctx)
+
+
 @pytest.mark.parametrize("shape", [(300,), (40, 50), (9, 10, 11), (4, 5, 6, 7), (3, 4, 5, 4, 3)])
 def test_constant_and_ramp(shape):
     const = np.full(shape, 1.5, np.float32)
