@@ -224,15 +224,20 @@ eg_status eg_paths(const float* field, int ndim, const int64_t* dims, void* stre
  * another, as in the paper's serial implementation.
  *
  *   EG_SIMPLIFY_BUNDLE  arc bundling: for every pair of maxima that share
- *                       saddles, the highest shared saddle represents the pair;
- *                       a saddle survives iff it represents one of its pairs.
+ *                       saddles, the highest shared saddle represents the pair
+ *                       and the pair's other saddles are discarded; a saddle
+ *                       survives iff it represents one of its pairs or has
+ *                       fewer than two distinct maxima (no pair shares it).
  *   EG_SIMPLIFY_CANCEL  persistence-directed cancellation: saddles are taken in
- *                       order of cost = height of their lowest maximum - height
- *                       of the saddle (ties: the lower saddle first), costs
- *                       recomputed when a saddle comes up; at cost <= threshold
- *                       the lowest maximum merges into the saddle's highest
- *                       maximum.  A saddle joining k maxima can be cancelled
- *                       k - 1 times.  Applied after bundling when both are set.
+ *                       order of cost = height of the second-highest of their
+ *                       maxima - height of the saddle (for a simple saddle the
+ *                       lower of its two maxima; ties: the lower saddle first),
+ *                       costs recomputed when a saddle comes up: above the
+ *                       threshold it is discarded, above the cost stored at
+ *                       the top of the queue it is queued again, else it is
+ *                       cancelled: every one of its maxima except the highest
+ *                       merges into the highest and the saddle leaves the
+ *                       graph.  Applied after bundling when both are set.
  *
  * Heights are the field values in the graph's order (ties by vertex id),
  * reversed for a minimum graph (flags = EG_MINIMA), passed as doubles (exact
@@ -241,11 +246,15 @@ eg_status eg_paths(const float* field, int ndim, const int64_t* dims, void* stre
  * saddles, CSR arcs of maxima ids) and the field value at every maximum and
  * saddle.  Outputs:
  *   out_offsets [nsad + 1], out_arcs [arc_offsets[nsad]]  the simplified arcs of
- *       every saddle (an empty row for a removed saddle), ascending maxima ids
+ *       every saddle (an empty row for a saddle removed by bundling or
+ *       cancelled), the ascending distinct representatives of its maxima (one
+ *       entry when they all merged into one)
  *   max_rep [nmax]     index of the maximum each maximum merged into (its own
  *                      index if it survives)
  *   pair_saddle, pair_max [arc_offsets[nsad]], pair_cost   the cancellations in
- *                      order: saddle index, maximum index, cost; *n_pairs of them
+ *                      order, one row per merged maximum (saddle index,
+ *                      maximum index, the cancellation's cost; the maxima of
+ *                      one cancellation from the highest down); *n_pairs rows
  * EG_ERR_ARG for NULL pointers, unknown ops, a NaN threshold, unsorted maxima,
  * malformed offsets or an arc to a vertex that is not in maxima.
  */

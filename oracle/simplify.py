@@ -3,7 +3,7 @@ arc bundling and persistence-directed cancellation).
 
 TEST INFRASTRUCTURE ONLY.  Only the tests may use it; the library never does.
 Written for clarity: dictionaries, sets and a binary heap, following the
-steps as the paper describes them.
+steps in the order Sec. 3.5 gives them.
 
 Readings (the paper describes the operations in prose; these are the
 choices written out):
@@ -13,22 +13,28 @@ choices written out):
   reversed.  ``height(v)`` below is the value in the graph's own direction
   (f for the maximum graph, -f for the minimum graph).
 * Arc bundling.  For every pair of maxima that share a saddle, the highest
-  shared saddle represents the pair.  A saddle survives iff it represents at
-  least one pair of its maxima, so every connected pair stays connected.
-  Saddles with fewer than two maxima have no pair and are dropped.
-* Persistence-directed cancellation, threshold t.  A saddle's maxima are
-  the representatives (after earlier merges) of its arcs' maxima; a saddle
-  with fewer than two distinct ones is not a candidate.  cost(s) =
-  height(lowest maximum) - height(s).  Saddles sit in a priority queue
-  ordered by (cost, then the saddle's order); the top is popped, its cost
-  recomputed: not a candidate -> dropped; cost > t -> discarded (costs never
-  fall); cost above the new top's -> reinserted; otherwise cancelled: the
-  lowest maximum m merges into the highest maximum of the saddle (the elder)
-  and the pair (s, m) is recorded.  A saddle with more maxima left after the
-  merge goes back into the queue, so a k-fold saddle can be cancelled k-1
-  times.  At the end, surviving maxima are those never merged; surviving
-  saddles those with at least two distinct maxima, whose arcs are those
-  maxima.
+  shared saddle represents the pair and the other saddles the pair shares
+  are discarded.  A saddle is kept iff it represents at least one pair of its
+  maxima (so every connected pair stays connected), or iff it has fewer than
+  two distinct maxima (then no pair shares it and nothing discards it).
+* Persistence-directed cancellation, threshold t.  The maxima of a saddle
+  are the representatives (after earlier merges) of its arcs' maxima.  The
+  cost of a saddle is height(second-highest of its maxima) - height(saddle):
+  for a simple saddle (two maxima) this is the smaller gap to its two
+  maxima, for a multi-saddle the gap to the second-highest maximum.  A saddle
+  with fewer than two distinct maxima has no cost and cannot be cancelled.
+  The queue starts with every saddle that has a cost, ordered by (cost, then
+  the saddle's order: lower first).  The top is popped and its cost
+  recomputed: no cost -> dropped; cost > t -> discarded; cost greater than
+  the cost stored at the new top of the queue -> reinserted; otherwise the
+  saddle is cancelled: every one of its maxima except the highest (the
+  surviving maximum) merges into the highest, and the saddle leaves the graph.
+  A cancellation is reported as one row (saddle, merged maximum, cost) per
+  merged maximum, the merged maxima from the highest down.
+* Output.  Surviving maxima are those never merged; surviving saddles are the
+  kept saddles that were not cancelled, each with the sorted distinct
+  representatives of its arcs' maxima as its arc row (a single entry when
+  all its maxima merged into one).
 """
 from __future__ import annotations
 
@@ -54,15 +60,18 @@ def bundle(maxima, max_values, saddles, sad_values, arc_offsets, arc_maxima, min
     """Indices (into ``saddles``) of the saddles that survive arc bundling."""
     hs = _heights(sad_values, minima)
     best = {}  # (ma, mb) -> saddle index
+    unshared = []
     for i in range(len(saddles)):
         ms = sorted(set(int(x) for x in arc_maxima[arc_offsets[i]:arc_offsets[i + 1]]))
+        if len(ms) < 2:
+            unshared.append(i)
         for a in range(len(ms)):
             for b in range(a + 1, len(ms)):
                 k = (ms[a], ms[b])
                 j = best.get(k)
                 if j is None or _above(hs[i], int(saddles[i]), hs[j], int(saddles[j]), minima):
                     best[k] = i
-    return sorted(set(best.values()))
+    return sorted(set(best.values()) | set(unshared))
 
 
 def cancel(maxima, max_values, saddles, sad_values, arc_offsets, arc_maxima, threshold, minima=False,
@@ -71,7 +80,7 @@ def cancel(maxima, max_values, saddles, sad_values, arc_offsets, arc_maxima, thr
     input to those saddle indices (e.g. the survivors of bundling).
 
     Returns (surviving maxima, surviving saddle indices, their arc rows,
-    cancelled pairs as (saddle index, maximum, cost) in cancellation order).
+    cancellation rows (saddle index, merged maximum, cost) in order).
     """
     hm = dict(zip((int(m) for m in maxima), _heights(max_values, minima)))
     hs = _heights(sad_values, minima)
@@ -85,15 +94,11 @@ def cancel(maxima, max_values, saddles, sad_values, arc_offsets, arc_maxima, thr
             m = parent[m]
         return m
 
-    def lowest_highest(i):
-        ms = sorted({find(m) for m in arcs[i]})
-        lo = hi = None
-        for m in ms:
-            if lo is None or _above(hm[lo], lo, hm[m], m, minima):
-                lo = m
-            if hi is None or _above(hm[m], m, hm[hi], hi, minima):
-                hi = m
-        return len(ms), lo, hi
+    def maxima_of(i):
+        """Distinct current maxima of saddle i, highest first."""
+        ms = list({find(m) for m in arcs[i]})
+        ms.sort(key=lambda m: (hm[m], -m if minima else m), reverse=True)
+        return ms
 
     def order_key(i):
         # the saddle's rank in the order, for ties in cost: lower saddles first
@@ -101,37 +106,37 @@ def cancel(maxima, max_values, saddles, sad_values, arc_offsets, arc_maxima, thr
         return (hs[i], -s if minima else s)
 
     def entry(i):
-        n, lo, _ = lowest_highest(i)
-        if n < 2:
+        ms = maxima_of(i)
+        if len(ms) < 2:
             return None
-        return (hm[lo] - hs[i], order_key(i), i)
+        return (hm[ms[1]] - hs[i], order_key(i), i)
 
     heap = [e for e in (entry(i) for i in arcs) if e is not None]
     heapq.heapify(heap)
     pairs = []
+    cancelled = set()
     while heap:
         _, _, i = heapq.heappop(heap)
         e = entry(i)
         if e is None:
             continue
-        if e[0] > threshold:
+        cost = e[0]
+        if cost > threshold:
             continue
-        if heap and e[:2] > heap[0][:2]:
+        if heap and cost > heap[0][0]:
             heapq.heappush(heap, e)
             continue
-        _, lo, hi = lowest_highest(i)
-        parent[lo] = hi
-        pairs.append((i, lo, e[0]))
-        e2 = entry(i)
-        if e2 is not None:
-            heapq.heappush(heap, e2)
+        ms = maxima_of(i)
+        for m in ms[1:]:
+            parent[m] = ms[0]
+            pairs.append((i, m, cost))
+        cancelled.add(i)
     surv_max = sorted(m for m in parent if find(m) == m)
     surv_sad, rows = [], []
     for i in sorted(arcs):
-        ms = sorted({find(m) for m in arcs[i]})
-        if len(ms) >= 2:
+        if i not in cancelled:
             surv_sad.append(i)
-            rows.append(ms)
+            rows.append(sorted({find(m) for m in arcs[i]}))
     return surv_max, surv_sad, rows, pairs
 
 
@@ -141,7 +146,8 @@ def superlevel_pairs(f, neighbours, minima=False):
     decreasing order, the elder rule deciding which component dies at a
     merge: a list of (vertex where a component dies, its maximum, persistence).
     ``neighbours(v)`` gives the grid neighbours of v.  Independent of the
-    extremum graph; used to pin ``cancel``."""
+    extremum graph; used to pin ``cancel`` on graphs whose saddles are all
+    simple (there the cancellation order is the elder rule's)."""
     vals = np.asarray(f, dtype=np.float64).reshape(-1)
     h = -vals if minima else vals
     n = vals.size

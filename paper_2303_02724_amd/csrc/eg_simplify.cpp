@@ -5,19 +5,30 @@
 // the grid has vertices, and the cancellations depend on each other.
 //
 //   arc bundling      for every pair of maxima that share saddles, the highest
-//                     shared saddle represents the pair; a saddle survives iff
-//                     it represents at least one of its pairs (connectivity
-//                     between maxima is kept).
+//                     shared saddle represents the pair and the pair's other
+//                     saddles are discarded; a saddle survives iff it
+//                     represents at least one of its pairs, or has fewer than
+//                     two distinct maxima (no pair shares it).
 //   cancellation      persistence-directed: saddles in a priority queue keyed
-//                     by cost = height of the lowest of their maxima - height
-//                     of the saddle (ties: the lower saddle first), costs
-//                     recomputed lazily when a saddle reaches the top; the
-//                     lowest maximum merges into the highest maximum of the
-//                     saddle, which stays queued while it still joins two or
-//                     more maxima.  Costs above the threshold end a saddle.
+//                     by cost = height of the second-highest of their maxima
+//                     - height of the saddle (for a simple saddle the lower of
+//                     its two maxima; ties: the lower saddle first), costs
+//                     recomputed when a saddle reaches the top: above the
+//                     threshold -> discarded; above the cost stored at the
+//                     top of the queue -> reinserted; else cancelled: every
+//                     maximum of the saddle except the highest merges into
+//                     the highest, and the saddle leaves the graph.
 //
 // Heights follow the graph's order: value, ties by vertex id (Sec. 3.3),
 // reversed for a minimum graph.
+//
+// Cost: bundling is linear in the number of (saddle, pair of maxima) records
+// (bucketed by the lower maximum, no comparison sort).  The queue holds the
+// initial entries as one sorted run plus a binary heap of reinserted entries;
+// a saddle with at most two maxima whose initial cost is above the threshold
+// is never queued, since merges only raise such a saddle's maxima and its
+// cost cannot fall back (dropping entries above the threshold never changes a
+// decision about an entry at or below it).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -76,40 +87,71 @@ bool load(const eg_graph_host* g, Graph* G)
     return true;
 }
 
+// Distinct entries of a short row, in place (rows hold at most a few dozen).
+int distinct(int32_t* ms, int n)
+{
+    int k = 0;
+    for (int a = 0; a < n; ++a) {
+        bool seen = false;
+        for (int b = 0; b < k; ++b) seen |= ms[b] == ms[a];
+        if (!seen) ms[k++] = ms[a];
+    }
+    return k;
+}
+
 // Saddles that survive bundling (flags per saddle).
 std::vector<char> bundle(const Graph& G)
 {
-    struct PairRec {
-        uint64_t key;  // (lower maximum index, higher maximum index)
-        int32_t sad;
-    };
-    std::vector<PairRec> recs;
-    std::vector<int32_t> ms;
-    for (size_t i = 0; i < G.sd.size(); ++i) {
-        ms.assign(G.arc.begin() + G.off[i], G.arc.begin() + G.off[i + 1]);
-        std::sort(ms.begin(), ms.end());
-        ms.erase(std::unique(ms.begin(), ms.end()), ms.end());
-        for (size_t a = 0; a < ms.size(); ++a)
-            for (size_t b = a + 1; b < ms.size(); ++b)
-                recs.push_back(PairRec{(uint64_t(uint32_t(ms[a])) << 32) | uint32_t(ms[b]), (int32_t)i});
+    const size_t nsad = G.sd.size(), nmax = G.mx.size();
+    std::vector<char> keep(nsad, 0);
+    std::vector<int32_t> row;
+    // pass 1: pairs per lower maximum index; saddles no pair shares are kept
+    std::vector<int64_t> start(nmax + 1, 0);
+    for (size_t i = 0; i < nsad; ++i) {
+        row.assign(G.arc.begin() + G.off[i], G.arc.begin() + G.off[i + 1]);
+        const int k = distinct(row.data(), (int)row.size());
+        if (k < 2) keep[i] = 1;
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b)
+                if (row[(size_t)a] < row[(size_t)b]) ++start[(size_t)row[(size_t)a] + 1];
     }
-    // group by pair; the highest saddle of each group is its representative
-    std::sort(recs.begin(), recs.end(), [&](const PairRec& x, const PairRec& y) {
-        if (x.key != y.key) return x.key < y.key;
-        return higher(G.sd[(size_t)x.sad], G.sd[(size_t)y.sad], G.minima);
-    });
-    std::vector<char> keep(G.sd.size(), 0);
-    for (size_t r = 0; r < recs.size(); ++r)
-        if (r == 0 || recs[r].key != recs[r - 1].key) keep[(size_t)recs[r].sad] = 1;
+    for (size_t j = 0; j < nmax; ++j) start[j + 1] += start[j];
+    // pass 2: (higher maximum, saddle) records bucketed by the lower maximum
+    std::vector<int32_t> other((size_t)start[nmax]), sad((size_t)start[nmax]);
+    std::vector<int64_t> fill(start.begin(), start.end() - 1);
+    for (size_t i = 0; i < nsad; ++i) {
+        row.assign(G.arc.begin() + G.off[i], G.arc.begin() + G.off[i + 1]);
+        const int k = distinct(row.data(), (int)row.size());
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b)
+                if (row[(size_t)a] < row[(size_t)b]) {
+                    const int64_t at = fill[(size_t)row[(size_t)a]]++;
+                    other[(size_t)at] = row[(size_t)b];
+                    sad[(size_t)at] = (int32_t)i;
+                }
+    }
+    // pass 3: per lower maximum, the highest saddle of each higher partner
+    std::vector<int32_t> best(nmax, -1);
+    for (size_t a = 0; a < nmax; ++a) {
+        for (int64_t r = start[a]; r < start[a + 1]; ++r) {
+            int32_t& b = best[(size_t)other[(size_t)r]];
+            const int32_t s = sad[(size_t)r];
+            if (b < 0 || higher(G.sd[(size_t)s], G.sd[(size_t)b], G.minima)) b = s;
+        }
+        for (int64_t r = start[a]; r < start[a + 1]; ++r) {
+            int32_t& b = best[(size_t)other[(size_t)r]];
+            if (b >= 0) keep[(size_t)b] = 1;
+            b = -1;
+        }
+    }
     return keep;
 }
 
-struct Cancel {
-    const Graph& G;
-    std::vector<int32_t> parent;  // union-find over maxima
-    explicit Cancel(const Graph& g) : G(g), parent(g.mx.size())
+struct UnionFind {
+    std::vector<int32_t> parent;  // over maxima indices; a root is a surviving maximum
+    explicit UnionFind(size_t n) : parent(n)
     {
-        for (size_t j = 0; j < parent.size(); ++j) parent[j] = (int32_t)j;
+        for (size_t j = 0; j < n; ++j) parent[j] = (int32_t)j;
     }
     int32_t root(int32_t m)
     {
@@ -119,26 +161,19 @@ struct Cancel {
         }
         return m;
     }
-    // distinct current maxima of saddle i; lowest and highest among them
-    int scan(int32_t i, int32_t* lo, int32_t* hi)
-    {
-        int n = 0;
-        int32_t l = -1, h = -1;
-        thread_local std::vector<int32_t> seen;
-        seen.clear();
-        for (int32_t k = G.off[i]; k < G.off[i + 1]; ++k) {
-            const int32_t m = root(G.arc[(size_t)k]);
-            if (std::find(seen.begin(), seen.end(), m) != seen.end()) continue;
-            seen.push_back(m);
-            ++n;
-            if (l < 0 || higher(G.mx[(size_t)l], G.mx[(size_t)m], G.minima)) l = m;
-            if (h < 0 || higher(G.mx[(size_t)m], G.mx[(size_t)h], G.minima)) h = m;
-        }
-        *lo = l;
-        *hi = h;
-        return n;
-    }
 };
+
+// Distinct current maxima of saddle i, highest first (into ms); returns how many.
+int current_maxima(const Graph& G, UnionFind& U, int32_t i, std::vector<int32_t>& ms)
+{
+    ms.clear();
+    for (int32_t k = G.off[i]; k < G.off[i + 1]; ++k) ms.push_back(U.root(G.arc[(size_t)k]));
+    const int n = distinct(ms.data(), (int)ms.size());
+    ms.resize((size_t)n);
+    std::sort(ms.begin(), ms.end(),
+              [&](int32_t a, int32_t b) { return higher(G.mx[(size_t)a], G.mx[(size_t)b], G.minima); });
+    return n;
+}
 
 struct Entry {
     double cost;
@@ -160,61 +195,78 @@ extern "C" eg_status eg_simplify(const eg_graph_host* g, uint32_t ops, double th
     if ((ops & EG_SIMPLIFY_CANCEL) && narc > 0 && (!pair_saddle || !pair_max || !pair_cost)) return EG_ERR_ARG;
 
     std::vector<char> live = (ops & EG_SIMPLIFY_BUNDLE) ? bundle(G) : std::vector<char>(nsad, 1);
-    Cancel C(G);
+    UnionFind U(G.mx.size());
     int64_t np = 0;
     if (ops & EG_SIMPLIFY_CANCEL) {
-        // min-queue on (cost, saddle order): lower saddles first among equal costs
-        auto after = [&](const Entry& a, const Entry& b) {
-            if (a.cost != b.cost) return a.cost > b.cost;
-            return higher(G.sd[(size_t)a.sad], G.sd[(size_t)b.sad], G.minima);
+        // (cost, saddle order): lower costs first, lower saddles first among equal costs
+        auto before = [&](const Entry& a, const Entry& b) {
+            if (a.cost != b.cost) return a.cost < b.cost;
+            return higher(G.sd[(size_t)b.sad], G.sd[(size_t)a.sad], G.minima);
         };
-        std::priority_queue<Entry, std::vector<Entry>, decltype(after)> q(after);
-        auto cost_of = [&](int32_t i, Entry* e) {
-            int32_t lo, hi;
-            if (C.scan(i, &lo, &hi) < 2) return false;
-            *e = Entry{G.mx[(size_t)lo].h - G.sd[(size_t)i].h, i};
-            return true;
-        };
+        auto after = [&](const Entry& a, const Entry& b) { return before(b, a); };
+        std::vector<int32_t> ms;
+        // initial entries, one sorted run
+        std::vector<Entry> run;
+        run.reserve(nsad);
         for (size_t i = 0; i < nsad; ++i) {
-            Entry e;
-            if (live[i] && cost_of((int32_t)i, &e)) q.push(e);
+            if (!live[i]) continue;
+            const int n = current_maxima(G, U, (int32_t)i, ms);
+            if (n < 2) continue;
+            const double cost = G.mx[(size_t)ms[1]].h - G.sd[i].h;
+            if (n == 2 && cost > threshold) continue;  // can never become cheaper
+            run.push_back(Entry{cost, (int32_t)i});
         }
-        while (!q.empty()) {
-            const int32_t i = q.top().sad;
-            q.pop();
-            Entry e;
-            if (!cost_of(i, &e)) continue;         // joins a single maximum now
-            if (e.cost > threshold) continue;      // costs only grow: never cancelled
-            if (!q.empty() && after(e, q.top())) {  // no longer the cheapest
-                q.push(e);
+        std::sort(run.begin(), run.end(), before);
+        std::priority_queue<Entry, std::vector<Entry>, decltype(after)> heap(after);  // reinserted entries
+        size_t pos = 0;
+        auto empty = [&]() { return pos == run.size() && heap.empty(); };
+        auto top = [&]() -> const Entry& {
+            if (pos == run.size()) return heap.top();
+            if (heap.empty() || before(run[pos], heap.top())) return run[pos];
+            return heap.top();
+        };
+        auto pop = [&]() {
+            if (pos < run.size() && (heap.empty() || before(run[pos], heap.top())))
+                ++pos;
+            else
+                heap.pop();
+        };
+        while (!empty()) {
+            const int32_t i = top().sad;
+            pop();
+            const int n = current_maxima(G, U, i, ms);
+            if (n < 2) continue;  // joins a single maximum now: no cost
+            const double cost = G.mx[(size_t)ms[1]].h - G.sd[(size_t)i].h;
+            if (cost > threshold) continue;  // discarded
+            if (!empty() && cost > top().cost) {  // the queue holds cheaper saddles
+                heap.push(Entry{cost, i});
                 continue;
             }
-            int32_t lo, hi;
-            C.scan(i, &lo, &hi);
-            C.parent[(size_t)lo] = hi;  // the lower maximum merges into the elder
-            pair_saddle[np] = i;
-            pair_max[np] = lo;
-            pair_cost[np] = e.cost;
-            ++np;
-            if (cost_of(i, &e)) q.push(e);
+            for (int k = 1; k < n; ++k) {  // all but the highest merge into it
+                U.parent[(size_t)ms[(size_t)k]] = ms[0];
+                pair_saddle[np] = i;
+                pair_max[np] = ms[(size_t)k];
+                pair_cost[np] = cost;
+                ++np;
+            }
+            live[(size_t)i] = 0;  // the cancelled saddle leaves the graph
         }
     }
     *n_pairs = np;
-    // rows of the simplified graph: surviving saddles join >= 2 maxima
+    // rows of the simplified graph: every live saddle, its distinct maxima
     out_offsets[0] = 0;
     int32_t at = 0;
     std::vector<int32_t> ms;
     for (size_t i = 0; i < nsad; ++i) {
         if (live[i]) {
             ms.clear();
-            for (int32_t k = G.off[i]; k < G.off[i + 1]; ++k) ms.push_back(G.mx[(size_t)C.root(G.arc[(size_t)k])].id);
+            for (int32_t k = G.off[i]; k < G.off[i + 1]; ++k) ms.push_back(G.mx[(size_t)U.root(G.arc[(size_t)k])].id);
             std::sort(ms.begin(), ms.end());
             ms.erase(std::unique(ms.begin(), ms.end()), ms.end());
-            if (ms.size() >= 2)
-                for (int32_t m : ms) out_arcs[at++] = m;
+            for (int32_t m : ms) out_arcs[at++] = m;
         }
         out_offsets[i + 1] = at;
     }
-    for (size_t j = 0; j < G.mx.size(); ++j) max_rep[j] = C.root((int32_t)j);
+    for (size_t j = 0; j < G.mx.size(); ++j) max_rep[j] = U.root((int32_t)j);
     return EG_OK;
 }

@@ -172,11 +172,11 @@ def test_oracle_matches_brute_alg2_reps():
 # ------------------------------------------------------------------ path geometry
 
 def _brute_paths(b):
-    """The brute force's Alg. 2 paths, flattened in the oracle's layout."""
+    """The brute force's gradient paths, flattened in the oracle's layout."""
     pair_offsets, path_offsets, verts = [0], [0], []
     for s in b["saddles"]:
-        for p, m in b["paths"][int(s)]:
-            verts += list(p) + [m]
+        for p in b["paths"][int(s)]:
+            verts += list(p)
             path_offsets.append(len(verts))
         pair_offsets.append(len(path_offsets) - 1)
     return (np.array(pair_offsets, np.int32), np.array(path_offsets, np.int32), np.array(verts, np.int32))
@@ -185,9 +185,10 @@ def _brute_paths(b):
 @pytest.mark.parametrize("shape", [(9,), (6, 7), (5, 4, 3), (3, 3, 2, 3)], ids=lambda s: "x".join(map(str, s)))
 @pytest.mark.parametrize("kind", ["uniform", "ties"])
 def test_paths_match_brute(shape, kind):
-    """Alg. 2 taken literally (brute.py walks the gradient from each rep until
-    a maximum) gives the same paths, in the same order: saddles ascending,
-    components by their smallest vertex id."""
+    """The brute force's gradient paths (each rep's path built from its
+    target's, highest vertex first) equal the oracle's walks of the pointers,
+    in the same order: saddles ascending, components by their smallest vertex
+    id."""
     for seed in range(2):
         f = W.random_field(shape, seed + 31 * len(shape), kind)
         for minima in (False, True):
