@@ -57,7 +57,8 @@ typedef enum eg_status {
     EG_ERR_WORKSPACE = 3, /* host: workspace NULL, misaligned or smaller than eg_workspace_bytes */
     EG_ERR_NAN = 4,       /* device header: the field holds a NaN (outputs undefined) */
     EG_ERR_CAPACITY = 5,  /* device header: an output capacity was too small; counts are the required sizes */
-    EG_ERR_HIP = 6        /* host: a HIP launch failed */
+    EG_ERR_HIP = 6,       /* host: a HIP launch failed */
+    EG_ERR_SCRATCH = 7    /* host: eg_build_noalloc: the field needs more than its fixed scratch */
 } eg_status;
 
 /* eg_out.flags */
@@ -150,6 +151,33 @@ size_t eg_workspace_bytes(int ndim, const int64_t* dims, int64_t cap_sad);
  */
 eg_status eg_build(const float* field, int ndim, const int64_t* dims, void* stream,
                    const eg_out* out);
+
+/*
+ * eg_build for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ *
+ * Same arguments, outputs and results as eg_build, except that out->workspace
+ * and out->ws_bytes are ignored: the workspace is a fixed device array inside
+ * the library, eg_noalloc_scratch_bytes() bytes (64 MiB) on each device,
+ * reserved when the library's code is loaded on that device and held until the
+ * process ends.  The caller still owns every output buffer and the header.
+ * The array of the device current at the call is used, so `stream` must
+ * belong to that device.  Nothing is allocated, freed or synchronised; the
+ * first call on a device looks up the array's address once (no allocation).
+ *
+ * Errors: as eg_build, plus EG_ERR_SCRATCH (synchronous, nothing queued) when
+ * eg_workspace_bytes(ndim, dims, out->cap_sad) exceeds the scratch size (about
+ * 15 M vertices of a 2D or 3D field with modest saddle capacity), and EG_ERR_HIP
+ * when the array's address cannot be found.
+ *
+ * Every call on one device shares that device's array (its contents are left
+ * from the last call; every call clears what it needs): calls that overlap on
+ * one device, from several streams or threads, race and give undefined
+ * results.  Serialise them, e.g. on one stream.
+ */
+eg_status eg_build_noalloc(const float* field, int ndim, const int64_t* dims, void* stream,
+                           const eg_out* out);
+size_t eg_noalloc_scratch_bytes(void);
 
 /*
  * The three stages of eg_build, callable one at a time with the same

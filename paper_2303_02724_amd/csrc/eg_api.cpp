@@ -1,7 +1,9 @@
 // eg_api.cpp -- the C ABI: argument checks, workspace carving and the kernel
 // sequence on the caller's stream.  Nothing here allocates or synchronises.
 #include <algorithm>
+#include <atomic>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "eg_internal.h"
@@ -152,6 +154,42 @@ eg_status batch_check(int count, const int* ndims, const int64_t* dims, const eg
 
 }  // namespace
 
+// ------------------------------------------------------------------ scratch
+
+// The workspace of eg_build_noalloc: one file-scope device array, so that the
+// entry point never allocates.  Each device that runs the library holds its
+// own copy until the process ends.  In host code `scratch` is only a handle:
+// its device address is looked up once per device (hipGetSymbolAddress, with
+// that device current) and only that address is ever passed to kernels.
+static constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::atomic<void*> g_scratch[kMaxDevices];
+std::mutex g_scratch_mu;
+
+// Device address of the current device's scratch array, or nullptr.
+void* scratch_address()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    void* p = g_scratch[dev].load(std::memory_order_acquire);
+    if (p) return p;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    p = g_scratch[dev].load(std::memory_order_relaxed);
+    if (!p) {
+        void* q = nullptr;
+        if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) return nullptr;
+        g_scratch[dev].store(q, std::memory_order_release);
+        p = q;
+    }
+    return p;
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t eg_batch_plan_bytes(int count)
@@ -286,6 +324,26 @@ eg_status eg_build(const float* field, int ndim, const int64_t* dims, void* stre
     return run_stages(S_ALL, field, ndim, dims, stream, out);
 }
 
+eg_status eg_build_noalloc(const float* field, int ndim, const int64_t* dims, void* stream, const eg_out* out)
+{
+    if (!out) return EG_ERR_ARG;
+    Grid g;
+    if (!grid_from(ndim, dims, &g)) return too_large_or_arg(ndim, dims);
+    if (!caps_ok(out->cap_max, out->cap_sad, out->cap_arc)) return EG_ERR_TOO_LARGE;
+    Tuning tu;
+    if (!decode_tuning(out->tuning, &tu)) return EG_ERR_ARG;
+    const Work need = carve(nullptr, g.ndim, g.N, g.dims[g.ndim - 1], out->cap_sad);
+    if (need.bytes > kScratchBytes) return EG_ERR_SCRATCH;
+    void* ws = scratch_address();
+    if (!ws) return EG_ERR_HIP;
+    eg_out o = *out;
+    o.workspace = ws;
+    o.ws_bytes = kScratchBytes;
+    return run_stages(S_ALL, field, ndim, dims, stream, &o);
+}
+
+size_t eg_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
 eg_status eg_classify(const float* field, int ndim, const int64_t* dims, void* stream, const eg_out* out)
 {
     return run_stages(S_CLASSIFY, field, ndim, dims, stream, out);
@@ -311,6 +369,7 @@ const char* eg_status_string(int status)
         case EG_ERR_NAN: return "field contains NaN";
         case EG_ERR_CAPACITY: return "output capacity too small (header holds required counts)";
         case EG_ERR_HIP: return "HIP launch failed";
+        case EG_ERR_SCRATCH: return "field needs more workspace than eg_build_noalloc's fixed scratch holds";
         default: return "unknown status";
     }
 }

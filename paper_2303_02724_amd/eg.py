@@ -24,7 +24,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libeg_hip.so")
 
-EG_OK, EG_ERR_ARG, EG_ERR_TOO_LARGE, EG_ERR_WORKSPACE, EG_ERR_NAN, EG_ERR_CAPACITY, EG_ERR_HIP = range(7)
+EG_OK, EG_ERR_ARG, EG_ERR_TOO_LARGE, EG_ERR_WORKSPACE, EG_ERR_NAN, EG_ERR_CAPACITY, EG_ERR_HIP, EG_ERR_SCRATCH = range(8)
 
 
 def tuning(tile3: int = 0, tile2: int = 0, hops: int = 0) -> int:
@@ -107,10 +107,12 @@ def lib():
     vp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
     L.eg_workspace_bytes.argtypes = [ctypes.c_int, i64p, ctypes.c_int64]
     L.eg_workspace_bytes.restype = ctypes.c_size_t
-    for name in ("eg_build", "eg_classify", "eg_label", "eg_arcs"):
+    for name in ("eg_build", "eg_build_noalloc", "eg_classify", "eg_label", "eg_arcs"):
         fn = getattr(L, name)
         fn.argtypes = [vp, ctypes.c_int, i64p, vp, ctypes.POINTER(eg_out)]
         fn.restype = ctypes.c_int
+    L.eg_noalloc_scratch_bytes.argtypes = []
+    L.eg_noalloc_scratch_bytes.restype = ctypes.c_size_t
     L.eg_paths.argtypes = [vp, ctypes.c_int, i64p, vp, ctypes.POINTER(eg_out), ctypes.POINTER(eg_paths_out)]
     L.eg_paths.restype = ctypes.c_int
     L.eg_simplify.argtypes = [ctypes.POINTER(eg_graph_host), ctypes.c_uint32, ctypes.c_double, vp, vp, vp, vp, vp,
@@ -247,9 +249,13 @@ class Builder:
     ``launch(field)`` queues the work on the current stream and returns at
     once; ``finish()`` synchronises, reads the device header and returns an
     ``EGResult`` of views into the buffers (valid until the next launch).
+
+    With ``noalloc=True`` no workspace is allocated and whole builds go
+    through ``eg_build_noalloc`` (the library's fixed per-device scratch).
     """
 
-    def __init__(self, shape, minima: bool = False, want_ptr: bool = False, device=None, tuning: int = 0, **caps):
+    def __init__(self, shape, minima: bool = False, want_ptr: bool = False, device=None, tuning: int = 0,
+                 noalloc: bool = False, **caps):
         self.shape = tuple(int(s) for s in shape)
         if not 1 <= len(self.shape) <= EG_MAX_NDIM:
             raise EGError(EG_ERR_ARG, f"ndim={len(self.shape)}")
@@ -259,6 +265,7 @@ class Builder:
         self.minima = minima
         self.want_ptr = want_ptr
         self.tuning = int(tuning)
+        self.noalloc = bool(noalloc)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         c = default_caps(self.n, len(self.shape))
         c.update({k: int(v) for k, v in caps.items() if v is not None})
@@ -279,9 +286,11 @@ class Builder:
         ws = workspace_bytes(self.shape, caps["cap_sad"])
         if ws == 0:
             raise EGError(EG_ERR_ARG, f"workspace query failed for {self.shape} {caps}")
-        self.ws = torch.empty(ws + 256, dtype=torch.uint8, device=dev)
-        base = self.ws.data_ptr()
-        aligned = (base + 255) & ~255
+        if self.noalloc:
+            self.ws, aligned, ws = None, None, 0
+        else:
+            self.ws = torch.empty(ws + 256, dtype=torch.uint8, device=dev)
+            aligned = (self.ws.data_ptr() + 255) & ~255
         o = eg_out()
         o.flags = EG_MINIMA if self.minima else 0
         o.labels = self.labels.data_ptr()
@@ -323,8 +332,10 @@ class Builder:
         replaced by their order surrogate (eg_order_field)."""
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         field = self._float_field(field, s)
-        fn = {"all": lib().eg_build, "classify": lib().eg_classify, "label": lib().eg_label,
-              "arcs": lib().eg_arcs}[stage]
+        if self.noalloc and stage != "all":
+            raise EGError(EG_ERR_ARG, "a no-alloc builder runs whole builds only")
+        fn = {"all": lib().eg_build_noalloc if self.noalloc else lib().eg_build, "classify": lib().eg_classify,
+              "label": lib().eg_label, "arcs": lib().eg_arcs}[stage]
         st = fn(ctypes.c_void_p(field.data_ptr()), len(self.shape), self._dims,
                 ctypes.c_void_p(s.cuda_stream), ctypes.byref(self.out))
         if st != EG_OK:

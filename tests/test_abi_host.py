@@ -251,3 +251,21 @@ def test_order_field_host_checks():
     assert L.eg_order_field(1, fake, 100, out, None, need, None) == eg.EG_ERR_WORKSPACE
     assert L.eg_order_field(1, fake, 100, out, ctypes.c_void_p(0x4000010), need, None) == eg.EG_ERR_WORKSPACE
     assert L.eg_order_field(1, fake, 100, out, ws, need - 1, None) == eg.EG_ERR_WORKSPACE
+
+
+def test_noalloc_rejects_fields_beyond_its_scratch_on_host():
+    L = eg.lib()
+    assert L.eg_noalloc_scratch_bytes() == 64 << 20
+    fake = ctypes.c_void_p(0x1000)
+    o = eg.eg_out()
+    o.cap_sad = 1000
+    # a 512^3 field needs far more than 64 MiB of workspace: refused before anything is queued
+    big = (ctypes.c_int64 * 3)(512, 512, 512)
+    assert L.eg_workspace_bytes(3, big, 1000) > L.eg_noalloc_scratch_bytes()
+    assert L.eg_build_noalloc(fake, 3, big, None, ctypes.byref(o)) == eg.EG_ERR_SCRATCH
+    # argument errors come first, as for eg_build
+    assert L.eg_build_noalloc(fake, 0, big, None, ctypes.byref(o)) == eg.EG_ERR_ARG
+    assert L.eg_build_noalloc(fake, 3, big, None, None) == eg.EG_ERR_ARG
+    huge = (ctypes.c_int64 * 2)(1 << 16, 1 << 16)
+    assert L.eg_build_noalloc(fake, 2, huge, None, ctypes.byref(o)) == eg.EG_ERR_TOO_LARGE
+    assert "scratch" in eg.status_string(eg.EG_ERR_SCRATCH)
