@@ -11,8 +11,14 @@ Gaussian random field (seed 1, correlation length 8 voxels), maxima graph.
 Prints one JSON line.  Besides the contract fields it carries
   roofline      the dominant kernel against the HBM peak (algorithmic bytes /
                 its average duration, timed with HIP events on the launch stream)
-  cpu_baseline  the CPU oracle timed on a bounded slab of the same field
+  cpu_baseline  the CPU oracle timed on bounded slabs of the same field, on all
+                host cores and on one (7 runs, best and worst dropped)
   stages_ms     per-stage times (classify / label / arcs), HIP events
+  batched       256 fields of uneven sizes in one eg_build_batched per step,
+                against one eg_build per field (default workload only)
+  serving       the request loop on host-resident fields at 200 requests/s:
+                p50/p99 latency (copy included), vertices/s, mean batch
+                (default workload only)
 """
 from __future__ import annotations
 
@@ -54,6 +60,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-paths", action="store_true", help="skip the gradient-path geometry measurement")
     ap.add_argument("--no-typed", action="store_true", help="skip the other-sample-type measurement")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched sub-measurement (256 fields)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving sub-measurement")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (library default tile shape and links per pass)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -209,6 +217,58 @@ def measure_graph(b, t, steps):
             "replays_equal_eager": bool(same)}
 
 
+def measure_streamed(f, tuning, minima, reps=7, slab=32):
+    """The field starting in pinned host memory (PCIe included): copied whole
+    and then built (one stream), against eg_build_streamed (slabs of `slab`
+    planes copied on a second stream while the slabs that have landed are
+    classified).  Host wall time per build, 7 runs, best and worst dropped;
+    the two results are compared."""
+    import torch
+
+    from paper_2303_02724_amd import eg
+
+    host = torch.empty(f.shape, dtype=torch.float32, pin_memory=True)
+    host.copy_(torch.from_numpy(f))
+    b = eg.Builder(f.shape, minima=minima, tuning=tuning)
+    b.run_streamed(host, slab)  # sizes the buffers
+    dev = b.field_dev
+    s = torch.cuda.current_stream()
+
+    def whole():
+        dev.copy_(host, non_blocking=True)
+        b.launch(dev, stream=s)
+
+    def streamed():
+        b.launch_streamed(host, slab, stream=s)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ts.sort()
+        mid = ts[1:-1] if len(ts) > 2 else ts
+        return sum(mid) / len(mid)
+
+    t_whole = timed(whole)
+    ref = (b.labels.clone(), b.arcs.clone(), b.header.clone())
+    t_str = timed(streamed)
+    same = all(torch.equal(x, y) for x, y in zip(ref, (b.labels, b.arcs, b.header)))
+    N = int(f.size)
+    out = {"slab_planes": slab, "slabs": -(-f.shape[0] // slab),
+           "copy_then_build": {"ms": round(t_whole * 1e3, 3), "vertices_per_s": N / t_whole},
+           "streamed": {"ms": round(t_str * 1e3, 3), "vertices_per_s": N / t_str},
+           "speedup": t_whole / t_str, "results_equal": bool(same),
+           "note": "PCIe-inclusive: the field starts in pinned host memory"}
+    del b, host, dev
+    torch.cuda.empty_cache()
+    return out
+
+
 def measure_simplify(res, t, minima):
     """Graph simplification (host): arc bundling then persistence-directed
     cancellation at 5 % of the field's value range, as in the paper's
@@ -274,37 +334,65 @@ def time_stages(b, t, reps):
     return {k: v / reps for k, v in acc.items()}
 
 
-def cpu_baseline(f, planes):
+def cpu_baseline(f, planes_all, planes_one, runs=7):
+    """The oracle on slabs of the field (the first planes along the slowest
+    axis), on all host cores and on one core: `runs` runs each, the best and
+    the worst dropped, the mean of the rest (the paper's Sec. 5 protocol),
+    with the median beside it."""
     from oracle import oracle as O
 
-    sub = f[:planes] if planes else f
-    t0 = time.perf_counter()
-    g = O.extremum_graph(sub)
-    dt = time.perf_counter() - t0
+    def timed(sub):
+        ts = []
+        g = None
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            g = O.extremum_graph(sub)
+            ts.append(time.perf_counter() - t0)
+        ts.sort()
+        trimmed = ts[1:-1] if len(ts) > 2 else ts
+        return sum(trimmed) / len(trimmed), ts[len(ts) // 2], g
+
+    cores = O.num_threads()
+    sub = f[:planes_all]
+    mean, med, g = timed(sub)
+    prev = O.set_threads(1)
+    try:
+        sub1 = f[:planes_one]
+        mean1, med1, _ = timed(sub1)
+    finally:
+        O.set_threads(prev)
     return {
-        "value": sub.size / dt,
+        "value": sub.size / mean,
         "unit": "vertices/s",
-        "cores": O.num_threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": f"oracle (classification + labels + arcs) on the first {sub.shape[0]} of {f.shape[0]} "
-                  f"slowest-axis planes, shape {list(sub.shape)}, {sub.size} vertices, {dt:.2f} s; "
+                  f"slowest-axis planes, shape {list(sub.shape)}, {sub.size} vertices, {mean:.3f} s per run; "
                   f"{len(g['maxima'])} maxima, {len(g['saddles'])} saddles",
+        "protocol": f"{runs} runs, best and worst dropped, mean of the rest",
+        "median_value": sub.size / med,
+        "one_core": {"value": sub1.size / mean1, "median_value": sub1.size / med1, "cores": 1,
+                     "sample": f"first {sub1.shape[0]} planes, {sub1.size} vertices, {mean1:.3f} s per run"},
     }
 
 
-def run_batched(args):
-    """Batched workload: all fields in one eg_build_batched per step, against
-    the same fields built one eg_build at a time on the same stream."""
+def batched_fields(count):
+    from paper_2303_02724_amd import workloads as W
+
+    specs = W.batched_specs(count=count)
+    return [W.batched_field(sp) for sp in specs]
+
+
+def measure_batched(fields, steps, warmup, graph=True):
+    """All fields in one eg_build_batched per step (the launch configuration
+    picked on this batch), against the same fields built one eg_build at a
+    time on the same stream; also the batch replayed from a captured HIP
+    graph.  Host wall time over the steps, inputs resident."""
     import torch
 
-    from paper_2303_02724_amd import eg, workloads as W
+    from paper_2303_02724_amd import eg
 
-    t_gen = time.perf_counter()
-    specs = W.batched_specs(count=args.fields)
-    fields = [W.batched_field(sp) for sp in specs]
-    t_gen = time.perf_counter() - t_gen
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     ts = [torch.from_numpy(f).to(dev) for f in fields]
     N = sum(int(f.size) for f in fields)
     bb = eg.BatchBuilder([f.shape for f in fields], device=dev)
@@ -315,78 +403,105 @@ def run_batched(args):
         h = b.header_values()
         caps.append({"cap_max": max(1, h[eg.H_NMAX]), "cap_sad": max(1, h[eg.H_NSAD]),
                      "cap_arc": max(1, h[eg.H_NARC])})
-    bb = eg.BatchBuilder([f.shape for f in fields], device=dev, caps=caps)
-    bb.run(ts)
     s = torch.cuda.current_stream()
-    graph = None
-    if args.graph:
+
+    def timed(step, n):
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            step()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n
+
+    # launch configuration for the batch: every 2D and 3D tile shape, timed
+    # on this batch (identical results by construction)
+    cands = {}
+    for tu in (eg.tuning(0, 0), eg.tuning(2, 0), eg.tuning(1, 0), eg.tuning(0, 1), eg.tuning(2, 1)):
+        cb = eg.BatchBuilder([f.shape for f in fields], device=dev, caps=caps, tuning=tu)
+        cb.run(ts)
+        cands[tu] = timed(lambda: cb.launch(stream=s), 3)
+        del cb
+    best = min(cands, key=cands.get)
+    bb = eg.BatchBuilder([f.shape for f in fields], device=dev, caps=caps, tuning=best)
+    bb.run(ts)
+    tb = timed(lambda: bb.launch(stream=s), steps)
+    heads = [b.header_values() for b in bb.builders]
+    bad = [h for h in heads if h[eg.H_STATUS] != eg.EG_OK]
+    if bad:
+        raise SystemExit(f"device status after the batched steps: {bad[:3]}")
+    tg = None
+    if graph:
         side = torch.cuda.Stream()
         side.wait_stream(s)
         with torch.cuda.stream(side):
             bb.launch(stream=side)  # warm the capture stream
         s.wait_stream(side)
         torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph, stream=side):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
             bb.launch(stream=side)
         torch.cuda.synchronize()
-
-    def batched_step():
-        if graph is not None:
-            graph.replay()
-        else:
-            bb.launch(stream=s)
+        tg = timed(g.replay, steps)
+        del g
+    for b, t in zip(bb.builders, ts):
+        b.tuning = best
+        b.out.tuning = best
 
     def per_field_step():
         for b, t in zip(bb.builders, ts):
             b.launch(t, stream=s)
 
-    def timed(step):
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / args.steps
+    tp = timed(per_field_step, max(2, steps // 4))
+    out = {"fields": len(fields), "vertices": N,
+           "shapes": "2D sides U[64,2048] or 3D sides U[32,192], p = 1/2, meta-seed 3",
+           "value": N / tb, "unit": "vertices/s", "ms_per_step": tb * 1e3,
+           "tuning": {"choice": hex(best), "candidates_ms": {hex(k): round(v * 1e3, 3) for k, v in cands.items()}},
+           "per_field": {"value": N / tp, "ms_per_step": tp * 1e3},
+           "speedup_vs_per_field": tp / tb}
+    if tg is not None:
+        out["graph_replay"] = {"value": N / tg, "ms_per_step": tg * 1e3}
+    del bb, ts
+    torch.cuda.empty_cache()
+    return out
 
-    tb = timed(batched_step)
-    heads = [b.header_values() for b in bb.builders]
-    bad = [h for h in heads if h[eg.H_STATUS] != eg.EG_OK]
-    if bad:
-        raise SystemExit(f"device status after the batched steps: {bad[:3]}")
-    tp = timed(per_field_step)
+
+def run_batched(args):
+    """Batched workload: all fields in one eg_build_batched per step, against
+    the same fields built one eg_build at a time on the same stream."""
+    import torch
+
+    t_gen = time.perf_counter()
+    fields = batched_fields(args.fields)
+    t_gen = time.perf_counter() - t_gen
+    torch.cuda.set_device(torch.device("cuda:0"))
+    m = measure_batched(fields, args.steps, args.warmup, graph=True)
     out = {
         "metric": METRIC,
-        "value": N / tb,
+        "value": m["value"],
         "unit": "vertices/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": tb * 1e3,
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"batched_{len(fields)}", "fields": len(fields), "vertices": N,
-                   "shapes": "2D sides U[64,2048] or 3D sides U[32,192], p = 1/2, meta-seed 3",
-                   "graph": bool(args.graph)},
-        "per_field": {"value": N / tp, "ms_per_step": tp * 1e3},
-        "speedup_vs_per_field": tp / tb,
+        "config": {"workload": f"batched_{len(fields)}", "fields": len(fields), "vertices": m["vertices"],
+                   "shapes": m["shapes"]},
+        "batched": m,
         "field_gen_s": round(t_gen, 2),
     }
     print(json.dumps(out), flush=True)
 
 
 def serving_pool(n_requests, rate, seed=4, n_small=47, big_side=384, p_big=0.1):
-    """Poisson arrivals; each request names one device-resident field: the
-    big_side^3 field with probability p_big, else one of n_small fields whose
-    shapes follow the batched workload (2D sides U[64,2048] or 3D sides
-    U[32,192])."""
-    import numpy as np
-
+    """Poisson arrivals; each request names one field: the big_side^3 field
+    with probability p_big, else one of n_small fields whose shapes follow
+    the batched workload (2D sides U[64,2048] or 3D sides U[32,192])."""
     from paper_2303_02724_amd import workloads as W
 
     specs = W.batched_specs(count=n_small, meta_seed=seed + 100)
@@ -410,31 +525,39 @@ def serving_requests(n_requests, rate, seed=4, n_small=47, p_big=0.1):
     return reqs
 
 
-def run_serving(args):
+def measure_serving(n_requests, rate, sat_rate):
+    """The serving loop on host-resident (pinned) fields, copied to the device
+    at admission: continuous batching against one request at a time, at the
+    configured arrival rate and at one above what the GPU sustains.  Latency
+    = completion seen by the host - arrival (copy included)."""
     import torch
 
     from paper_2303_02724_amd import eg, serving
 
     t_gen = time.perf_counter()
-    fields, reqs = serving_pool(args.requests, args.rate)
+    host, reqs = serving_pool(n_requests, rate)
     t_gen = time.perf_counter() - t_gen
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    ts = [torch.from_numpy(f).to(dev) for f in fields]
-    # capacities measured once per field shape (untimed), so no request retries
+    fields = []
     caps = {}
-    for t in ts:
-        r = eg.build(t)
-        caps[tuple(t.shape)] = {"cap_max": max(1, r.counts["maxima"]), "cap_sad": max(1, r.counts["saddles"]),
+    for f in host:
+        p = torch.empty(f.shape, dtype=torch.float32, pin_memory=True)
+        p.copy_(torch.from_numpy(f))
+        fields.append(p)
+        # capacities measured once per field shape (untimed), so no request retries
+        r = eg.build(p.to(dev))
+        caps[tuple(f.shape)] = {"cap_max": max(1, r.counts["maxima"]), "cap_sad": max(1, r.counts["saddles"]),
                                 "cap_arc": max(1, r.counts["arcs"])}
+    del r
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     policies = [("continuous_batching", dict(max_batch=32, lanes=3, max_slots=96)),
                 ("one_at_a_time", dict(max_batch=1, lanes=1, max_slots=1))]
     servers = {}
     for name, kw in policies:
         srv = serving.Server(device=dev, caps_for=lambda sh: caps[sh], **kw)
-        srv.prewarm([tuple(t.shape) for t in ts], per_shape=2 if kw["max_batch"] > 1 else 1)
-        srv.run(reqs[: min(50, len(reqs))], ts)  # warm-up stream
+        srv.prewarm([tuple(f.shape) for f in fields], per_shape=2 if kw["max_batch"] > 1 else 1)
+        srv.run(reqs[: min(50, len(reqs))], fields)  # warm-up stream
         servers[name] = srv
     torch.cuda.synchronize()
 
@@ -442,19 +565,38 @@ def run_serving(args):
         res = {}
         for name, _ in policies:
             torch.cuda.synchronize()
-            res[name] = servers[name].run(rq, ts).summary()
+            res[name] = servers[name].run(rq, fields).summary()
         return res
 
     out = measure(reqs)
-    # the same pool at an arrival rate above what the GPU sustains
-    sat = measure(serving_requests(args.requests, args.sat_rate))
+    sat = measure(serving_requests(n_requests, sat_rate))
     cb, fifo = out["continuous_batching"], out["one_at_a_time"]
+    res = {"rate_hz": rate, "requests": len(reqs),
+           "fields": "host-resident (pinned), copied at admission: 47 batched-workload shapes + 384^3 with p = 0.1",
+           "p50_ms": cb["p50_ms"], "p99_ms": cb["p99_ms"], "vertices_per_s": cb["vertices_per_s"],
+           "mean_batch": cb["mean_batch"], "continuous_batching": cb, "one_at_a_time": fifo,
+           "saturated": {"rate_hz": sat_rate, "continuous_batching": sat["continuous_batching"],
+                         "one_at_a_time": sat["one_at_a_time"],
+                         "throughput_ratio": sat["continuous_batching"]["vertices_per_s"] /
+                         sat["one_at_a_time"]["vertices_per_s"]},
+           "field_gen_s": round(t_gen, 2)}
+    del servers, fields
+    torch.cuda.empty_cache()
+    return res
+
+
+def run_serving(args):
+    import torch
+
+    torch.cuda.set_device(torch.device("cuda:0"))
+    m = measure_serving(args.requests, args.rate, args.sat_rate)
+    cb = m["continuous_batching"]
     res = {
         "metric": METRIC,
         "value": cb["vertices_per_s"],
         "unit": "vertices/s",
         "n_gpus": 1,
-        "steps": len(reqs),
+        "steps": m["requests"],
         "warmup": 50,
         "ms_per_step": cb["mean_ms"],
         "higher_is_better": True,
@@ -462,18 +604,11 @@ def run_serving(args):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"serving_poisson_{int(args.rate)}hz", "requests": len(reqs),
-                   "fields": "47 batched-workload shapes + 384^3 with p = 0.1", "rate_hz": args.rate},
-        "p50_ms": cb["p50_ms"],
-        "p99_ms": cb["p99_ms"],
-        "serving": cb,
-        "one_at_a_time": fifo,
-        "saturated": {"rate_hz": args.sat_rate,
-                      "continuous_batching": sat["continuous_batching"],
-                      "one_at_a_time": sat["one_at_a_time"],
-                      "throughput_ratio": sat["continuous_batching"]["vertices_per_s"] /
-                      sat["one_at_a_time"]["vertices_per_s"]},
-        "field_gen_s": round(t_gen, 2),
+        "config": {"workload": f"serving_poisson_{int(args.rate)}hz", "requests": m["requests"],
+                   "fields": m["fields"], "rate_hz": args.rate},
+        "p50_ms": m["p50_ms"],
+        "p99_ms": m["p99_ms"],
+        "serving": m,
     }
     print(json.dumps(res), flush=True)
 
@@ -609,6 +744,8 @@ def main():
     if not args.no_paths:
         out["paths"] = measure_paths(args, f, t, tuning)
     out["simplify"] = measure_simplify(res, t, args.minima)
+    if f.ndim in (2, 3):
+        out["streamed"] = measure_streamed(f, tuning, args.minima)
     if not args.no_typed:
         out["typed"] = measure_typed(args, t, tuning)
     if args.profile_stage:
@@ -622,13 +759,20 @@ def main():
                 b.launch(t, stream=s, stage="classify")
             b.launch(t, stream=s, stage=args.profile_stage)
         torch.cuda.synchronize()
+    del b
+    torch.cuda.empty_cache()
+    if args.workload == "grf512" and not args.no_batched:
+        out["batched"] = measure_batched(batched_fields(args.fields), steps=10, warmup=2)
+    if args.workload == "grf512" and not args.no_serving:
+        out["serving"] = measure_serving(args.requests, args.rate, args.sat_rate)
     if not args.no_cpu_baseline:
         planes = args.cpu_planes
         if planes is None:
-            planes = {"grf512": max(1, f.shape[0] // 4), "2d256": f.shape[0], "5d32": max(1, f.shape[0] // 4),
-                      "6d16": max(1, f.shape[0] // 4)}[
-                args.workload]
-        out["cpu_baseline"] = cpu_baseline(f, planes)
+            planes = {"grf512": max(1, f.shape[0] // 8), "2d256": f.shape[0], "5d32": max(1, f.shape[0] // 8),
+                      "6d16": max(1, f.shape[0] // 8)}[args.workload]
+        one = {"grf512": max(1, f.shape[0] // 64), "2d256": f.shape[0], "5d32": max(1, f.shape[0] // 16),
+               "6d16": max(1, f.shape[0] // 16)}[args.workload]
+        out["cpu_baseline"] = cpu_baseline(f, planes, one)
     print(json.dumps(out), flush=True)
 
 

@@ -58,7 +58,9 @@ typedef enum eg_status {
     EG_ERR_NAN = 4,       /* device header: the field holds a NaN (outputs undefined) */
     EG_ERR_CAPACITY = 5,  /* device header: an output capacity was too small; counts are the required sizes */
     EG_ERR_HIP = 6,       /* host: a HIP launch failed */
-    EG_ERR_SCRATCH = 7    /* host: eg_build_noalloc: the field needs more than its fixed scratch */
+    EG_ERR_SCRATCH = 7,   /* host: eg_build_noalloc: the field needs more than its fixed scratch */
+    EG_ERR_UNRESOLVED = 8 /* device header: a label was still a code after the last label pass
+                             (an internal error: the pass count covers every path; outputs undefined) */
 } eg_status;
 
 /* eg_out.flags */
@@ -116,11 +118,16 @@ typedef struct eg_out {
  *   EG_TUNE_TILE3(v)  3D tile: 0 = 64x8x8, 1 = 64x4x16, 2 = 64x8x4
  *   EG_TUNE_TILE2(v)  2D tile: 0 = 64x32, 1 = 64x16
  *   EG_TUNE_HOPS(h)   links followed per label pass: 0 = 64; 16, 32, 64 or 128
- * Other values are EG_ERR_ARG.  A batch uses outs[0].tuning for every field.
+ *   EG_TUNE_EXITS(e)  most exit-list entries: 0 = the default capacity, e = 1..30
+ *                     caps it at 2^e (a test hook for the path that tiles whose
+ *                     exits do not fit take: labels by vertex codes instead)
+ * Other values are EG_ERR_ARG.  A batch uses outs[0].tuning for its launch
+ * choices and each field's own EG_TUNE_EXITS.
  */
 #define EG_TUNE_TILE3(v) ((uint32_t)(v) & 0xFu)
 #define EG_TUNE_TILE2(v) (((uint32_t)(v) & 0xFu) << 4)
 #define EG_TUNE_HOPS(h) (((uint32_t)(h) & 0xFFu) << 8)
+#define EG_TUNE_EXITS(e) (((uint32_t)(e) & 0x1Fu) << 16)
 
 /*
  * Workspace bytes that eg_build needs for a field of the given shape and the
@@ -178,6 +185,37 @@ eg_status eg_build(const float* field, int ndim, const int64_t* dims, void* stre
 eg_status eg_build_noalloc(const float* field, int ndim, const int64_t* dims, void* stream,
                            const eg_out* out);
 size_t eg_noalloc_scratch_bytes(void);
+
+/*
+ * eg_build of a field that sits in host memory, with the copy to the device
+ * overlapped with classification (the paper's slab decomposition along the
+ * slowest axis, Sec. 4, re-thought for one GPU whose memory holds the field):
+ * the field is copied slab by slab (slab_planes planes of axis 0, rounded up
+ * to whole tile rows) on copy_stream, each slab followed by events[k]; on
+ * stream, the tiles of slab k are classified once slab k + 1 has landed (one
+ * plane of it is their ghost layer); labels and arcs follow for the whole
+ * field.  Results equal eg_build's on the same field.
+ *
+ *   host_field   host, float32[N], C order; page-locked (pinned) memory for
+ *                the copies to overlap (pageable memory works, but the runtime
+ *                may then copy synchronously)
+ *   dev_field    device, float32[N]: receives the field (caller-owned)
+ *   ndim         2 or 3
+ *   slab_planes  >= 1
+ *   stream       compute stream; copy_stream: a different stream for the copies
+ *   events       hipEvent_t[nevents] created by the caller, nevents >= the
+ *                number of slabs, ceil(dims[0] / slab planes), plus one: the
+ *                last is recorded on stream first, and the copies wait for it
+ *                (work already queued there may still read dev_field)
+ *   out          as for eg_build
+ *
+ * Errors: as eg_build, plus EG_ERR_ARG for a NULL host or device field, ndim
+ * outside {2, 3}, slab_planes < 1 or too few events; EG_ERR_HIP when a copy
+ * or an event call fails.  Nothing is allocated or synchronised.
+ */
+eg_status eg_build_streamed(const float* host_field, float* dev_field, int ndim, const int64_t* dims,
+                            int64_t slab_planes, void* stream, void* copy_stream, void* const* events,
+                            int64_t nevents, const eg_out* out);
 
 /*
  * The three stages of eg_build, callable one at a time with the same

@@ -253,6 +253,20 @@ int ego_num_threads(void)
 #endif
 }
 
+/* Threads of the parallel loops that follow (n < 1: leave unchanged); returns
+   the previous count.  Used to time the oracle on one core and on all. */
+int ego_set_threads(int n)
+{
+#ifdef _OPENMP
+    const int before = omp_get_max_threads();
+    if (n >= 1) omp_set_num_threads(n);
+    return before;
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
 /* Neighbour ids of vertex v (count returned; at most 3^ndim - 1). */
 int ego_neighbours(const void* f, int dtype, int ndim, const int64_t* dims, int64_t v, int64_t* out)
 {

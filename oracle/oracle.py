@@ -57,6 +57,8 @@ def use_library(path):
 def _bind(lib):
     vp = ctypes.c_void_p
     lib.ego_num_threads.restype = ctypes.c_int
+    lib.ego_set_threads.argtypes = [ctypes.c_int]
+    lib.ego_set_threads.restype = ctypes.c_int
     ci = ctypes.c_int
     lib.ego_neighbours.argtypes = [vp, ci, ctypes.c_int, vp, ctypes.c_int64, vp]
     lib.ego_neighbours.restype = ctypes.c_int
@@ -104,6 +106,12 @@ def _p(a):
 
 def num_threads() -> int:
     return int(_load().ego_num_threads())
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's parallel loops from now on; returns the
+    previous count."""
+    return int(_load().ego_set_threads(int(n)))
 
 
 def neighbours(shape, v: int) -> np.ndarray:

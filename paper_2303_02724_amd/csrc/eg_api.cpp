@@ -63,10 +63,10 @@ eg_status check_one(const float* field, int ndim, const int64_t* dims, const eg_
     if ((o->cap_max > 0 && !o->maxima) || (o->cap_sad > 0 && !o->saddles) || (o->cap_arc > 0 && !o->arc_maxima))
         return EG_ERR_ARG;
     const int64_t X = g->dims[g->ndim - 1];
-    const Work need = carve(nullptr, g->ndim, g->N, X, o->cap_sad);
+    const Work need = carve(nullptr, g->ndim, g->N, X, o->cap_sad, tu.exit_cap);
     if (!o->workspace || (reinterpret_cast<uintptr_t>(o->workspace) & 255u) || o->ws_bytes < need.bytes)
         return EG_ERR_WORKSPACE;
-    *w = carve(o->workspace, g->ndim, g->N, X, o->cap_sad);
+    *w = carve(o->workspace, g->ndim, g->N, X, o->cap_sad, tu.exit_cap);
     return EG_OK;
 }
 
@@ -87,10 +87,14 @@ hipError_t stage_label(const Grid& g, const eg_out& o, const Work& w, const Tuni
 }
 
 // Stage (d) and the canonical outputs: ascending maxima and saddles, the
-// arcs of every saddle as a CSR, and the header.
-hipError_t stage_arcs(const float* field, const Grid& g, const eg_out& o, const Work& w, hipStream_t s)
+// arcs of every saddle as a CSR, and the header (which also reports labels
+// left unresolved by the last label pass).
+hipError_t stage_arcs(const float* field, const Grid& g, const eg_out& o, const Work& w, const Tuning& tu,
+                      hipStream_t s)
 {
-    return launch_arcs(arc_args(field, g, o, w), s);
+    ArcArgs a = arc_args(field, g, o, w);
+    a.last_flag = gptr<const uint32_t>(w.ctr + C_FINAL + tu.passes - 1);
+    return launch_arcs(a, s);
 }
 
 enum Stage { S_CLASSIFY = 1, S_LABEL = 2, S_ARCS = 4, S_ALL = 7 };
@@ -111,7 +115,7 @@ eg_status run_stages(int stages, const float* field, int ndim, const int64_t* di
     hipError_t e = hipSuccess;
     if (stages & S_CLASSIFY) e = stage_classify(field, g, t, *out, w, tu, s);
     if (e == hipSuccess && (stages & S_LABEL)) e = stage_label(g, *out, w, tu, s);
-    if (e == hipSuccess && (stages & S_ARCS)) e = stage_arcs(field, g, *out, w, s);
+    if (e == hipSuccess && (stages & S_ARCS)) e = stage_arcs(field, g, *out, w, tu, s);
     return e == hipSuccess ? EG_OK : EG_ERR_HIP;
 }
 
@@ -271,6 +275,8 @@ eg_status eg_batch_plan(int count, const float* const* fields, const int* ndims,
     int64_t max_n = 1;
     for (int i = 0; i < count; ++i) max_n = std::max<int64_t>(max_n, F[i].N);
     P->tuning.passes = passes_for(P->tuning, max_n);
+    for (int k = 0; k < count; ++k)
+        F[k].arc.last_flag = gptr<const uint32_t>((const uint32_t*)P->bctr + C_FINAL + P->tuning.passes - 1);
     P->total_tiles = tiles;
     P->total_arc_blocks = arc_blocks_total;
     return EG_OK;
@@ -332,7 +338,7 @@ eg_status eg_build_noalloc(const float* field, int ndim, const int64_t* dims, vo
     if (!caps_ok(out->cap_max, out->cap_sad, out->cap_arc)) return EG_ERR_TOO_LARGE;
     Tuning tu;
     if (!decode_tuning(out->tuning, &tu)) return EG_ERR_ARG;
-    const Work need = carve(nullptr, g.ndim, g.N, g.dims[g.ndim - 1], out->cap_sad);
+    const Work need = carve(nullptr, g.ndim, g.N, g.dims[g.ndim - 1], out->cap_sad, tu.exit_cap);
     if (need.bytes > kScratchBytes) return EG_ERR_SCRATCH;
     void* ws = scratch_address();
     if (!ws) return EG_ERR_HIP;
@@ -343,6 +349,62 @@ eg_status eg_build_noalloc(const float* field, int ndim, const int64_t* dims, vo
 }
 
 size_t eg_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+eg_status eg_build_streamed(const float* host_field, float* dev_field, int ndim, const int64_t* dims,
+                            int64_t slab_planes, void* stream, void* copy_stream, void* const* events,
+                            int64_t nevents, const eg_out* out)
+{
+    if (!host_field || !dev_field || !events || slab_planes < 1) return EG_ERR_ARG;
+    if (ndim != 2 && ndim != 3) return EG_ERR_ARG;
+    Grid g;
+    Work w;
+    const eg_status st = check_one(dev_field, ndim, dims, out, &g, &w);
+    if (st != EG_OK) return st;
+    Tuning tu;
+    decode_tuning(out->tuning, &tu);
+    tu.passes = passes_for(tu, g.N);
+    int ty, tz;
+    tile_shape(tu, ndim, &ty, &tz);
+    // slabs are whole tile rows along axis 0 (the slowest)
+    const int64_t depth = ndim == 3 ? tz : ty;
+    const int64_t D0 = g.dims[0];
+    const int64_t plane = (int64_t)g.N / D0;
+    const int64_t slab = (slab_planes + depth - 1) / depth * depth;
+    const int64_t nslabs = (D0 + slab - 1) / slab;
+    const int64_t rows = (D0 + depth - 1) / depth;
+    if (nevents < nslabs + 1) return EG_ERR_ARG;
+    for (int64_t k = 0; k <= nslabs; ++k)
+        if (!events[k]) return EG_ERR_ARG;
+    const TileArgs ta = tile_args(dev_field, g, out->labels, out->ptr, w, ty, tz);
+    const int64_t tiles_per_row = (int64_t)ta.tiles_x * (ndim == 3 ? ta.tiles_y : 1);
+    hipStream_t s = (hipStream_t)stream, cs = (hipStream_t)copy_stream;
+    // the copies overwrite dev_field: they wait for the work already queued
+    // on the compute stream (an earlier build may still read it)
+    if (hipEventRecord((hipEvent_t)events[nslabs], s) != hipSuccess) return EG_ERR_HIP;
+    if (hipStreamWaitEvent(cs, (hipEvent_t)events[nslabs], 0) != hipSuccess) return EG_ERR_HIP;
+    // every copy first, each slab followed by its event, so the copy engine
+    // streams while the compute stream classifies the slabs that have landed
+    for (int64_t k = 0; k < nslabs; ++k) {
+        const int64_t p0 = k * slab, p1 = std::min(D0, p0 + slab);
+        if (hipMemcpyAsync(dev_field + p0 * plane, host_field + p0 * plane, (size_t)((p1 - p0) * plane) * sizeof(float),
+                           hipMemcpyHostToDevice, cs) != hipSuccess)
+            return EG_ERR_HIP;
+        if (hipEventRecord((hipEvent_t)events[k], cs) != hipSuccess) return EG_ERR_HIP;
+    }
+    const bool minima = (out->flags & EG_MINIMA) != 0;
+    hipError_t e = launch_init(w.ctr, out->header, s);
+    for (int64_t k = 0; k < nslabs && e == hipSuccess; ++k) {
+        // the tiles of slab k read one plane past it: wait for the next slab too
+        e = hipStreamWaitEvent(s, (hipEvent_t)events[std::min(k + 1, nslabs - 1)], 0);
+        const int64_t r0 = k * slab / depth, r1 = std::min(rows, (k + 1) * slab / depth);
+        if (e == hipSuccess)
+            e = launch_classify_tiled(dev_field, g, minima, out->labels, out->ptr, w, tu, s, r0 * tiles_per_row,
+                                      (r1 - r0) * tiles_per_row);
+    }
+    if (e == hipSuccess) e = stage_label(g, *out, w, tu, s);
+    if (e == hipSuccess) e = stage_arcs(dev_field, g, *out, w, tu, s);
+    return e == hipSuccess ? EG_OK : EG_ERR_HIP;
+}
 
 eg_status eg_classify(const float* field, int ndim, const int64_t* dims, void* stream, const eg_out* out)
 {
@@ -370,6 +432,7 @@ const char* eg_status_string(int status)
         case EG_ERR_CAPACITY: return "output capacity too small (header holds required counts)";
         case EG_ERR_HIP: return "HIP launch failed";
         case EG_ERR_SCRATCH: return "field needs more workspace than eg_build_noalloc's fixed scratch holds";
+        case EG_ERR_UNRESOLVED: return "labels left unresolved by the last label pass (internal error)";
         default: return "unknown status";
     }
 }

@@ -809,6 +809,8 @@ __global__ void k_finalize(Sel sel)
     int status = EG_OK;
     if (c[C_NAN])
         status = EG_ERR_NAN;
+    else if (A.last_flag && *A.last_flag)
+        status = EG_ERR_UNRESOLVED;
     else if (nmax > A.cap_max || sad_over || narc > A.cap_arc)
         status = EG_ERR_CAPACITY;
     int32_t* h = A.header;

@@ -101,27 +101,23 @@ __device__ __forceinline__ void double_tile_chains(int (&cur)[VPT], int32_t* s_n
 
 // Every vertex whose steepest step leaves the tile gets its own entry of the
 // exit list, which records the step's target; before the tile's chains are
-// resolved, cur[k] < 0 holds -(target + 1) for such a vertex.  One block scan
-// and one atomic per tile place the entries; cur[k] becomes the entry's code,
-// so the pointer doubling hands that code to every vertex whose path leaves
-// the tile there, and the label pass resolves each entry once.  A tile that
-// does not fit in the list keeps the vertex codes.
+// resolved, cur[k] < 0 holds -(target + 1) for such a vertex.  Entries are
+// ranked without a scan: per k, a wave ballot of its exiting lanes, the
+// lane's rank among them (mbcnt) and the running count of the wave (scalar);
+// one atomic per tile places the tile's block.  cur[k] becomes the entry's
+// code, so the pointer doubling hands that code to every vertex whose path
+// leaves the tile there, and the label pass resolves each entry once.  A tile
+// that does not fit in the list keeps the vertex codes.
 template <int VPT>
 __device__ __forceinline__ void alloc_exits(int (&cur)[VPT], uint32_t* s_tmp, uint32_t* __restrict__ ctr,
                                             uint32_t* __restrict__ exits, uint32_t cap_exit, int N)
 {
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    uint32_t mask = 0;
+    const int tid = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    uint32_t wave_total = 0;
 #pragma unroll
-    for (int k = 0; k < VPT; ++k) mask |= (cur[k] < 0 ? 1u : 0u) << k;
-    const uint32_t cnt = (uint32_t)__popc(mask);
-    uint32_t inc = cnt;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(inc, o);
-        if (lane >= o) inc += y;
-    }
-    if (lane == 63) s_tmp[w] = inc;
+    for (int k = 0; k < VPT; ++k) wave_total += (uint32_t)__popcll(__ballot(cur[k] < 0));
+    if ((tid & 63) == 0) s_tmp[w] = wave_total;
     __syncthreads();
     uint32_t pre = 0;
     for (int k = 0; k < w; ++k) pre += s_tmp[k];
@@ -131,17 +127,19 @@ __device__ __forceinline__ void alloc_exits(int (&cur)[VPT], uint32_t* s_tmp, ui
     __syncthreads();
     const uint32_t base = s_tmp[4];
     const bool ok = (uint64_t)base + total <= cap_exit;
-    uint32_t r = base + pre + inc - cnt;
+    uint32_t r0 = base + pre;  // first entry of this wave's k-th group (uniform)
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
-        if ((mask >> k) & 1u) {
-            const int e = -cur[k] - 1;
+        const uint64_t bal = __ballot(cur[k] < 0);
+        if (cur[k] < 0) {
+            const uint32_t r =
+                r0 + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
             // entries below the capacity are always written, so the list
             // never holds garbage even when this tile cannot use it
-            if (r < cap_exit) exits[r] = (uint32_t)e;
+            if (r < cap_exit) exits[r] = (uint32_t)(-cur[k] - 1);
             if (ok) cur[k] = exit_list_code(N, r);
-            ++r;
         }
+        r0 += (uint32_t)__popcll(bal);
     }
 }
 
@@ -343,15 +341,10 @@ __device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u,
 //   bit 31      the vertex itself (a maximum)
 constexpr uint32_t kSelfPack = 1u << 31;
 
-// Halo positions outside the grid read one of these words instead of the
-// field: NaN bit patterns whose key (bits_key, computed on the bits, so no
-// float operation can rewrite them) is 1 in the maximum and in the minimum
-// graph, below the key of every number.  The halo loads then need no
-// validity flag after they are issued.
-__device__ const uint32_t c_outside[2] = {0xFFFFFFFFu, 0x7FFFFFFFu};
-
 // mode_key on the bit pattern: -0 folded into +0 by an integer test, the same
-// order-preserving flip and clamp.
+// order-preserving flip and clamp (every vertex key is at least 1, so the
+// key 0 of positions outside the grid stays below all of them, NaN included:
+// no pointer can leave the grid).
 template <bool MINMODE>
 __device__ __forceinline__ uint32_t bits_key(uint32_t b)
 {
@@ -363,6 +356,29 @@ __device__ __forceinline__ uint32_t bits_key(uint32_t b)
 // Keys of numbers lie in [0x007FFFFF, 0xFF800000] in both graphs (-inf and
 // +inf at the ends); keys outside come from NaN patterns.
 __device__ __forceinline__ bool nan_key(uint32_t k) { return k < 0x007FFFFFu || k > 0xFF800000u; }
+
+// The key with its last four bits replaced by st (one instruction).
+template <int ST>
+__device__ __forceinline__ uint32_t bucket_step(uint32_t u)
+{
+    uint32_t r;
+    asm("v_and_or_b32 %0, %1, -16, %2" : "=v"(r) : "v"(u), "n"(ST));
+    return r;
+}
+
+// up = 2 up + (u above c): the comparison's lane mask is the carry of an add
+// that doubles the mask, two instructions per row; a neighbour that wins ties
+// is above at equal keys.
+template <bool WINS_TIE>
+__device__ __forceinline__ uint32_t push_above(uint32_t up, uint32_t u, uint32_t c)
+{
+    uint32_t r;
+    if constexpr (WINS_TIE)
+        asm("v_cmp_ge_u32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, %3, %3, vcc" : "=v"(r) : "v"(u), "v"(c), "v"(up) : "vcc");
+    else
+        asm("v_cmp_gt_u32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, %3, %3, vcc" : "=v"(r) : "v"(u), "v"(c), "v"(up) : "vcc");
+    return r;
+}
 template <int TY, int HY, int HX>
 __device__ __forceinline__ constexpr uint32_t succ_pack(int dz, int dy, int dx)
 {
@@ -381,8 +397,8 @@ struct Win {
     static constexpr int plane = dz + 1;
 };
 
-template <bool MINMODE, int TY, int TZ>
-__device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, uint32_t* s_conn, uint32_t* s_tmp)
+template <bool MINMODE, int TY, int TZ, bool FULL>
+__device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* s_u, uint32_t* s_conn, uint32_t* s_tmp)
 {
     constexpr int K = 14;
     constexpr int TX = 64;
@@ -402,6 +418,7 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
     // per row (and K = the vertex itself): packed successor and global offset
     uint32_t* s_pack = s_tmp + 8;
     int32_t* s_gdel = reinterpret_cast<int32_t*>(s_tmp + 8 + 16);
+    int32_t* s_hoff = reinterpret_cast<int32_t*>(s_tmp + 8 + 32);  // halo index offset
 
     // the wave index is uniform: keep it (and every row quantity) scalar
     const int tid = threadIdx.x, lx = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -413,42 +430,53 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
     const int SY = X;
     const int SZ = X * Y;
     if (tid <= K) {
+        // entry st: the candidate visited at step st (the vertex itself at K / 2)
+        const int pos = MINMODE ? K - tid : tid;
         uint32_t pk = kSelfPack;
-        int gd = 0;
-        if (tid < K) {
-            const int dz = (int)((Pack<3>::z >> (2 * tid)) & 3u) - 1;
-            const int dy = (int)((Pack<3>::y >> (2 * tid)) & 3u) - 1;
-            const int dx = (int)((Pack<3>::x >> (2 * tid)) & 3u) - 1;
+        int gd = 0, ho = 0;
+        if (pos != K / 2) {
+            const int j = pos < K / 2 ? pos : pos - 1;
+            const int dz = (int)((Pack<3>::z >> (2 * j)) & 3u) - 1;
+            const int dy = (int)((Pack<3>::y >> (2 * j)) & 3u) - 1;
+            const int dx = (int)((Pack<3>::x >> (2 * j)) & 3u) - 1;
             pk = succ_pack<TY, HY, HX>(dz, dy, dx);
             gd = dz * SZ + dy * SY + dx;
+            ho = (dz * HY + dy) * HX + dx;
         }
         s_pack[tid] = pk;
         s_gdel[tid] = gd;
+        s_hoff[tid] = ho;
     }
 
     bool nan = false;
     {
         // every load of this thread is issued before the first one is used:
-        // rows of 64 aligned values (one per lane), then the two edge columns
-        // of every row (one value per thread); positions outside the grid
-        // read the outside word
+        // rows of 64 aligned values (one per lane) from a uniform row address,
+        // then the two edge columns of every row (one value per thread);
+        // positions outside the grid get the sentinel key 0
         constexpr int ROWS = HY * HZ;
         constexpr int RPW = (ROWS + 3) / 4;
         constexpr int EDGES = 2 * ROWS;
         static_assert(EDGES <= 256, "one edge value per thread");
+        static_assert(RPW <= 32, "row flags fit a word");
         const uint32_t* __restrict__ fb = reinterpret_cast<const uint32_t*>(f);
-        const uint32_t* outside = &c_outside[MINMODE ? 1 : 0];
         const int gx = x0 + lx;
         const bool xin = gx < X;
+        const int gxc = FULL ? gx : (xin ? gx : X - 1);  // lanes past the grid read a safe address
+        const uint32_t lane_boff = 4u * (uint32_t)gxc;
         uint32_t vals[RPW];
+        uint32_t rin_bits = 0;  // rows of this wave inside the grid (bit i)
 #pragma unroll
         for (int i = 0; i < RPW; ++i) {
             const int row = wv + 4 * i;
             const int hy = row % HY, hz = row / HY;
             const int gy = y0 + hy - 1, gz = z0 + hz - 1;
-            const bool vin = row < ROWS && xin && (unsigned)gy < (unsigned)Y && (unsigned)gz < (unsigned)Z;
-            vals[i] = *(vin ? fb + (gz * SZ + gy * SY + gx) : outside);
+            const bool rin = row < ROWS && (unsigned)gy < (unsigned)Y && (unsigned)gz < (unsigned)Z;
+            rin_bits |= (rin ? 1u : 0u) << i;
+            const char* rowp = reinterpret_cast<const char*>(fb + (rin ? (int64_t)gz * SZ + (int64_t)gy * SY : 0));
+            vals[i] = *reinterpret_cast<const uint32_t*>(rowp + lane_boff);
         }
+        rin_bits = __builtin_amdgcn_readfirstlane(rin_bits);
         // edge value of this thread: row tid >> 1, left (x0 - 1) or right (x0 + 64)
         const int erow = tid >> 1;
         const int ehy = erow % HY, ehz = erow / HY;
@@ -456,16 +484,17 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
         const int egy = y0 + ehy - 1, egz = z0 + ehz - 1;
         const bool ein = tid < EDGES && (unsigned)egx < (unsigned)X && (unsigned)egy < (unsigned)Y &&
                          (unsigned)egz < (unsigned)Z;
-        const uint32_t eval = *(ein ? fb + (egz * SZ + egy * SY + egx) : outside);
+        const uint32_t eval = fb[ein ? egz * SZ + egy * SY + egx : 0];
         const uint32_t conn_a = c_conn3.w[tid], conn_b = c_conn3.w[tid + 256];
         s_conn[tid] = conn_a;
         s_conn[tid + 256] = conn_b;
 #pragma unroll
         for (int i = 0; i < RPW; ++i) {
             const int row = wv + 4 * i;
-            if (row < ROWS) s_u[row * HX + lx + 1] = bits_key<MINMODE>(vals[i]);
+            const bool ok = ((rin_bits >> i) & 1u) && (FULL || xin);
+            if (row < ROWS) s_u[row * HX + lx + 1] = ok ? bits_key<MINMODE>(vals[i]) : 0u;
         }
-        if (tid < EDGES) s_u[erow * HX + ((tid & 1) ? HX - 1 : 0)] = bits_key<MINMODE>(eval);
+        if (tid < EDGES) s_u[erow * HX + ((tid & 1) ? HX - 1 : 0)] = ein ? bits_key<MINMODE>(eval) : 0u;
     }
     __syncthreads();
 
@@ -501,37 +530,61 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
         for (int lz = 0; lz < TZ; ++lz) {
             load_plane(win[(lz + 2) % 3], lz + 2);
             const int gz = z0 + lz;
-            const bool in = gx < X && gy < Y && gz < Z;
+            const bool in = FULL || (gx < X && gy < Y && gz < Z);
             const uint32_t uv = win[(lz + 1) % 3][3];
             nan |= in && nan_key(uv);
             // upper-link mask in two 7-row halves (bit constants stay inline)
-            uint32_t up_lo = 0, up_hi = 0, best_u = 0;
-            int best_j = K;  // the steepest candidate so far; K is the vertex itself
+            // upper-link mask: row 13 first, so that row j ends in bit j; each
+            // row's comparison is the carry of an add that doubles the mask
+            uint32_t up = 0;
+            static_for<0, K>([&](auto step) {
+                constexpr int j = K - 1 - decltype(step)::value;
+                using WJ = Win<3, j>;
+                constexpr bool wins_tie = (j >= K / 2) != MINMODE;
+                up = push_above<wins_tie>(up, win[(lz + WJ::plane) % 3][WJ::pos], uv);
+            });
+            // steepest candidate: the maximum of (key with its last four bits
+            // replaced by the visiting step), so that equal keys go to the
+            // later step; exact unless a key 1..15 units below the maximum
+            // sits at a later step than it, which the check below catches
+            uint32_t pbest = 0, kbest = 0;
             static_for<0, K + 1>([&](auto step) {
                 constexpr int st = decltype(step)::value;
                 constexpr int pos = MINMODE ? K - st : st;
+                uint32_t u;
                 if constexpr (pos == K / 2) {
-                    if (uv >= best_u) {
-                        best_u = uv;
-                        best_j = K;
-                    }
+                    u = uv;
                 } else {
                     constexpr int j = pos < K / 2 ? pos : pos - 1;
                     using WJ = Win<3, j>;
-                    constexpr bool wins_tie = (j >= K / 2) != MINMODE;
-                    const uint32_t u = win[(lz + WJ::plane) % 3][WJ::pos];
-                    const bool above = wins_tie ? (u >= uv) : (u > uv);
-                    if constexpr (j < 7)
-                        up_lo |= above ? (1u << j) : 0u;
-                    else
-                        up_hi |= above ? (1u << (j - 7)) : 0u;
-                    if (u >= best_u) {
-                        best_u = u;
-                        best_j = j;
-                    }
+                    u = win[(lz + WJ::plane) % 3][WJ::pos];
                 }
+                pbest = max(pbest, bucket_step<st>(u));
+                kbest = max(kbest, u);
             });
-            const uint32_t up = up_lo | (up_hi << 7);
+            int best_st = (int)(pbest & 15u);
+            const int cidx = ((lz + 1) * HY + ly + 1) * HX + lx + 1;
+            if (s_u[cidx + s_hoff[best_st]] != kbest) {
+                // a near tie decided by the dropped bits: the exact scan
+                uint32_t bu = 0;
+                static_for<0, K + 1>([&](auto step) {
+                    constexpr int st = decltype(step)::value;
+                    constexpr int pos = MINMODE ? K - st : st;
+                    uint32_t u;
+                    if constexpr (pos == K / 2) {
+                        u = uv;
+                    } else {
+                        constexpr int j = pos < K / 2 ? pos : pos - 1;
+                        using WJ = Win<3, j>;
+                        u = win[(lz + WJ::plane) % 3][WJ::pos];
+                    }
+                    if (u >= bu) {
+                        bu = u;
+                        best_st = st;
+                    }
+                });
+            }
+            const int best_j = best_st;  // the successor tables are indexed by visiting step
             const bool is_max = in && up == 0;
             const bool is_sad = in && up != 0 && !((s_conn[up >> 5] >> (up & 31)) & 1u);
             const int v = gz * SZ + gy * SY + gx;
@@ -583,10 +636,25 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
         for (int lz = 0; lz < TZ; ++lz) {
             const int gz = z0 + lz;
             const int n = nxt[c * TZ + lz];
-            if (gx < X && gy < Y && gz < Z)
+            if (FULL || (gx < X && gy < Y && gz < Z))
                 lab[tile0 + s_rowoff[lz * TY + ly] + lx] = n >= 0 ? tile0 + s_rowoff[n >> 6] + (n & 63) : n;
         }
     }
+}
+
+// Full tiles (every vertex in the grid, the common case) run a variant without
+// per-vertex bounds tests.
+template <bool MINMODE, int TY, int TZ>
+__device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, uint32_t* s_conn, uint32_t* s_tmp)
+{
+    const int tx = b % a.tiles_x;
+    const int rr = b / a.tiles_x;
+    const int ty = rr % a.tiles_y;
+    const int tz = rr / a.tiles_y;
+    if ((tx + 1) * 64 <= a.X && (ty + 1) * TY <= a.Y && (tz + 1) * TZ <= a.Z)
+        tile3d_body<MINMODE, TY, TZ, true>(a, b, s_u, s_conn, s_tmp);
+    else
+        tile3d_body<MINMODE, TY, TZ, false>(a, b, s_u, s_conn, s_tmp);
 }
 
 // Tiles of one XCD are consecutive in memory: workgroups are dispatched to
@@ -699,23 +767,25 @@ hipError_t launch_final_tiled_batched(const BatchPlan* dplan, const BatchPlan& h
     return hipGetLastError();
 }
 
+// The tiles [first, first + count): every tile of the grid, or the tile rows
+// of one slab of a streamed build.
 template <bool MINMODE, int TY, int TZ>
-__global__ __launch_bounds__(256) void k_classify3d(TileArgs a)
+__global__ __launch_bounds__(256) void k_classify3d(TileArgs a, int first, int count)
 {
     constexpr int HALO = 66 * (TY + 2) * (TZ + 2);
     __shared__ uint32_t s_u[HALO];
     __shared__ uint32_t s_conn[512];
-    __shared__ uint32_t s_tmp[40];
-    tile3d<MINMODE, TY, TZ>(a, xcd_tile(blockIdx.x, a.ntiles), s_u, s_conn, s_tmp);
+    __shared__ uint32_t s_tmp[64];
+    tile3d<MINMODE, TY, TZ>(a, first + xcd_tile(blockIdx.x, count), s_u, s_conn, s_tmp);
 }
 
 template <bool MINMODE, int TY>
-__global__ __launch_bounds__(256) void k_classify2d(TileArgs a)
+__global__ __launch_bounds__(256) void k_classify2d(TileArgs a, int first, int count)
 {
     __shared__ uint32_t s_u[66 * (TY + 2)];
     __shared__ int32_t s_nxt[64 * TY];
     __shared__ uint32_t s_tmp[8];
-    tile_nd<2, MINMODE, TY, 1>(a, xcd_tile(blockIdx.x, a.ntiles), s_u, s_nxt, nullptr, s_tmp);
+    tile_nd<2, MINMODE, TY, 1>(a, first + xcd_tile(blockIdx.x, count), s_u, s_nxt, nullptr, s_tmp);
 }
 
 TileArgs tile_args(const float* f, const Grid& g, int32_t* lab, int32_t* ptr, const Work& w, int ty, int tz)
@@ -750,7 +820,7 @@ __global__ __launch_bounds__(256) void k_classify_batched(const BatchPlan* __res
     constexpr int WORDS = NDIM == 3 ? HALO3 : HALO2 + 64 * TY;
     __shared__ uint32_t s_u[WORDS];
     __shared__ uint32_t s_conn[NDIM == 3 ? 512 : 1];
-    __shared__ uint32_t s_tmp[40];
+    __shared__ uint32_t s_tmp[64];
     const EG_GPTR(BatchField) fs = plan->fields;
     const int f0 = plan->class_field[cls], f1 = plan->class_field[cls + 1];
     const int64_t item = plan->class_tile[cls] + blockIdx.x;
@@ -806,21 +876,21 @@ hipError_t launch_classify_batched(const BatchPlan* dplan, const BatchPlan& hpla
 }
 
 template <int TY, int TZ>
-static void launch_3d(const TileArgs& a, bool minima, hipStream_t s)
+static void launch_3d(const TileArgs& a, bool minima, int first, int count, hipStream_t s)
 {
     if (minima)
-        hipLaunchKernelGGL((k_classify3d<true, TY, TZ>), dim3(a.ntiles), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_classify3d<true, TY, TZ>), dim3(count), dim3(256), 0, s, a, first, count);
     else
-        hipLaunchKernelGGL((k_classify3d<false, TY, TZ>), dim3(a.ntiles), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_classify3d<false, TY, TZ>), dim3(count), dim3(256), 0, s, a, first, count);
 }
 
 template <int TY>
-static void launch_2d(const TileArgs& a, bool minima, hipStream_t s)
+static void launch_2d(const TileArgs& a, bool minima, int first, int count, hipStream_t s)
 {
     if (minima)
-        hipLaunchKernelGGL((k_classify2d<true, TY>), dim3(a.ntiles), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_classify2d<true, TY>), dim3(count), dim3(256), 0, s, a, first, count);
     else
-        hipLaunchKernelGGL((k_classify2d<false, TY>), dim3(a.ntiles), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_classify2d<false, TY>), dim3(count), dim3(256), 0, s, a, first, count);
 }
 
 hipError_t launch_final_tiled(const Grid& g, int32_t* lab, const Work& w, const Tuning& tu, int flag_slot,
@@ -848,23 +918,30 @@ hipError_t launch_final_tiled(const Grid& g, int32_t* lab, const Work& w, const 
 }
 
 hipError_t launch_classify_tiled(const float* f, const Grid& g, bool minima, int32_t* lab, int32_t* ptr,
-                                 const Work& w, const Tuning& tu, hipStream_t s)
+                                 const Work& w, const Tuning& tu, hipStream_t s, int64_t first, int64_t count)
 {
     int ty, tz;
     tile_shape(tu, g.ndim, &ty, &tz);
     const TileArgs a = tile_args(f, g, lab, ptr, w, ty, tz);
+    if (count < 0) {
+        first = 0;
+        count = a.ntiles;
+    }
+    if (first < 0 || first + count > a.ntiles) return hipErrorInvalidValue;
+    if (count == 0) return hipSuccess;
+    const int f0 = (int)first, n = (int)count;
     if (g.ndim == 3) {
         if (tu.tile3 == 1)
-            launch_3d<4, 16>(a, minima, s);
+            launch_3d<4, 16>(a, minima, f0, n, s);
         else if (tu.tile3 == 2)
-            launch_3d<8, 4>(a, minima, s);
+            launch_3d<8, 4>(a, minima, f0, n, s);
         else
-            launch_3d<8, 8>(a, minima, s);
+            launch_3d<8, 8>(a, minima, f0, n, s);
     } else if (g.ndim == 2) {
         if (tu.tile2 == 1)
-            launch_2d<16>(a, minima, s);
+            launch_2d<16>(a, minima, f0, n, s);
         else
-            launch_2d<32>(a, minima, s);
+            launch_2d<32>(a, minima, f0, n, s);
     } else {
         return hipErrorInvalidValue;
     }

@@ -36,6 +36,7 @@ struct Tuning {
     int tile2;  // 0: 64x32, 1: 64x16
     int hops;   // links per label pass
     int passes; // passes that cover any path of fewer than 2^31 links
+    int64_t exit_cap;  // most exit-list entries (0: the default capacity)
 };
 bool decode_tuning(uint32_t t, Tuning* out);
 // Label passes for a grid of n vertices: a steepest-ascent path has fewer
@@ -157,6 +158,10 @@ struct ArcArgs {
     int32_t dims[EG_MAX_NDIM];
     uint32_t cap_max, cap_sad, cap_arc;
     int32_t arc_blocks;  // blocks of this field in the stage (d) kernels (<= kArcBlocks)
+    int32_t pad0;
+    // "not converged" flag of the last label pass (set: some label is still
+    // a code, the header reports EG_ERR_UNRESOLVED); null: not checked
+    EG_GPTR(const uint32_t) last_flag;
 };
 
 // The outputs of eg_paths for one field.
@@ -202,7 +207,7 @@ int make_rows(int ndim, int8_t (*off)[EG_MAX_NDIM], uint64_t* adj);
 void make_table(const Grid& g, LinkTable* t);
 // Host: carve (or size, when base == nullptr) the workspace of a grid with N
 // vertices.
-Work carve(void* base, int ndim, int64_t N, int64_t X, int64_t cap_sad);
+Work carve(void* base, int ndim, int64_t N, int64_t X, int64_t cap_sad, int64_t exit_cap = 0);
 // Exit-list capacity for a grid of N vertices (label codes need N + cap < 2^31).
 int64_t exit_capacity(int64_t N);
 // Bits needed to hold any vertex id of a grid with N vertices.
@@ -257,8 +262,11 @@ __device__ __forceinline__ bool row_wins_tie(int j, int k)
 hipError_t launch_init(uint32_t* ctr, int32_t* header, hipStream_t s);
 hipError_t launch_classify(const float* f, const Grid& g, const LinkTable& t, bool minima, int32_t* lab,
                            int32_t* ptr, const Work& w, const Tuning& tu, hipStream_t s);
+// Classification of the 2D/3D tiles [first, first + count) (tiles in C order:
+// tile rows along axis 0 are contiguous ranges); count < 0: every tile.
 hipError_t launch_classify_tiled(const float* f, const Grid& g, bool minima, int32_t* lab, int32_t* ptr,
-                                 const Work& w, const Tuning& tu, hipStream_t s);
+                                 const Work& w, const Tuning& tu, hipStream_t s, int64_t first = 0,
+                                 int64_t count = -1);
 TileArgs tile_args(const float* f, const Grid& g, int32_t* lab, int32_t* ptr, const Work& w, int ty, int tz);
 ArcArgs arc_args(const float* f, const Grid& g, const eg_out& o, const Work& w);
 uint32_t arc_blocks(int64_t N);

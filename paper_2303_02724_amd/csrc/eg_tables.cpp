@@ -78,7 +78,9 @@ bool decode_tuning(uint32_t t, Tuning* out)
     u.tile3 = (int)(t & 0xFu);
     u.tile2 = (int)((t >> 4) & 0xFu);
     const int h = (int)((t >> 8) & 0xFFu);
-    if ((t >> 16) != 0 || u.tile3 > 2 || u.tile2 > 1) return false;
+    const int e = (int)((t >> 16) & 0x1Fu);
+    if ((t >> 21) != 0 || u.tile3 > 2 || u.tile2 > 1 || e > 30) return false;
+    u.exit_cap = e == 0 ? 0 : int64_t(1) << e;
     u.hops = h == 0 ? kJumpHops : h;
     if (u.hops != 16 && u.hops != 32 && u.hops != 64 && u.hops != 128) return false;
     int bits = 0;
@@ -100,10 +102,11 @@ int64_t exit_capacity(int64_t N)
     return std::max<int64_t>(0, std::min(cap, room));
 }
 
-Work carve(void* base, int ndim, int64_t N, int64_t X, int64_t cap_sad)
+Work carve(void* base, int ndim, int64_t N, int64_t X, int64_t cap_sad, int64_t exit_cap)
 {
     Work w{};
     w.cap_exit = exit_capacity(N);
+    if (exit_cap > 0) w.cap_exit = std::min(w.cap_exit, exit_cap);
     w.words = mask_words(N, X);
     size_t off = 0;
     auto take = [&](size_t bytes) {

@@ -24,12 +24,14 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libeg_hip.so")
 
-EG_OK, EG_ERR_ARG, EG_ERR_TOO_LARGE, EG_ERR_WORKSPACE, EG_ERR_NAN, EG_ERR_CAPACITY, EG_ERR_HIP, EG_ERR_SCRATCH = range(8)
+(EG_OK, EG_ERR_ARG, EG_ERR_TOO_LARGE, EG_ERR_WORKSPACE, EG_ERR_NAN, EG_ERR_CAPACITY, EG_ERR_HIP, EG_ERR_SCRATCH,
+ EG_ERR_UNRESOLVED) = range(9)
 
 
-def tuning(tile3: int = 0, tile2: int = 0, hops: int = 0) -> int:
-    """eg_out.tuning value (EG_TUNE_TILE3 | EG_TUNE_TILE2 | EG_TUNE_HOPS)."""
-    return (tile3 & 0xF) | ((tile2 & 0xF) << 4) | ((hops & 0xFF) << 8)
+def tuning(tile3: int = 0, tile2: int = 0, hops: int = 0, exits_log2: int = 0) -> int:
+    """eg_out.tuning value (EG_TUNE_TILE3 | EG_TUNE_TILE2 | EG_TUNE_HOPS |
+    EG_TUNE_EXITS)."""
+    return (tile3 & 0xF) | ((tile2 & 0xF) << 4) | ((hops & 0xFF) << 8) | ((exits_log2 & 0x1F) << 16)
 EG_MINIMA = 0x1
 EG_MAX_NDIM = 6
 H_STATUS, H_NMAX, H_NSAD, H_NARC, H_NPAIRS, H_PASSES, H_EXITS = range(7)
@@ -111,6 +113,9 @@ def lib():
         fn = getattr(L, name)
         fn.argtypes = [vp, ctypes.c_int, i64p, vp, ctypes.POINTER(eg_out)]
         fn.restype = ctypes.c_int
+    L.eg_build_streamed.argtypes = [vp, vp, ctypes.c_int, i64p, ctypes.c_int64, vp, vp, vp, ctypes.c_int64,
+                                    ctypes.POINTER(eg_out)]
+    L.eg_build_streamed.restype = ctypes.c_int
     L.eg_noalloc_scratch_bytes.argtypes = []
     L.eg_noalloc_scratch_bytes.restype = ctypes.c_size_t
     L.eg_paths.argtypes = [vp, ctypes.c_int, i64p, vp, ctypes.POINTER(eg_out), ctypes.POINTER(eg_paths_out)]
@@ -342,6 +347,35 @@ class Builder:
             raise EGError(st)
         self._stream = s
 
+    def launch_streamed(self, host: torch.Tensor, slab_planes: int, stream=None, copy_stream=None):
+        """Queue eg_build_streamed: ``host`` (float32, pinned, this builder's
+        shape) is copied to the builder's device field slab by slab on
+        ``copy_stream`` while ``stream`` classifies the slabs that have
+        landed.  Returns the device field."""
+        if host.is_cuda or host.dtype != torch.float32 or not host.is_contiguous() or host.numel() != self.n:
+            raise EGError(EG_ERR_ARG, "host field must be a contiguous float32 CPU tensor of the builder's shape")
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        cs = getattr(self, "_copy_stream", None) if copy_stream is None else copy_stream
+        if cs is None:
+            cs = self._copy_stream = torch.cuda.Stream(device=self.device)
+        if getattr(self, "field_dev", None) is None:
+            self.field_dev = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        nslabs = -(-self.shape[0] // max(1, int(slab_planes)))
+        evs = getattr(self, "_slab_events", [])
+        while len(evs) < nslabs + 1:
+            ev = torch.cuda.Event()
+            ev.record(s)  # creates the event; the library records it again on the copy stream
+            evs.append(ev)
+        self._slab_events = evs
+        handles = (ctypes.c_void_p * len(evs))(*[ev.cuda_event for ev in evs])
+        st = lib().eg_build_streamed(ctypes.c_void_p(host.data_ptr()), ctypes.c_void_p(self.field_dev.data_ptr()),
+                                     len(self.shape), self._dims, int(slab_planes), ctypes.c_void_p(s.cuda_stream),
+                                     ctypes.c_void_p(cs.cuda_stream), handles, len(evs), ctypes.byref(self.out))
+        if st != EG_OK:
+            raise EGError(st, "eg_build_streamed")
+        self._stream = s
+        return self.field_dev
+
     def header_values(self):
         return [int(x) for x in self.header.cpu().tolist()]
 
@@ -438,6 +472,28 @@ class Builder:
             return self.finish()
         raise EGError(EG_ERR_CAPACITY, "capacity retries exhausted")
 
+    def run_streamed(self, host: torch.Tensor, slab_planes: int, max_retries: int = 4) -> EGResult:
+        """launch_streamed + finish, growing the buffers while the library
+        reports a capacity shortfall (the field is copied again)."""
+        for _ in range(max_retries + 1):
+            self.launch_streamed(host, slab_planes)
+            self._stream.synchronize()
+            h = self.header_values()
+            if h[H_STATUS] == EG_ERR_CAPACITY:
+                self.grow(h)
+                continue
+            return self.finish()
+        raise EGError(EG_ERR_CAPACITY, "capacity retries exhausted")
+
+
+def build_streamed(host: torch.Tensor, slab_planes: int = 32, minima: bool = False, want_ptr: bool = False,
+                   device=None, tuning: int = 0, **caps) -> EGResult:
+    """Extremum graph of a host-resident float32 field (2D or 3D; pinned memory
+    for the copy to overlap), copied slab by slab while earlier slabs are
+    classified (eg_build_streamed)."""
+    b = Builder(host.shape, minima=minima, want_ptr=want_ptr, device=device, tuning=tuning, **caps)
+    return b.run_streamed(host.contiguous(), slab_planes)
+
 
 class BatchBuilder:
     """Extremum graphs of many 2D/3D fields with one batched launch sequence.
@@ -510,7 +566,7 @@ class BatchBuilder:
         pb = int(L.eg_batch_plan_bytes(self.count))
         pinned = getattr(self, "_pinned", None)
         if pinned is None or pinned.numel() < pb:
-            pinned = torch.empty(max(pb, 1 << 16), dtype=torch.uint8).pin_memory()
+            pinned = torch.empty(max(pb, 1 << 16), dtype=torch.uint8, pin_memory=True)
             self._pinned = pinned
         host = pinned[:pb]
         fptrs = (ctypes.c_void_p * self.count)(*[f.data_ptr() for f in flo])

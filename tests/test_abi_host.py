@@ -78,7 +78,9 @@ def test_build_rejects_bad_arguments_on_host():
     assert L.eg_build(fake, 2, dims, None, ctypes.byref(o)) == eg.EG_ERR_ARG
     o.tuning = 0x700  # 7 links per pass is not offered
     assert L.eg_build(fake, 2, dims, None, ctypes.byref(o)) == eg.EG_ERR_ARG
-    o.tuning = eg.tuning(tile3=2, tile2=1, hops=128) | (1 << 20)  # unknown bits
+    o.tuning = eg.tuning(tile3=2, tile2=1, hops=128) | (1 << 21)  # unknown bits
+    assert L.eg_build(fake, 2, dims, None, ctypes.byref(o)) == eg.EG_ERR_ARG
+    o.tuning = eg.tuning(exits_log2=31)  # the exit list is capped at 2^1 .. 2^30 entries
     assert L.eg_build(fake, 2, dims, None, ctypes.byref(o)) == eg.EG_ERR_ARG
     o.tuning = 0
     o.cap_sad = 1 << 31
@@ -269,3 +271,16 @@ def test_noalloc_rejects_fields_beyond_its_scratch_on_host():
     huge = (ctypes.c_int64 * 2)(1 << 16, 1 << 16)
     assert L.eg_build_noalloc(fake, 2, huge, None, ctypes.byref(o)) == eg.EG_ERR_TOO_LARGE
     assert "scratch" in eg.status_string(eg.EG_ERR_SCRATCH)
+
+
+def test_streamed_build_rejects_bad_arguments_on_host():
+    L = eg.lib()
+    fake, fake2 = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    o = eg.eg_out()
+    dims = (ctypes.c_int64 * 3)(16, 16, 16)
+    evs = (ctypes.c_void_p * 4)(0x10, 0x20, 0x30, 0x40)
+    assert L.eg_build_streamed(None, fake2, 3, dims, 8, None, None, evs, 4, ctypes.byref(o)) == eg.EG_ERR_ARG
+    assert L.eg_build_streamed(fake, None, 3, dims, 8, None, None, evs, 4, ctypes.byref(o)) == eg.EG_ERR_ARG
+    assert L.eg_build_streamed(fake, fake2, 3, dims, 0, None, None, evs, 4, ctypes.byref(o)) == eg.EG_ERR_ARG
+    assert L.eg_build_streamed(fake, fake2, 4, dims, 8, None, None, evs, 4, ctypes.byref(o)) == eg.EG_ERR_ARG
+    assert L.eg_build_streamed(fake, fake2, 3, dims, 8, None, None, None, 4, ctypes.byref(o)) == eg.EG_ERR_ARG

@@ -201,37 +201,77 @@ def test_batched_replay_and_capacity_retry():
             assert_same(_result_np(r), o, KEYS, f"batched replay {f.shape}")
 
 
-def test_serving_mix_equals_alone():
-    """Continuous batching: every request's result in the mix equals the same
-    field built alone (exact), and admission never exceeds the budget."""
+def _pinned(f):
+    import torch
+    t = torch.empty(f.shape, dtype=torch.float32, pin_memory=True)
+    t.copy_(torch.from_numpy(np.ascontiguousarray(f)))
+    return t
+
+
+def test_serving_results_equal_the_oracle():
+    """Continuous batching with host-resident fields (copied to the device at
+    admission): every request's result equals the oracle's graph of its
+    field, exactly, for small 2D/3D fields and a 192^3 field, with exact and
+    with tiny starting capacities (requests then grow and run again), and
+    the server never holds more device memory than its budget."""
     import torch
     from paper_2303_02724_amd import eg, serving
     specs = W.batched_specs(count=6, side2=(40, 400), side3=(16, 64), meta_seed=11)
-    fields = [torch.from_numpy(W.batched_field(sp)).cuda() for sp in specs]
-    alone = [_result_np(eg.build(t)) for t in fields]
+    host = [W.batched_field(sp) for sp in specs]
+    host.append(W.gaussian_mixture((192, 192, 192), 17, n_gauss=8, noise=1e-3))
+    big = len(host) - 1
+    want = [O.extremum_graph(f) for f in host]
+    fields = [_pinned(f) for f in host]
     rng = np.random.default_rng(1)
     t, reqs = 0.0, []
-    for _ in range(60):
+    for i in range(60):
         t += rng.exponential(1 / 2000.0)
-        reqs.append((t, int(rng.integers(0, len(fields)))))
-    caps = {tuple(t.shape): {"cap_max": max(1, len(a["maxima"])), "cap_sad": max(1, len(a["saddles"])),
-                             "cap_arc": max(1, len(a["arc_maxima"]))}
-            for t, a in zip(fields, alone)}
-    budget = 3 * max(serving.footprint(eg.Builder(sh, **caps[sh])) for sh in caps)
+        reqs.append((t, big if i % 15 == 7 else int(rng.integers(0, big))))
+    caps = {f.shape: {"cap_max": max(1, len(w["maxima"])), "cap_sad": max(1, len(w["saddles"])),
+                      "cap_arc": max(1, len(w["arc_maxima"]))} for f, w in zip(host, want)}
+    budget = 3 * serving.footprint_of(host[big].shape, caps[host[big].shape])
     for caps_for, exact in ((lambda sh: caps[sh], True), (lambda sh: {"cap_max": 1, "cap_sad": 1,
                                                                        "cap_arc": 1}, False)):
         got = {}
         srv = serving.Server(hbm_budget=budget, max_slots=8, max_batch=4, lanes=2, caps_for=caps_for)
         st = srv.run(reqs, fields, on_done=lambda ri, b: got.__setitem__(ri, _result_np(b.finish())))
+        print(f"exact={exact}: {st.summary()}", flush=True)
         assert len(got) == len(reqs)
+        assert st.copied_bytes == sum(host[fi].nbytes for _, fi in reqs)  # every field crossed PCIe once
         if exact:
             assert st.peak_bytes <= budget  # admission respects the budget
             assert st.regrown == 0
         else:
             assert st.regrown > 0  # undersized requests grew and ran again
-        assert st.batches < len(reqs)  # requests were batched
         for ri, (_, fi) in enumerate(reqs):
-            assert_same(got[ri], alone[fi], KEYS, f"request {ri} field {fi}")
+            assert_same(got[ri], want[fi], KEYS, f"request {ri} field {fi} {host[fi].shape}")
+        del srv
+        torch.cuda.empty_cache()
+
+
+def test_serving_batches_a_large_field_alone_and_with_others():
+    """Device-resident fields arriving together are launched as batches of up
+    to max_batch: the 192^3 field is served inside a batch and, arriving on
+    its own later, as a single request; every result equals the oracle."""
+    import torch
+    from paper_2303_02724_amd import serving
+    specs = W.batched_specs(count=5, side2=(40, 300), side3=(16, 48), meta_seed=12)
+    host = [W.batched_field(sp) for sp in specs]
+    host.append(W.gaussian_mixture((192, 192, 192), 18, n_gauss=8, noise=1e-3))
+    big = len(host) - 1
+    want = [O.extremum_graph(f) for f in host]
+    fields = [torch.from_numpy(f).cuda() for f in host]
+    reqs = [(0.0, i) for i in (0, 1, big, 2, 3, 4, 0, 1)] + [(0.5, big)]
+    caps = {f.shape: {"cap_max": max(1, len(w["maxima"])), "cap_sad": max(1, len(w["saddles"])),
+                      "cap_arc": max(1, len(w["arc_maxima"]))} for f, w in zip(host, want)}
+    got, sizes = {}, {}
+    srv = serving.Server(max_slots=16, max_batch=4, lanes=2, caps_for=lambda sh: caps[sh])
+    st = srv.run(reqs, fields, on_done=lambda ri, b: got.__setitem__(ri, _result_np(b.finish())))
+    for d in st.done:
+        sizes[d.index] = d.size
+    assert sizes[2] > 1 and sizes[8] == 1, sizes
+    for ri, (_, fi) in enumerate(reqs):
+        assert_same(got[ri], want[fi], KEYS, f"request {ri} field {fi}")
 
 
 def test_every_tuning_gives_identical_results():
