@@ -73,25 +73,31 @@ def parse():
     return ap.parse_args()
 
 
-# sources that define each profiled kernel: a counter summary stays valid
-# only while these files are unchanged
+# sources that define each profiled kernel (or the whole path): a counter
+# summary stays valid only while these files are unchanged
 KERNEL_SOURCES = {"k_classify": ("eg_classify_tiled.hip", "eg_internal.h", "eg_rows.h")}
+
+
+def path_sources():
+    d = os.path.join(ROOT, "paper_2303_02724_amd", "csrc")
+    return tuple(sorted(n for n in os.listdir(d) if n.endswith((".hip", ".h", ".cpp"))))
 
 
 def kernel_source_hash(kernel: str = "k_classify") -> str:
     d = os.path.join(ROOT, "paper_2303_02724_amd", "csrc")
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES[kernel]:
+    for name in (path_sources() if kernel == "path" else KERNEL_SOURCES[kernel]):
         h.update(name.encode())
         with open(os.path.join(d, name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def recorded_counter(prefix: str, key: str, kernel: str, workload: str, tile3: int):
+def recorded_counter(prefix: str, key: str, kernel: str, workload: str, tile3):
     """A per-launch figure from a committed counter summary
     (profiles/<prefix>_<kernel>_<workload>.txt), used only if the summary was
-    taken on the current kernel sources and the same tile shape (else None)."""
+    taken on the current kernel sources and the same tile shape (else None;
+    tile3=None reads an unprefixed key)."""
     p = os.path.join(ROOT, "profiles", f"{prefix}_{kernel}_{workload}.txt")
     if not os.path.exists(p):
         return None
@@ -104,7 +110,7 @@ def recorded_counter(prefix: str, key: str, kernel: str, workload: str, tile3: i
     if vals.get("source_sha256") != kernel_source_hash(kernel):
         return None
     try:
-        return float(vals[f"tile3_{tile3}_{key}"])
+        return float(vals[key if tile3 is None else f"tile3_{tile3}_{key}"])
     except (KeyError, ValueError):
         return None
 
@@ -711,6 +717,17 @@ def main():
     # what actually limits the kernel: vector instruction issue (counted
     # wave64 instructions of one launch over its measured duration, against
     # 256 CUs x 4 SIMDs x 2.4 GHz with a wave64 instruction every 4 cycles)
+    # the whole path: counted HBM bytes of one step (all kernels, default
+    # launch configuration) over the live per-stage kernel time
+    pbytes = recorded_counter("traffic", "path_traffic_bytes_per_step", "path", cfg["workload"], None)
+    if pbytes is not None and (tuning & 0xF) == 0:
+        path_ms = sum(stages.values())
+        pg = pbytes / (path_ms * 1e-3) / 1e9
+        roof["path_rocprof"] = {"traffic_bytes_per_step": pbytes, "kernel_ms_per_step": round(path_ms, 4),
+                                "achieved": round(pg, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": round(pg / HBM_PEAK_GBS, 4),
+                                "note": "(FETCH_SIZE + WRITE_SIZE) of every kernel of one step / the sum of the "
+                                        "stage times; counts re-reads, unlike the 16 B/vertex effective_GBs"}
     valu = recorded_counter("valu", "sq_insts_valu_per_launch", "k_classify", cfg["workload"], tile3)
     if valu is not None:
         rate = valu / (cls_ms * 1e-3) / 1e9

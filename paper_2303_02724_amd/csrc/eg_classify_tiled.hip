@@ -69,33 +69,34 @@ struct Pack {
 // negative entries.
 
 // Resolve the tile's successor array by pointer jumping.  cur[k] holds the
-// successor of this thread's k-th vertex (s_idx(k) is its tile index): >= 0 a
-// tile index (a maximum is its own successor), < 0 the exit code of the first
-// vertex outside the tile.  Each round replaces every successor by the
-// successor's successor, in place: a value read is always a vertex further
-// along the same path (or its end), so a round needs no barrier between its
-// reads and writes, and only changed entries are written.  log2 of the
-// longest in-tile path bounds the rounds.  On return cur[k] is a tile-local
-// maximum (>= 0) or an exit code.  Must be called by the whole workgroup,
-// after s_nxt holds every successor.
-template <int VPT, class Idx>
+// successor of this thread's k-th vertex (s_idx(k) is its tile index): in
+// [0, TILE) a tile index, >= TILE a tile-local maximum (TILE + its own index),
+// < 0 the exit code of the first vertex outside the tile; the last two end a
+// chain.  Each round replaces every tile index by that vertex's successor, in
+// place: a value read is always a vertex further along the same path (or
+// its end), so a round needs no barrier between its reads and writes.  The
+// loop stops after the round in which every chain has reached its end (no
+// extra round to find that nothing changed); log2 of the longest in-tile path
+// bounds the rounds.  Must be called by the whole workgroup, after s_nxt
+// holds every successor.
+template <int VPT, int TILE, class Idx>
 __device__ __forceinline__ void double_tile_chains(int (&cur)[VPT], int32_t* s_nxt, Idx s_idx)
 {
-    for (;;) {
-        int changed = 0;
+    int pending = 0;
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) pending |= (unsigned)cur[k] < (unsigned)TILE;
+    while (__syncthreads_or(pending)) {
+        pending = 0;
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
             const int n = cur[k];
-            if (n >= 0) {
+            if ((unsigned)n < (unsigned)TILE) {
                 const int m = s_nxt[n];
-                if (m != n) {
-                    changed = 1;
-                    cur[k] = m;
-                    s_nxt[s_idx(k)] = m;
-                }
+                cur[k] = m;
+                s_nxt[s_idx(k)] = m;
+                pending |= (unsigned)m < (unsigned)TILE;
             }
         }
-        if (!__syncthreads_or(changed)) break;
     }
 }
 
@@ -174,6 +175,7 @@ __device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u,
     constexpr int TX = 64;
     constexpr int HX = TX + 2, HY = TY + 2, HZ = NDIM == 3 ? TZ + 2 : 1;
     constexpr int HALO = HX * HY * HZ;
+    constexpr int TILE = TX * TY * TZ;
     constexpr int YPT = TY / 4;
     constexpr int VPT = YPT * TZ;
     constexpr int ZH = NDIM == 3 ? 1 : 0;  // halo depth along z
@@ -238,7 +240,7 @@ __device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u,
         const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
         const bool in = gx < X && gy < Y && gz < Z;
         const int li = (lz * TY + ly) * TX + lx;
-        int n = li;  // vertices outside the grid stay put and are never written
+        int n = TILE + li;  // vertices outside the grid end their own chain and are never written
         bool is_max = false, is_sad = false;
         int v = 0;
         if (in) {
@@ -280,7 +282,7 @@ __device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u,
             v = gz * SZ + gy * SY + gx;
             int pv = v;
             if (best_j == K) {
-                n = li;  // a maximum points to itself
+                n = TILE + li;  // a maximum ends its chain
             } else {
                 const int dz = NDIM == 3 ? (int)((Pack<NDIM>::z >> (2 * best_j)) & 3u) - 1 : 0;
                 const int dy = (int)((Pack<NDIM>::y >> (2 * best_j)) & 3u) - 1;
@@ -313,7 +315,7 @@ __device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u,
     // read per vertex instead of quarter-rate multiplies)
     __shared__ int s_rowoff[TY * TZ];
     if (tid < TY * TZ) s_rowoff[tid] = (tid / TY) * SZ + (tid % TY) * SY;
-    double_tile_chains<VPT>(nxt, s_nxt, s_idx);
+    double_tile_chains<VPT, TILE>(nxt, s_nxt, s_idx);
     const int tile0 = z0 * SZ + y0 * SY + x0;
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
@@ -322,7 +324,7 @@ __device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u,
         const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
         const int n = nxt[k];
         if (gx < X && gy < Y && gz < Z)
-            lab[tile0 + s_rowoff[lz * TY + ly] + lx] = n >= 0 ? tile0 + s_rowoff[n >> 6] + (n & 63) : n;
+            lab[tile0 + s_rowoff[lz * TY + ly] + lx] = n >= 0 ? tile0 + s_rowoff[(n - TILE) >> 6] + (n & 63) : n;
     }
 }
 
@@ -589,7 +591,7 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
             const bool is_sad = in && up != 0 && !((s_conn[up >> 5] >> (up & 31)) & 1u);
             const int v = gz * SZ + gy * SY + gx;
             const int li = (lz * TY + ly) * TX + lx;
-            int n = li;  // a maximum, or a vertex outside the grid, stays put
+            int n = TILE + li;  // a maximum, or a vertex outside the grid, ends its own chain
             if (in) {
                 const uint32_t best_p = s_pack[best_j];
                 const int pv = v + s_gdel[best_j];
@@ -626,7 +628,7 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
     // two quarter-rate multiplies
     __shared__ int s_rowoff[TY * TZ];
     if (tid < TY * TZ) s_rowoff[tid] = (tid / TY) * SZ + (tid % TY) * SY;
-    double_tile_chains<VPT>(nxt, s_nxt, [&](int k) { return ((k % TZ) * TY + wv + 4 * (k / TZ)) * TX + lx; });
+    double_tile_chains<VPT, TILE>(nxt, s_nxt, [&](int k) { return ((k % TZ) * TY + wv + 4 * (k / TZ)) * TX + lx; });
     const int tile0 = z0 * SZ + y0 * SY + x0;
 #pragma unroll
     for (int c = 0; c < YPT; ++c) {
@@ -637,7 +639,7 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
             const int gz = z0 + lz;
             const int n = nxt[c * TZ + lz];
             if (FULL || (gx < X && gy < Y && gz < Z))
-                lab[tile0 + s_rowoff[lz * TY + ly] + lx] = n >= 0 ? tile0 + s_rowoff[n >> 6] + (n & 63) : n;
+                lab[tile0 + s_rowoff[lz * TY + ly] + lx] = n >= 0 ? tile0 + s_rowoff[(n - TILE) >> 6] + (n & 63) : n;
         }
     }
 }
