@@ -23,10 +23,16 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-fconstexpr-steps=200000000",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
+# Per-source flags.  The tiled classification claims exit-list space with one
+# atomic per tile and needs its value only after the tile's pointer doubling;
+# the compiler's atomic optimizer would rewrite that atomic so that its result
+# is awaited at once, stalling the workgroup on a device-wide round trip.
+EXTRA = {"eg_classify_tiled.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
+
 
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + FLAGS + EXTRA.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC, "-x", "hip"] + FLAGS + ["-c", src, "-o", obj]
     if verbose:

@@ -71,8 +71,8 @@ struct Pack {
 // Resolve the tile's successor array by pointer jumping.  cur[k] holds the
 // successor of this thread's k-th vertex (s_idx(k) is its tile index): in
 // [0, TILE) a tile index, >= TILE a tile-local maximum (TILE + its own index),
-// < 0 the exit code of the first vertex outside the tile; the last two end a
-// chain.  Each round replaces every tile index by that vertex's successor, in
+// < 0 the tile-local code of the exit by which the path leaves the tile; the
+// last two end a chain.  Each round replaces every tile index by that vertex's successor, in
 // place: a value read is always a vertex further along the same path (or
 // its end), so a round needs no barrier between its reads and writes.  The
 // loop stops after the round in which every chain has reached its end (no
@@ -102,16 +102,19 @@ __device__ __forceinline__ void double_tile_chains(int (&cur)[VPT], int32_t* s_n
 
 // Every vertex whose steepest step leaves the tile gets its own entry of the
 // exit list, which records the step's target; before the tile's chains are
-// resolved, cur[k] < 0 holds -(target + 1) for such a vertex.  Entries are
-// ranked without a scan: per k, a wave ballot of its exiting lanes, the
-// lane's rank among them (mbcnt) and the running count of the wave (scalar);
-// one atomic per tile places the tile's block.  cur[k] becomes the entry's
-// code, so the pointer doubling hands that code to every vertex whose path
-// leaves the tile there, and the label pass resolves each entry once.  A tile
-// that does not fit in the list keeps the vertex codes.
+// resolved, cur[k] < 0 holds -(target + 1) for such a vertex.  rank_exits
+// numbers the tile's exits without a scan: per k, a wave ballot of its
+// exiting lanes, the lane's rank among them (mbcnt) and the running count of
+// the wave (scalar).  The targets go to s_exv in rank order and cur[k] becomes
+// the tile-local code -(rank + 1), which the pointer doubling hands to every
+// vertex whose path leaves the tile there.  One atomic per tile claims the
+// tile's block of the list: thread 0 issues it here and first needs its value
+// in place_exits, after the doubling, so the round trip of a device-wide
+// atomic overlaps the doubling instead of stalling the workgroup.  Writes
+// s_exv after a barrier, so the caller may alias it with the halo.
 template <int VPT>
-__device__ __forceinline__ void alloc_exits(int (&cur)[VPT], uint32_t* s_tmp, uint32_t* __restrict__ ctr,
-                                            uint32_t* __restrict__ exits, uint32_t cap_exit, int N)
+__device__ __forceinline__ uint32_t rank_exits(int (&cur)[VPT], uint32_t* s_tmp, uint32_t* s_exv,
+                                               uint32_t* __restrict__ ctr, uint32_t& claim)
 {
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -120,28 +123,54 @@ __device__ __forceinline__ void alloc_exits(int (&cur)[VPT], uint32_t* s_tmp, ui
     for (int k = 0; k < VPT; ++k) wave_total += (uint32_t)__popcll(__ballot(cur[k] < 0));
     if ((tid & 63) == 0) s_tmp[w] = wave_total;
     __syncthreads();
-    uint32_t pre = 0;
-    for (int k = 0; k < w; ++k) pre += s_tmp[k];
+    uint32_t r0 = 0;  // first rank of this wave's k-th group (uniform)
+    for (int k = 0; k < w; ++k) r0 += s_tmp[k];
     const uint32_t total = s_tmp[0] + s_tmp[1] + s_tmp[2] + s_tmp[3];
-    __syncthreads();
-    if (tid == 0) s_tmp[4] = total ? atomicAdd(&ctr[C_NEXIT], total) : 0u;
-    __syncthreads();
-    const uint32_t base = s_tmp[4];
-    const bool ok = (uint64_t)base + total <= cap_exit;
-    uint32_t r0 = base + pre;  // first entry of this wave's k-th group (uniform)
+    claim = 0;
+    if (tid == 0 && total) claim = atomicAdd(&ctr[C_NEXIT], total);
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
         const uint64_t bal = __ballot(cur[k] < 0);
         if (cur[k] < 0) {
             const uint32_t r =
                 r0 + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-            // entries below the capacity are always written, so the list
-            // never holds garbage even when this tile cannot use it
-            if (r < cap_exit) exits[r] = (uint32_t)(-cur[k] - 1);
-            if (ok) cur[k] = exit_list_code(N, r);
+            s_exv[r] = (uint32_t)(-cur[k] - 1);
+            cur[k] = -(int)r - 1;
         }
         r0 += (uint32_t)__popcll(bal);
     }
+    return total;
+}
+
+// After the doubling: the tile's block of the exit list starts at the claimed
+// base; the block is written with coalesced stores.  Entries below the
+// capacity are always written, so the list never holds garbage even when the
+// tile's block does not fit; such a tile gives its vertices the vertex codes
+// of their exits' targets instead of list codes.  Returns whether it fit.
+__device__ __forceinline__ bool place_exits(uint32_t total, uint32_t claim, const uint32_t* s_exv, uint32_t* s_tmp,
+                                            uint32_t* __restrict__ exits, uint32_t cap_exit, uint32_t& base)
+{
+    const int tid = threadIdx.x;
+    if (tid == 0) s_tmp[4] = claim;
+    __syncthreads();
+    base = s_tmp[4];
+    for (uint32_t i = tid; i < total; i += 256)
+        if (base + i < cap_exit) exits[base + i] = s_exv[i];
+    return (uint64_t)base + total <= cap_exit;
+}
+
+// The offset that turns a tile-local exit code n < 0 into the label code of
+// its list entry: exit_list_code(N, base - n - 1) = n - (N + base).  A tile
+// whose block did not fit turns its codes into the vertex codes of the exits'
+// targets here instead (offset 0).
+template <int VPT>
+__device__ __forceinline__ int exit_offset(int (&cur)[VPT], bool fit, uint32_t base, const uint32_t* s_exv, int N)
+{
+    if (fit) return N + (int)base;
+#pragma unroll
+    for (int k = 0; k < VPT; ++k)
+        if (cur[k] < 0) cur[k] = -(int)s_exv[-cur[k] - 1] - 1;
+    return 0;
 }
 
 // Critical-vertex bitmasks: each wave handles one 64-vertex row segment of
@@ -152,9 +181,16 @@ __device__ __forceinline__ void alloc_exits(int (&cur)[VPT], uint32_t* s_tmp, ui
 __device__ __forceinline__ void park_word(uint64_t& mine, bool pred, int lane)
 {
     const uint64_t b = __ballot(pred);
-    if (__lane_id() == lane) mine = b;
+    uint32_t lo = (uint32_t)mine, hi = (uint32_t)(mine >> 32);
+    if (__lane_id() == lane) {
+        lo = (uint32_t)b;
+        hi = (uint32_t)(b >> 32);
+    }
+    // pin the word here: otherwise the selects sink to the final store and
+    // every step's two ballots stay alive in scalar registers until then
+    asm volatile("" : "+v"(lo), "+v"(hi));
+    mine = ((uint64_t)hi << 32) | lo;
 }
-
 __device__ __forceinline__ void store_words(const TileArgs& a, uint64_t word, int vpt, int row, bool row_in, int tx)
 {
     // row: the grid row (gz * Y + gy) of this lane's step; row_in: it exists
@@ -306,7 +342,8 @@ __device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u,
     }
     if (__ballot(nan) != 0 && __lane_id() == 0) atomicOr(&ctr[C_NAN], 1u);
     const int N = X * Y * Z;
-    alloc_exits<VPT>(nxt, s_tmp, ctr, a.exits, a.cap_exit, N);
+    uint32_t claim;
+    const uint32_t nexit = rank_exits<VPT>(nxt, s_tmp, s_u, ctr, claim);  // the halo is no longer read
     auto s_idx = [&](int k) { return ((k / YPT) * TY + wv + 4 * (k % YPT)) * TX + lx; };
 #pragma unroll
     for (int k = 0; k < VPT; ++k) s_nxt[s_idx(k)] = nxt[k];
@@ -316,6 +353,9 @@ __device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u,
     __shared__ int s_rowoff[TY * TZ];
     if (tid < TY * TZ) s_rowoff[tid] = (tid / TY) * SZ + (tid % TY) * SY;
     double_tile_chains<VPT, TILE>(nxt, s_nxt, s_idx);
+    uint32_t base;
+    const bool fit = place_exits(nexit, claim, s_u, s_tmp, a.exits, a.cap_exit, base);
+    const int xoff = exit_offset<VPT>(nxt, fit, base, s_u, N);
     const int tile0 = z0 * SZ + y0 * SY + x0;
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
@@ -324,7 +364,8 @@ __device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u,
         const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
         const int n = nxt[k];
         if (gx < X && gy < Y && gz < Z)
-            lab[tile0 + s_rowoff[lz * TY + ly] + lx] = n >= 0 ? tile0 + s_rowoff[(n - TILE) >> 6] + (n & 63) : n;
+            lab[tile0 + s_rowoff[lz * TY + ly] + lx] =
+                n >= 0 ? tile0 + s_rowoff[(n - TILE) >> 6] + (n & 63) : n - xoff;
     }
 }
 
@@ -339,14 +380,24 @@ __device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u,
 // the steepest candidate:
 //   bits 0..5   faces of the tile the step crosses if the vertex lies on them
 //               (x-, x+, y-, y+, z-, z+)
-//   bits 6..16  tile-local index offset (signed, 11 bits)
-//   bit 31      the vertex itself (a maximum)
-constexpr uint32_t kSelfPack = 1u << 31;
+//   bits 6..31  tile-local index offset (signed)
+// The vertex itself (a maximum) has no faces and the offset TILE, which turns
+// its own tile index into the chain end TILE + index.
+
+// Store to lane lx of a row whose first element sits at the uniform address
+// `row`: the address stays scalar and only the lane's byte offset lives in a
+// vector register.
+__device__ __forceinline__ void store_row(int32_t* row, uint32_t lane_b, int32_t v)
+{
+    *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(row) + lane_b) = v;
+}
 
 // mode_key on the bit pattern: -0 folded into +0 by an integer test, the same
 // order-preserving flip and clamp (every vertex key is at least 1, so the
 // key 0 of positions outside the grid stays below all of them, NaN included:
 // no pointer can leave the grid).
+__device__ __forceinline__ uint32_t max3u(uint32_t a, uint32_t b, uint32_t c) { return max(max(a, b), c); }
+
 template <bool MINMODE>
 __device__ __forceinline__ uint32_t bits_key(uint32_t b)
 {
@@ -387,7 +438,7 @@ __device__ __forceinline__ constexpr uint32_t succ_pack(int dz, int dy, int dx)
     const int loff = (dz * TY + dy) * 64 + dx;
     const uint32_t em = (dx < 0 ? 1u : 0u) | (dx > 0 ? 2u : 0u) | (dy < 0 ? 4u : 0u) | (dy > 0 ? 8u : 0u) |
                         (dz < 0 ? 16u : 0u) | (dz > 0 ? 32u : 0u);
-    return em | ((uint32_t(loff) & 0x7FFu) << 6);
+    return em | (uint32_t(loff) << 6);
 }
 
 template <int NDIM_, int J>
@@ -399,7 +450,7 @@ struct Win {
     static constexpr int plane = dz + 1;
 };
 
-template <bool MINMODE, int TY, int TZ, bool FULL>
+template <bool MINMODE, int TY, int TZ, bool FULL, bool PTR>
 __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* s_u, uint32_t* s_conn, uint32_t* s_tmp)
 {
     constexpr int K = 14;
@@ -409,8 +460,11 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
     constexpr int TILE = TX * TY * TZ;
     constexpr int YPT = TY / 4;
     constexpr int VPT = YPT * TZ;
-    static_assert(TILE <= HALO, "the chains reuse the halo's LDS");
+    // only vertices on the tile's faces can step out of it
+    constexpr int SURF = TILE - (TX - 2) * (TY - 2) * (TZ - 2);
+    static_assert(TILE + SURF <= HALO, "the chains and the exit targets reuse the halo's LDS");
     static_assert(TY % 4 == 0, "four waves split the y rows");
+    static_assert(((TY * TZ) & (TY * TZ - 1)) == 0, "row count is a power of two");
     const float* __restrict__ f = a.f;
     const int X = a.X, Y = a.Y, Z = a.Z;
     int32_t* __restrict__ lab = a.lab;
@@ -434,7 +488,7 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
     if (tid <= K) {
         // entry st: the candidate visited at step st (the vertex itself at K / 2)
         const int pos = MINMODE ? K - tid : tid;
-        uint32_t pk = kSelfPack;
+        uint32_t pk = (uint32_t)TILE << 6;
         int gd = 0, ho = 0;
         if (pos != K / 2) {
             const int j = pos < K / 2 ? pos : pos - 1;
@@ -507,6 +561,7 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
     // lx = 63), by shifts rather than compares, so that no lane mask has to
     // stay alive across the unrolled loop
     const uint32_t bx = ((uint32_t)(lx - 1) >> 31) | (((uint32_t)(lx + 1) >> 6) << 1);
+    const uint32_t lane_b = 4u * (uint32_t)lx;
 #pragma unroll
     for (int c = 0; c < YPT; ++c) {
         const int ly = wv + 4 * c;
@@ -549,60 +604,52 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
             // replaced by the visiting step), so that equal keys go to the
             // later step; exact unless a key 1..15 units below the maximum
             // sits at a later step than it, which the check below catches
-            uint32_t pbest = 0, kbest = 0;
+            uint32_t us[K + 1];  // the candidates by visiting step
             static_for<0, K + 1>([&](auto step) {
                 constexpr int st = decltype(step)::value;
                 constexpr int pos = MINMODE ? K - st : st;
-                uint32_t u;
                 if constexpr (pos == K / 2) {
-                    u = uv;
+                    us[st] = uv;
                 } else {
                     constexpr int j = pos < K / 2 ? pos : pos - 1;
                     using WJ = Win<3, j>;
-                    u = win[(lz + WJ::plane) % 3][WJ::pos];
+                    us[st] = win[(lz + WJ::plane) % 3][WJ::pos];
                 }
-                pbest = max(pbest, bucket_step<st>(u));
-                kbest = max(kbest, u);
             });
+            uint32_t pbest = 0;
+            static_for<0, K + 1>([&](auto step) {
+                constexpr int st = decltype(step)::value;
+                pbest = max(pbest, bucket_step<st>(us[st]));
+            });
+            // the exact maximum as a balanced tree of three-way maxima
+            const uint32_t kbest = max3u(max3u(max3u(us[0], us[1], us[2]), max3u(us[3], us[4], us[5]),
+                                               max3u(us[6], us[7], us[8])),
+                                         max3u(us[9], us[10], us[11]), max3u(us[12], us[13], us[14]));
             int best_st = (int)(pbest & 15u);
             const int cidx = ((lz + 1) * HY + ly + 1) * HX + lx + 1;
             if (s_u[cidx + s_hoff[best_st]] != kbest) {
-                // a near tie decided by the dropped bits: the exact scan
-                uint32_t bu = 0;
+                // a near tie decided by the dropped bits: the last step that
+                // holds the maximum
                 static_for<0, K + 1>([&](auto step) {
                     constexpr int st = decltype(step)::value;
-                    constexpr int pos = MINMODE ? K - st : st;
-                    uint32_t u;
-                    if constexpr (pos == K / 2) {
-                        u = uv;
-                    } else {
-                        constexpr int j = pos < K / 2 ? pos : pos - 1;
-                        using WJ = Win<3, j>;
-                        u = win[(lz + WJ::plane) % 3][WJ::pos];
-                    }
-                    if (u >= bu) {
-                        bu = u;
-                        best_st = st;
-                    }
+                    if (us[st] == kbest) best_st = st;
                 });
             }
-            const int best_j = best_st;  // the successor tables are indexed by visiting step
+            // every quantity below without a branch (the successor tables are
+            // indexed by visiting step; the table marks the empty link as no
+            // saddle, so a maximum needs no test of its own)
             const bool is_max = in && up == 0;
-            const bool is_sad = in && up != 0 && !((s_conn[up >> 5] >> (up & 31)) & 1u);
-            const int v = gz * SZ + gy * SY + gx;
+            const bool is_sad = in && !((s_conn[up >> 5] >> (up & 31)) & 1u);
+            const uint32_t best_p = s_pack[best_st];
+            const int row0 = gz * SZ + gy * SY + x0;  // uniform
+            const int pv = row0 + lx + s_gdel[best_st];
             const int li = (lz * TY + ly) * TX + lx;
-            int n = TILE + li;  // a maximum, or a vertex outside the grid, ends its own chain
-            if (in) {
-                const uint32_t best_p = s_pack[best_j];
-                const int pv = v + s_gdel[best_j];
-                if (!(best_p & kSelfPack)) {
-                    // leaves the tile iff it steps across a face the vertex lies on
-                    const uint32_t faces = bb_xy | (lz == 0 ? 16u : 0u) | (lz == TZ - 1 ? 32u : 0u);
-                    const int loff = (int)(best_p << 15) >> 21;
-                    n = (faces & best_p & 63u) ? -(pv + 1) : li + loff;
-                }
-                if (ptr) ptr[v] = pv;
-            }
+            // leaves the tile iff it steps across a face the vertex lies on
+            const uint32_t faces = bb_xy | (lz == 0 ? 16u : 0u) | (lz == TZ - 1 ? 32u : 0u);
+            int n = (faces & best_p & 63u) ? -(pv + 1) : li + ((int)best_p >> 6);
+            if constexpr (!FULL) n = in ? n : TILE + li;  // a vertex outside the grid ends its own chain
+            if constexpr (PTR)
+                if (in) store_row(ptr + row0, lane_b, pv);
             nxt[c * TZ + lz] = n;
             park_word(word, is_max, c * TZ + lz);
             park_word(word, is_sad, 32 + c * TZ + lz);
@@ -614,7 +661,9 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
         store_words(a, word, VPT, (z0 + lz) * Y + y0 + ly, y0 + ly < Y && z0 + lz < Z, tx);
     }
     if (__ballot(nan) != 0 && __lane_id() == 0) atomicOr(&ctr[C_NAN], 1u);
-    alloc_exits<VPT>(nxt, s_tmp, ctr, a.exits, a.cap_exit, X * Y * Z);  // has barriers: the halo is no longer read
+    // exit targets go behind the chains, in LDS the halo no longer needs
+    uint32_t claim;
+    const uint32_t nexit = rank_exits<VPT>(nxt, s_tmp, s_u + TILE, ctr, claim);
 #pragma unroll
     for (int c = 0; c < YPT; ++c)
 #pragma unroll
@@ -629,6 +678,9 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
     __shared__ int s_rowoff[TY * TZ];
     if (tid < TY * TZ) s_rowoff[tid] = (tid / TY) * SZ + (tid % TY) * SY;
     double_tile_chains<VPT, TILE>(nxt, s_nxt, [&](int k) { return ((k % TZ) * TY + wv + 4 * (k / TZ)) * TX + lx; });
+    uint32_t base;
+    const bool fit = place_exits(nexit, claim, s_u + TILE, s_tmp, a.exits, a.cap_exit, base);
+    const int xoff = exit_offset<VPT>(nxt, fit, base, s_u + TILE, X * Y * Z);
     const int tile0 = z0 * SZ + y0 * SY + x0;
 #pragma unroll
     for (int c = 0; c < YPT; ++c) {
@@ -638,14 +690,18 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
         for (int lz = 0; lz < TZ; ++lz) {
             const int gz = z0 + lz;
             const int n = nxt[c * TZ + lz];
+            // the row offset is read for every vertex (masked into range), so
+            // that the label is a select rather than a branch
+            const int ro = s_rowoff[((uint32_t)(n - TILE) >> 6) & (TY * TZ - 1)];
             if (FULL || (gx < X && gy < Y && gz < Z))
-                lab[tile0 + s_rowoff[lz * TY + ly] + lx] = n >= 0 ? tile0 + s_rowoff[(n - TILE) >> 6] + (n & 63) : n;
+                store_row(lab + (gz * SZ + gy * SY + x0), lane_b, n >= 0 ? tile0 + ro + (n & 63) : n - xoff);
         }
     }
 }
 
 // Full tiles (every vertex in the grid, the common case) run a variant without
-// per-vertex bounds tests.
+// per-vertex bounds tests; whether pointers are written is a compile-time
+// choice too, which keeps the output address out of the unrolled loop.
 template <bool MINMODE, int TY, int TZ>
 __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, uint32_t* s_conn, uint32_t* s_tmp)
 {
@@ -653,10 +709,18 @@ __device__ __forceinline__ void tile3d(const TileArgs& a, int b, uint32_t* s_u, 
     const int rr = b / a.tiles_x;
     const int ty = rr % a.tiles_y;
     const int tz = rr / a.tiles_y;
-    if ((tx + 1) * 64 <= a.X && (ty + 1) * TY <= a.Y && (tz + 1) * TZ <= a.Z)
-        tile3d_body<MINMODE, TY, TZ, true>(a, b, s_u, s_conn, s_tmp);
-    else
-        tile3d_body<MINMODE, TY, TZ, false>(a, b, s_u, s_conn, s_tmp);
+    const bool full = (tx + 1) * 64 <= a.X && (ty + 1) * TY <= a.Y && (tz + 1) * TZ <= a.Z;
+    if (a.ptr) {
+        if (full)
+            tile3d_body<MINMODE, TY, TZ, true, true>(a, b, s_u, s_conn, s_tmp);
+        else
+            tile3d_body<MINMODE, TY, TZ, false, true>(a, b, s_u, s_conn, s_tmp);
+    } else {
+        if (full)
+            tile3d_body<MINMODE, TY, TZ, true, false>(a, b, s_u, s_conn, s_tmp);
+        else
+            tile3d_body<MINMODE, TY, TZ, false, false>(a, b, s_u, s_conn, s_tmp);
+    }
 }
 
 // Tiles of one XCD are consecutive in memory: workgroups are dispatched to

@@ -98,10 +98,13 @@ struct Conn3 {
     uint32_t w[(1 << 14) / 32];
 };
 
+// Bit m: an upper link with row mask m makes no saddle, i.e. it is empty
+// (a maximum) or a single component.
 constexpr Conn3 make_conn3()
 {
     constexpr Rows<3> r = make_rows_ce<3>();
     Conn3 c{};
+    c.w[0] = 1u;
     for (uint32_t m = 1; m < (1u << 14); ++m) {
         const uint64_t comp = closure_ce<3>(r, m & (~m + 1u), m);
         if (comp == m) c.w[m >> 5] |= 1u << (m & 31);
