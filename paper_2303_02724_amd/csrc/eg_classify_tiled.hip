@@ -72,21 +72,22 @@ struct Pack {
 // successor of this thread's k-th vertex (s_idx(k) is its tile index): in
 // [0, TILE) a tile index, >= TILE a tile-local maximum (TILE + its own index),
 // < 0 the tile-local code of the exit by which the path leaves the tile; the
-// last two end a chain.  Each round replaces every tile index by that vertex's successor, in
-// place: a value read is always a vertex further along the same path (or
-// its end), so a round needs no barrier between its reads and writes.  The
-// loop stops after the round in which every chain has reached its end (no
-// extra round to find that nothing changed); log2 of the longest in-tile path
-// bounds the rounds.  Must be called by the whole workgroup, after s_nxt
-// holds every successor.
+// last two end a chain.  Each round replaces every tile index by that
+// vertex's successor, in place.  Only the owning wave writes an entry, and
+// every value written is a vertex further along the same path (or its end),
+// so any value a wave reads, old or new, is a valid successor that moves its
+// chain forward.  Hence every wave runs its own rounds until its own chains
+// have ended, with no barrier (a wave that finishes early leaves final
+// entries behind); log2 of the longest in-tile path bounds the rounds.  Call
+// after a barrier that follows the last store to s_nxt.
 template <int VPT, int TILE, class Idx>
 __device__ __forceinline__ void double_tile_chains(int (&cur)[VPT], int32_t* s_nxt, Idx s_idx)
 {
-    int pending = 0;
+    bool pending = false;
 #pragma unroll
     for (int k = 0; k < VPT; ++k) pending |= (unsigned)cur[k] < (unsigned)TILE;
-    while (__syncthreads_or(pending)) {
-        pending = 0;
+    while (__ballot(pending) != 0) {
+        pending = false;
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
             const int n = cur[k];
@@ -178,14 +179,17 @@ __device__ __forceinline__ int exit_offset(int (&cur)[VPT], bool fit, uint32_t b
 // multiples of 64 along x).  Step k parks its maxima word in lane k and its
 // saddle word in lane 32 + k; at the end every lane stores at most one word,
 // so the masks cost one store instruction per wave and no atomics.
+// v_writelane_b32 (lane `lane` of a vector register takes a scalar value) and
+// v_bfe_u32 (which reads only the low five bits of the offset), as the
+// compiler's own intrinsics
+extern "C" __device__ int eg_writelane(int src, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+extern "C" __device__ uint32_t eg_ubfe(uint32_t src, uint32_t offset, uint32_t width) __asm("llvm.amdgcn.ubfe.i32");
+
 __device__ __forceinline__ void park_word(uint64_t& mine, bool pred, int lane)
 {
     const uint64_t b = __ballot(pred);
-    uint32_t lo = (uint32_t)mine, hi = (uint32_t)(mine >> 32);
-    if (__lane_id() == lane) {
-        lo = (uint32_t)b;
-        hi = (uint32_t)(b >> 32);
-    }
+    uint32_t lo = (uint32_t)eg_writelane((int)(uint32_t)b, lane, (int)(uint32_t)mine);
+    uint32_t hi = (uint32_t)eg_writelane((int)(uint32_t)(b >> 32), lane, (int)(uint32_t)(mine >> 32));
     // pin the word here: otherwise the selects sink to the final store and
     // every step's two ballots stay alive in scalar registers until then
     asm volatile("" : "+v"(lo), "+v"(hi));
@@ -639,7 +643,7 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
             // indexed by visiting step; the table marks the empty link as no
             // saddle, so a maximum needs no test of its own)
             const bool is_max = in && up == 0;
-            const bool is_sad = in && !((s_conn[up >> 5] >> (up & 31)) & 1u);
+            const bool is_sad = in && eg_ubfe(s_conn[up >> 5], up, 1u) == 0u;
             const uint32_t best_p = s_pack[best_st];
             const int row0 = gz * SZ + gy * SY + x0;  // uniform
             const int pv = row0 + lx + s_gdel[best_st];
