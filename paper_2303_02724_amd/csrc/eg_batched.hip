@@ -8,6 +8,7 @@
 namespace eg {
 
 constexpr int kBatchBlocksPerField = 48;
+constexpr int kBatchLateBlocksPerField = 2;
 
 __device__ __forceinline__ uint32_t rd(const uint32_t* p)
 {
@@ -120,12 +121,16 @@ hipError_t launch_batched_init(const BatchPlan* dplan, const BatchPlan& hplan, h
 hipError_t launch_batched_rest(const BatchPlan* dplan, const BatchPlan& hplan, hipStream_t s)
 {
     const dim3 grid(kBatchBlocksPerField, hplan.count);
+    // later passes run only when the pass before stopped short, which is
+    // rare: their launches mostly return at once, so they get small grids
+    const dim3 late(kBatchLateBlocksPerField, hplan.count);
     hipLaunchKernelGGL(k_bexit_init, grid, dim3(256), 0, s, dplan);
-    for (int p = 0; p < hplan.tuning.passes; ++p) hipLaunchKernelGGL(k_bexit_jump, grid, dim3(256), 0, s, dplan, p);
+    for (int p = 0; p < hplan.tuning.passes; ++p)
+        hipLaunchKernelGGL(k_bexit_jump, p == 0 ? grid : late, dim3(256), 0, s, dplan, p);
     // pass 0 in tile order, the rest linear (each gated by the pass before)
     hipError_t e = launch_final_tiled_batched(dplan, hplan, s);
     if (e != hipSuccess) return e;
-    for (int p = 1; p < hplan.tuning.passes; ++p) hipLaunchKernelGGL(k_bfinal, grid, dim3(256), 0, s, dplan, p);
+    for (int p = 1; p < hplan.tuning.passes; ++p) hipLaunchKernelGGL(k_bfinal, late, dim3(256), 0, s, dplan, p);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_arcs_batched(dplan, hplan, s);

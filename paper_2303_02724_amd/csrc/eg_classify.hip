@@ -469,14 +469,27 @@ __device__ __forceinline__ bool gate(const uint32_t* ctr, int flag_base, int pas
            __hip_atomic_load(&ctr[flag_base + pass - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
+// Both exit-list kernels take four consecutive entries per thread (one
+// 16-byte access, four independent gathers or chains in flight): the links
+// are latency-bound gathers, so more of them per thread hide more latency.
+// The list base is 16-byte aligned (the workspace is carved in 256-byte
+// steps).
 __global__ __launch_bounds__(256) void k_exit_init(const uint32_t* __restrict__ exits, int32_t* __restrict__ res,
                                                    const int32_t* __restrict__ lab, const uint32_t* __restrict__ ctr,
                                                    uint32_t cap)
 {
     const uint32_t req = __hip_atomic_load(&ctr[C_NEXIT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t n = req < cap ? req : cap;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        res[i] = lab[exits[i]];
+    const uint32_t nq = n >> 2;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint4* e4 = reinterpret_cast<const uint4*>(exits);
+    int4* r4 = reinterpret_cast<int4*>(res);
+    for (uint32_t q = t; q < nq; q += stride) {
+        const uint4 e = e4[q];
+        r4[q] = make_int4(lab[e.x], lab[e.y], lab[e.z], lab[e.w]);
+    }
+    if (t < (n & 3u)) res[(nq << 2) + t] = lab[exits[(nq << 2) + t]];
 }
 
 __global__ __launch_bounds__(256) void k_exit_jump(int32_t* res, const int32_t* __restrict__ lab, int N,
@@ -485,15 +498,28 @@ __global__ __launch_bounds__(256) void k_exit_jump(int32_t* res, const int32_t* 
     if (!gate(ctr, C_JUMP, pass)) return;
     const uint32_t req = __hip_atomic_load(&ctr[C_NEXIT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t n = req < cap ? req : cap;
+    const uint32_t nq = n >> 2;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    int4* r4 = reinterpret_cast<int4*>(res);
     bool notdone = false;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    for (uint32_t q = t; q < nq; q += stride) {
+        const int4 x = r4[q];
+        if ((x.x | x.y | x.z | x.w) >= 0) continue;  // all four final
+        int y0 = x.x, y1 = x.y, y2 = x.z, y3 = x.w;
+        for (int h = 0; (y0 < 0 || y1 < 0 || y2 < 0 || y3 < 0) && h < hops; ++h) {
+            if (y0 < 0) y0 = next_link(lab, res, N, y0);
+            if (y1 < 0) y1 = next_link(lab, res, N, y1);
+            if (y2 < 0) y2 = next_link(lab, res, N, y2);
+            if (y3 < 0) y3 = next_link(lab, res, N, y3);
+        }
+        r4[q] = make_int4(y0, y1, y2, y3);
+        notdone |= (y0 < 0) | (y1 < 0) | (y2 < 0) | (y3 < 0);
+    }
+    if (t < (n & 3u)) {
+        const uint32_t i = (nq << 2) + t;
         int x = res[i];
-        if (x >= 0) continue;
-        int h = 0;
-        do {
-            x = next_link(lab, res, N, x);
-            ++h;
-        } while (x < 0 && h < hops);
+        for (int h = 0; x < 0 && h < hops; ++h) x = next_link(lab, res, N, x);
         res[i] = x;
         notdone |= x < 0;
     }
@@ -546,11 +572,15 @@ hipError_t launch_labels(const Grid& g, int32_t* lab, const Work& w, const Tunin
     const int32_t N = g.N;
     if (reinterpret_cast<uintptr_t>(lab) & 15u) return hipErrorInvalidValue;
     const uint32_t cap = (uint32_t)w.cap_exit;
-    const int64_t ewant = (w.cap_exit + 255) / 256;
+    if ((reinterpret_cast<uintptr_t>(w.exits) | reinterpret_cast<uintptr_t>(w.exres)) & 15u)
+        return hipErrorInvalidValue;
+    const int64_t ewant = (w.cap_exit / 4 + 255) / 256;
     const int eblocks = (int)(ewant < 2048 ? (ewant > 0 ? ewant : 1) : 2048);
-    // later passes usually find their flag clear and return at once: smaller
-    // grids keep those launches cheap
-    const int eblocks_late = eblocks < 1024 ? eblocks : 1024;
+    // a later pass runs only when the pass before it stopped short, which
+    // the tiled grids' passes practically never do: most of these launches
+    // return at once, and small grids keep them cheap (a pass that does run
+    // then takes longer)
+    const int eblocks_late = eblocks < 128 ? eblocks : 128;
     // the first pass reads entries that other threads of the same pass have
     // already advanced, which shortens long chains: it needs every entry
     // initialised first
@@ -560,15 +590,19 @@ hipError_t launch_labels(const Grid& g, int32_t* lab, const Work& w, const Tunin
                            w.ctr, cap, p, tu.hops);
     const int64_t want = ((int64_t)N / 4 + 255) / 256;
     const int blocks = (int)(want < 2048 ? (want > 0 ? want : 1) : 2048);
+    const bool tiled = g.ndim == 2 || g.ndim == 3;
     int p = 0;
-    if (g.ndim == 2 || g.ndim == 3) {
+    if (tiled) {
         // pass 0 in tile order (the classification wrote exit-list codes)
         const hipError_t e = launch_final_tiled(g, lab, w, tu, C_FINAL, s);
         if (e != hipSuccess) return e;
         p = 1;
     }
+    // untiled grids resolve their vertex codes in these passes: full grids
+    const int blocks_late = tiled && blocks > 128 ? 128 : blocks;
     for (; p < tu.passes; ++p)
-        hipLaunchKernelGGL(k_final, dim3(blocks), dim3(256), 0, s, lab, w.exres, N, w.ctr, p, tu.hops);
+        hipLaunchKernelGGL(k_final, dim3(p == 0 ? blocks : blocks_late), dim3(256), 0, s, lab, w.exres, N, w.ctr, p,
+                           tu.hops);
     return hipGetLastError();
 }
 

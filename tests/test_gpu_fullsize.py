@@ -6,6 +6,7 @@ cores), plus the invariants every extremum graph has.
 * 512^3 Gaussian random field: both graphs, every launch configuration the
   autotuner chooses from (3D tile shape x links per label pass);
 * 32^5 Gaussian mixture (maxima): every pass length;
+* 16^6 Schwefel samples (maxima): every pass length;
 * the 256 batched fields, in one batch with exact-fit capacities as the
   benchmark runs them.
 """
@@ -82,6 +83,21 @@ def test_full_5d_32_every_pass_length():
     want = O.extremum_graph(f)
     for tu in tune.candidates(5):
         ctx = f"32^5 tuning={tu:#x}"
+        print(ctx, flush=True)
+        g = _graph(eg.build(t, want_ptr=True, tuning=tu))
+        assert_same(g, want, KEYS + ["ptr"], ctx)
+    _invariants(f, g, False)
+
+
+def test_full_6d_16_schwefel_every_pass_length():
+    """The 6D benchmark grid at its full size (16^6 = 16.8 M vertices): the
+    symmetric Schwefel samples have many exact ties and saddles joining many
+    maxima."""
+    f = W.field_6d(16)
+    t = torch.from_numpy(f).cuda()
+    want = O.extremum_graph(f)
+    for tu in tune.candidates(6):
+        ctx = f"16^6 tuning={tu:#x}"
         print(ctx, flush=True)
         g = _graph(eg.build(t, want_ptr=True, tuning=tu))
         assert_same(g, want, KEYS + ["ptr"], ctx)
