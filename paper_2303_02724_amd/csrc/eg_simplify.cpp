@@ -28,16 +28,55 @@
 // a saddle with at most two maxima whose initial cost is above the threshold
 // is never queued, since merges only raise such a saddle's maxima and its
 // cost cannot fall back (dropping entries above the threshold never changes a
-// decision about an entry at or below it).
+// decision about an entry at or below it).  An entry carries the saddle's
+// height and, for a saddle with two maxima (the common case), both maxima, so
+// the dependent loop reads neither the saddle table nor the arc rows for it:
+// only the union-find roots of its two maxima.  Every phase but that loop
+// (arc look-up, bundling, initial costs, the sort of the run, the output
+// rows) splits its items over the host's hardware threads; results do not
+// depend on the split.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <queue>
+#include <thread>
 #include <vector>
 
 #include "eg.h"
 
 namespace {
+
+// f(begin, end) over [0, n), split over up to 16 hardware threads when n is
+// large enough to pay for them.
+template <class F>
+void parallel_for(int64_t n, F&& f)
+{
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int T = n < 32768 ? 1 : (int)std::max(1u, std::min(hw, 16u));
+    if (T == 1) {
+        f((int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve((size_t)T);
+    for (int t = 0; t < T; ++t) th.emplace_back([&f, n, t, T] { f(n * t / T, n * (t + 1) / T); });
+    for (auto& x : th) x.join();
+}
+
+// f(t) for t in [0, T), one thread each.
+template <class F>
+void parallel_parts(int T, F&& f)
+{
+    if (T <= 1) {
+        f(0);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve((size_t)T);
+    for (int t = 0; t < T; ++t) th.emplace_back([&f, t] { f(t); });
+    for (auto& x : th) x.join();
+}
 
 struct Node {
     double h;  // height in the graph's direction
@@ -51,11 +90,16 @@ inline bool higher(const Node& a, const Node& b, bool minima)
     return minima ? a.id < b.id : a.id > b.id;
 }
 
+// Inside, maxima are numbered by height (rank 0 the lowest), so comparing two
+// maxima is comparing two integers; rank and inv map to and from the caller's
+// indices.
 struct Graph {
     bool minima;
     std::vector<Node> mx, sd;
+    std::vector<int32_t> rank, inv;
+    std::vector<double> hr;  // height by rank
     const int32_t* off;
-    std::vector<int32_t> arc;  // maxima indices
+    std::vector<int32_t> arc;  // maxima ranks
 };
 
 bool load(const eg_graph_host* g, Graph* G)
@@ -78,13 +122,38 @@ bool load(const eg_graph_host* g, Graph* G)
         if (g->arc_offsets[i + 1] < g->arc_offsets[i]) return false;
     const int64_t narc = g->arc_offsets[g->nsad];
     if (narc > 0 && !g->arc_maxima) return false;
-    G->arc.resize((size_t)narc);
-    for (int64_t k = 0; k < narc; ++k) {
-        const int32_t* p = std::lower_bound(g->maxima, g->maxima + g->nmax, g->arc_maxima[k]);
-        if (p == g->maxima + g->nmax || *p != g->arc_maxima[k]) return false;  // not a maximum
-        G->arc[(size_t)k] = (int32_t)(p - g->maxima);
+    const size_t nmax = G->mx.size();
+    {
+        struct Key {
+            Node n;
+            int32_t j;
+        };
+        std::vector<Key> k(nmax);
+        for (size_t j = 0; j < nmax; ++j) k[j] = Key{G->mx[j], (int32_t)j};
+        const bool minima = G->minima;
+        std::sort(k.begin(), k.end(), [minima](const Key& a, const Key& b) { return higher(b.n, a.n, minima); });
+        G->inv.resize(nmax);
+        for (size_t r = 0; r < nmax; ++r) G->inv[r] = k[r].j;
     }
-    return true;
+    G->rank.resize(nmax);
+    G->hr.resize(nmax);
+    for (size_t r = 0; r < nmax; ++r) {
+        G->rank[(size_t)G->inv[r]] = (int32_t)r;
+        G->hr[r] = G->mx[(size_t)G->inv[r]].h;
+    }
+    G->arc.resize((size_t)narc);
+    std::atomic<bool> bad{false};
+    parallel_for(narc, [&](int64_t k0, int64_t k1) {
+        for (int64_t k = k0; k < k1; ++k) {
+            const int32_t* p = std::lower_bound(g->maxima, g->maxima + g->nmax, g->arc_maxima[k]);
+            if (p == g->maxima + g->nmax || *p != g->arc_maxima[k]) {  // not a maximum
+                bad.store(true, std::memory_order_relaxed);
+                return;
+            }
+            G->arc[(size_t)k] = G->rank[(size_t)(p - g->maxima)];
+        }
+    });
+    return !bad.load();
 }
 
 // Distinct entries of a short row, in place (rows hold at most a few dozen).
@@ -102,48 +171,61 @@ int distinct(int32_t* ms, int n)
 // Saddles that survive bundling (flags per saddle).
 std::vector<char> bundle(const Graph& G)
 {
-    const size_t nsad = G.sd.size(), nmax = G.mx.size();
-    std::vector<char> keep(nsad, 0);
-    std::vector<int32_t> row;
+    const int64_t nsad = (int64_t)G.sd.size(), nmax = (int64_t)G.mx.size();
+    std::vector<char> keep((size_t)nsad, 0);
     // pass 1: pairs per lower maximum index; saddles no pair shares are kept
-    std::vector<int64_t> start(nmax + 1, 0);
-    for (size_t i = 0; i < nsad; ++i) {
-        row.assign(G.arc.begin() + G.off[i], G.arc.begin() + G.off[i + 1]);
-        const int k = distinct(row.data(), (int)row.size());
-        if (k < 2) keep[i] = 1;
-        for (int a = 0; a < k; ++a)
-            for (int b = 0; b < k; ++b)
-                if (row[(size_t)a] < row[(size_t)b]) ++start[(size_t)row[(size_t)a] + 1];
-    }
-    for (size_t j = 0; j < nmax; ++j) start[j + 1] += start[j];
+    std::vector<std::atomic<int64_t>> count((size_t)nmax + 1);
+    for (auto& c : count) c.store(0, std::memory_order_relaxed);
+    parallel_for(nsad, [&](int64_t i0, int64_t i1) {
+        std::vector<int32_t> row;
+        for (int64_t i = i0; i < i1; ++i) {
+            row.assign(G.arc.begin() + G.off[i], G.arc.begin() + G.off[i + 1]);
+            const int k = distinct(row.data(), (int)row.size());
+            if (k < 2) keep[(size_t)i] = 1;
+            for (int a = 0; a < k; ++a)
+                for (int b = 0; b < k; ++b)
+                    if (row[(size_t)a] < row[(size_t)b])
+                        count[(size_t)row[(size_t)a] + 1].fetch_add(1, std::memory_order_relaxed);
+        }
+    });
+    std::vector<int64_t> start((size_t)nmax + 1, 0);
+    for (int64_t j = 0; j < nmax; ++j) start[(size_t)j + 1] = start[(size_t)j] + count[(size_t)j + 1].load();
     // pass 2: (higher maximum, saddle) records bucketed by the lower maximum
-    std::vector<int32_t> other((size_t)start[nmax]), sad((size_t)start[nmax]);
-    std::vector<int64_t> fill(start.begin(), start.end() - 1);
-    for (size_t i = 0; i < nsad; ++i) {
-        row.assign(G.arc.begin() + G.off[i], G.arc.begin() + G.off[i + 1]);
-        const int k = distinct(row.data(), (int)row.size());
-        for (int a = 0; a < k; ++a)
-            for (int b = 0; b < k; ++b)
-                if (row[(size_t)a] < row[(size_t)b]) {
-                    const int64_t at = fill[(size_t)row[(size_t)a]]++;
-                    other[(size_t)at] = row[(size_t)b];
-                    sad[(size_t)at] = (int32_t)i;
-                }
-    }
+    // (the order inside a bucket does not matter: pass 3 takes a maximum)
+    std::vector<int32_t> other((size_t)start[(size_t)nmax]), sad((size_t)start[(size_t)nmax]);
+    std::vector<std::atomic<int64_t>> fill((size_t)nmax);
+    for (int64_t j = 0; j < nmax; ++j) fill[(size_t)j].store(start[(size_t)j], std::memory_order_relaxed);
+    parallel_for(nsad, [&](int64_t i0, int64_t i1) {
+        std::vector<int32_t> row;
+        for (int64_t i = i0; i < i1; ++i) {
+            row.assign(G.arc.begin() + G.off[i], G.arc.begin() + G.off[i + 1]);
+            const int k = distinct(row.data(), (int)row.size());
+            for (int a = 0; a < k; ++a)
+                for (int b = 0; b < k; ++b)
+                    if (row[(size_t)a] < row[(size_t)b]) {
+                        const int64_t at = fill[(size_t)row[(size_t)a]].fetch_add(1, std::memory_order_relaxed);
+                        other[(size_t)at] = row[(size_t)b];
+                        sad[(size_t)at] = (int32_t)i;
+                    }
+        }
+    });
     // pass 3: per lower maximum, the highest saddle of each higher partner
-    std::vector<int32_t> best(nmax, -1);
-    for (size_t a = 0; a < nmax; ++a) {
-        for (int64_t r = start[a]; r < start[a + 1]; ++r) {
-            int32_t& b = best[(size_t)other[(size_t)r]];
-            const int32_t s = sad[(size_t)r];
-            if (b < 0 || higher(G.sd[(size_t)s], G.sd[(size_t)b], G.minima)) b = s;
+    // (each thread its own scratch row over the partners)
+    parallel_for(nmax, [&](int64_t a0, int64_t a1) {
+        std::vector<int32_t> best((size_t)nmax, -1);
+        for (int64_t a = a0; a < a1; ++a) {
+            for (int64_t r = start[(size_t)a]; r < start[(size_t)a + 1]; ++r) {
+                int32_t& b = best[(size_t)other[(size_t)r]];
+                const int32_t s = sad[(size_t)r];
+                if (b < 0 || higher(G.sd[(size_t)s], G.sd[(size_t)b], G.minima)) b = s;
+            }
+            for (int64_t r = start[(size_t)a]; r < start[(size_t)a + 1]; ++r) {
+                int32_t& b = best[(size_t)other[(size_t)r]];
+                if (b >= 0) __atomic_store_n(&keep[(size_t)b], (char)1, __ATOMIC_RELAXED);
+                b = -1;
+            }
         }
-        for (int64_t r = start[a]; r < start[a + 1]; ++r) {
-            int32_t& b = best[(size_t)other[(size_t)r]];
-            if (b >= 0) keep[(size_t)b] = 1;
-            b = -1;
-        }
-    }
+    });
     return keep;
 }
 
@@ -161,24 +243,63 @@ struct UnionFind {
         }
         return m;
     }
+    // the same without path halving, for readers running side by side
+    int32_t root_const(int32_t m) const
+    {
+        while (parent[(size_t)m] != m) m = parent[(size_t)m];
+        return m;
+    }
 };
 
-// Distinct current maxima of saddle i, highest first (into ms); returns how many.
-int current_maxima(const Graph& G, UnionFind& U, int32_t i, std::vector<int32_t>& ms)
-{
-    ms.clear();
-    for (int32_t k = G.off[i]; k < G.off[i + 1]; ++k) ms.push_back(U.root(G.arc[(size_t)k]));
-    const int n = distinct(ms.data(), (int)ms.size());
-    ms.resize((size_t)n);
-    std::sort(ms.begin(), ms.end(),
-              [&](int32_t a, int32_t b) { return higher(G.mx[(size_t)a], G.mx[(size_t)b], G.minima); });
-    return n;
-}
-
+// A queue entry: the cost when queued, the saddle's height and id (for the
+// tie-break), the saddle, and for a saddle with two distinct maxima both of
+// them (m1 < 0 marks a saddle whose row must be read again).
 struct Entry {
     double cost;
+    double sh;
+    int32_t sid;
     int32_t sad;
+    int32_t m0, m1;
 };
+
+// Sort a run with the comparator `before`: chunks in parallel, then merged
+// pairwise in parallel rounds.
+template <class Cmp>
+void parallel_sort(std::vector<Entry>& v, Cmp before)
+{
+    const int64_t n = (int64_t)v.size();
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int T = n < 65536 ? 1 : (int)std::max(1u, std::min(hw, 16u));
+    if (T == 1) {
+        std::sort(v.begin(), v.end(), before);
+        return;
+    }
+    std::vector<int64_t> cut((size_t)T + 1);
+    for (int t = 0; t <= T; ++t) cut[(size_t)t] = n * t / T;
+    {
+        std::vector<std::thread> th;
+        for (int t = 0; t < T; ++t)
+            th.emplace_back([&, t] { std::sort(v.begin() + cut[(size_t)t], v.begin() + cut[(size_t)t + 1], before); });
+        for (auto& x : th) x.join();
+    }
+    std::vector<Entry> tmp((size_t)n);
+    std::vector<Entry>* src = &v;
+    std::vector<Entry>* dst = &tmp;
+    for (int width = 1; width < T; width *= 2) {
+        std::vector<std::thread> th;
+        for (int t = 0; t < T; t += 2 * width) {
+            const int64_t a = cut[(size_t)t], m = cut[(size_t)std::min(t + width, T)],
+                          b = cut[(size_t)std::min(t + 2 * width, T)];
+            th.emplace_back([=, &before] {
+                std::merge(src->begin() + a, src->begin() + m, src->begin() + m, src->begin() + b, dst->begin() + a,
+                           before);
+            });
+        }
+        for (auto& x : th) x.join();
+        std::swap(src, dst);
+    }
+    if (src != &v) v.swap(*src);
+}
 
 }  // namespace
 
@@ -198,25 +319,73 @@ extern "C" eg_status eg_simplify(const eg_graph_host* g, uint32_t ops, double th
     UnionFind U(G.mx.size());
     int64_t np = 0;
     if (ops & EG_SIMPLIFY_CANCEL) {
+        const bool minima = G.minima;
+        // saddle a strictly below saddle b, from the heights the entries carry
+        auto lower_sad = [minima](const Entry& a, const Entry& b) {
+            if (a.sh != b.sh) return a.sh < b.sh;
+            return minima ? a.sid > b.sid : a.sid < b.sid;
+        };
         // (cost, saddle order): lower costs first, lower saddles first among equal costs
         auto before = [&](const Entry& a, const Entry& b) {
             if (a.cost != b.cost) return a.cost < b.cost;
-            return higher(G.sd[(size_t)b.sad], G.sd[(size_t)a.sad], G.minima);
+            return lower_sad(a, b);
         };
         auto after = [&](const Entry& a, const Entry& b) { return before(b, a); };
-        std::vector<int32_t> ms;
-        // initial entries, one sorted run
+        // initial entries (no merges yet: every maximum is its own root), one
+        // sorted run; each thread fills its own part in saddle order
+        const unsigned hw = std::thread::hardware_concurrency();
+        const int T = nsad < 32768 ? 1 : (int)std::max(1u, std::min(hw, 16u));
+        std::vector<std::vector<Entry>> parts((size_t)T);
+        parallel_parts(T, [&](int t) {
+            {
+                std::vector<int32_t> ms;
+                std::vector<Entry>& out = parts[(size_t)t];
+                const int64_t i0 = (int64_t)nsad * t / T, i1 = (int64_t)nsad * (t + 1) / T;
+                for (int64_t i = i0; i < i1; ++i) {
+                    if (!live[(size_t)i]) continue;
+                    ms.assign(G.arc.begin() + G.off[i], G.arc.begin() + G.off[i + 1]);
+                    const int n = distinct(ms.data(), (int)ms.size());
+                    if (n < 2) continue;
+                    ms.resize((size_t)n);
+                    std::sort(ms.begin(), ms.end(), [](int32_t a, int32_t b) { return a > b; });
+                    const double cost = G.hr[(size_t)ms[1]] - G.sd[(size_t)i].h;
+                    if (n == 2 && cost > threshold) continue;  // can never become cheaper
+                    // two maxima inline; more: -(their count), placed after the sort
+                    out.push_back(Entry{cost, G.sd[(size_t)i].h, G.sd[(size_t)i].id, (int32_t)i, ms[0],
+                                        n == 2 ? ms[1] : -n});
+                }
+            }
+        });
         std::vector<Entry> run;
-        run.reserve(nsad);
-        for (size_t i = 0; i < nsad; ++i) {
-            if (!live[i]) continue;
-            const int n = current_maxima(G, U, (int32_t)i, ms);
-            if (n < 2) continue;
-            const double cost = G.mx[(size_t)ms[1]].h - G.sd[i].h;
-            if (n == 2 && cost > threshold) continue;  // can never become cheaper
-            run.push_back(Entry{cost, (int32_t)i});
+        {
+            size_t total = 0;
+            for (auto& p : parts) total += p.size();
+            run.reserve(total);
+            for (auto& p : parts) {
+                run.insert(run.end(), p.begin(), p.end());
+                std::vector<Entry>().swap(p);
+            }
         }
-        std::sort(run.begin(), run.end(), before);
+        parallel_sort(run, before);
+        // maxima of the saddles with more than two, copied in run order: the
+        // loop then reads them front to back (m0 becomes the offset)
+        std::vector<int32_t> many;
+        {
+            std::vector<int64_t> at(run.size() + 1, 0);
+            for (size_t r = 0; r < run.size(); ++r) at[r + 1] = at[r] + (run[r].m1 < 0 ? -run[r].m1 : 0);
+            many.resize((size_t)at[run.size()]);
+            parallel_for((int64_t)run.size(), [&](int64_t r0, int64_t r1) {
+                std::vector<int32_t> ms;
+                for (int64_t r = r0; r < r1; ++r) {
+                    Entry& e = run[(size_t)r];
+                    if (e.m1 >= 0) continue;
+                    ms.assign(G.arc.begin() + G.off[e.sad], G.arc.begin() + G.off[e.sad + 1]);
+                    const int n = distinct(ms.data(), (int)ms.size());
+                    std::copy(ms.begin(), ms.begin() + n, many.begin() + at[(size_t)r]);
+                    e.m0 = (int32_t)at[(size_t)r];
+                }
+            });
+        }
         std::priority_queue<Entry, std::vector<Entry>, decltype(after)> heap(after);  // reinserted entries
         size_t pos = 0;
         auto empty = [&]() { return pos == run.size() && heap.empty(); };
@@ -226,47 +395,102 @@ extern "C" eg_status eg_simplify(const eg_graph_host* g, uint32_t ops, double th
             return heap.top();
         };
         auto pop = [&]() {
-            if (pos < run.size() && (heap.empty() || before(run[pos], heap.top())))
-                ++pos;
-            else
+            Entry e;
+            if (pos < run.size() && (heap.empty() || before(run[pos], heap.top()))) {
+                e = run[pos++];
+            } else {
+                e = heap.top();
                 heap.pop();
+            }
+            return e;
         };
+        auto record = [&](int32_t i, int32_t m, double cost) {
+            pair_saddle[np] = i;
+            pair_max[np] = G.inv[(size_t)m];
+            pair_cost[np] = cost;
+            ++np;
+        };
+        std::vector<int32_t> ms;
+        constexpr size_t kAhead = 16;  // prefetch distance along the run
         while (!empty()) {
-            const int32_t i = top().sad;
-            pop();
-            const int n = current_maxima(G, U, i, ms);
+            if (pos + kAhead < run.size()) {
+                const Entry& f = run[pos + kAhead];
+                if (f.m1 >= 0) {
+                    __builtin_prefetch(&U.parent[(size_t)f.m0]);
+                    __builtin_prefetch(&U.parent[(size_t)f.m1]);
+                } else {
+                    __builtin_prefetch(&U.parent[(size_t)many[(size_t)f.m0]]);
+                }
+            }
+            Entry e = pop();
+            const int32_t i = e.sad;
+            if (e.m1 >= 0) {
+                // two maxima: their current roots are all the row can give
+                int32_t a = U.root(e.m0), b = U.root(e.m1);
+                if (a == b) continue;  // joins a single maximum now: no cost
+                if (b > a) std::swap(a, b);
+                const double cost = G.hr[(size_t)b] - e.sh;
+                if (cost > threshold) continue;  // discarded
+                if (!empty() && cost > top().cost) {  // the queue holds cheaper saddles
+                    e.cost = cost;
+                    heap.push(e);
+                    continue;
+                }
+                U.parent[(size_t)b] = a;
+                record(i, b, cost);
+                live[(size_t)i] = 0;  // the cancelled saddle leaves the graph
+                continue;
+            }
+            // more than two maxima: their current roots, distinct, highest first
+            ms.clear();
+            for (int k = 0; k < -e.m1; ++k) ms.push_back(U.root(many[(size_t)e.m0 + (size_t)k]));
+            const int n = distinct(ms.data(), (int)ms.size());
+            ms.resize((size_t)n);
+            std::sort(ms.begin(), ms.end(), [](int32_t a, int32_t b) { return a > b; });
             if (n < 2) continue;  // joins a single maximum now: no cost
-            const double cost = G.mx[(size_t)ms[1]].h - G.sd[(size_t)i].h;
+            const double cost = G.hr[(size_t)ms[1]] - e.sh;
             if (cost > threshold) continue;  // discarded
             if (!empty() && cost > top().cost) {  // the queue holds cheaper saddles
-                heap.push(Entry{cost, i});
+                e.cost = cost;
+                heap.push(e);
                 continue;
             }
             for (int k = 1; k < n; ++k) {  // all but the highest merge into it
                 U.parent[(size_t)ms[(size_t)k]] = ms[0];
-                pair_saddle[np] = i;
-                pair_max[np] = ms[(size_t)k];
-                pair_cost[np] = cost;
-                ++np;
+                record(i, ms[(size_t)k], cost);
             }
             live[(size_t)i] = 0;  // the cancelled saddle leaves the graph
         }
     }
     *n_pairs = np;
     // rows of the simplified graph: every live saddle, its distinct maxima
+    // (sizes first, then the rows, both in parallel)
+    std::vector<int32_t> len(nsad, 0);
+    auto row_of = [&](size_t i, std::vector<int32_t>& ms) {
+        ms.clear();
+        for (int32_t k = G.off[i]; k < G.off[i + 1]; ++k)
+            ms.push_back(G.mx[(size_t)G.inv[(size_t)U.root_const(G.arc[(size_t)k])]].id);
+        std::sort(ms.begin(), ms.end());
+        ms.erase(std::unique(ms.begin(), ms.end()), ms.end());
+    };
+    parallel_for((int64_t)nsad, [&](int64_t i0, int64_t i1) {
+        std::vector<int32_t> ms;
+        for (int64_t i = i0; i < i1; ++i)
+            if (live[(size_t)i]) {
+                row_of((size_t)i, ms);
+                len[(size_t)i] = (int32_t)ms.size();
+            }
+    });
     out_offsets[0] = 0;
-    int32_t at = 0;
-    std::vector<int32_t> ms;
-    for (size_t i = 0; i < nsad; ++i) {
-        if (live[i]) {
-            ms.clear();
-            for (int32_t k = G.off[i]; k < G.off[i + 1]; ++k) ms.push_back(G.mx[(size_t)U.root(G.arc[(size_t)k])].id);
-            std::sort(ms.begin(), ms.end());
-            ms.erase(std::unique(ms.begin(), ms.end()), ms.end());
-            for (int32_t m : ms) out_arcs[at++] = m;
-        }
-        out_offsets[i + 1] = at;
-    }
-    for (size_t j = 0; j < G.mx.size(); ++j) max_rep[j] = U.root((int32_t)j);
+    for (size_t i = 0; i < nsad; ++i) out_offsets[i + 1] = out_offsets[i] + len[i];
+    parallel_for((int64_t)nsad, [&](int64_t i0, int64_t i1) {
+        std::vector<int32_t> ms;
+        for (int64_t i = i0; i < i1; ++i)
+            if (live[(size_t)i]) {
+                row_of((size_t)i, ms);
+                std::copy(ms.begin(), ms.end(), out_arcs + out_offsets[i]);
+            }
+    });
+    for (size_t j = 0; j < G.mx.size(); ++j) max_rep[j] = G.inv[(size_t)U.root_const(G.rank[j])];
     return EG_OK;
 }
