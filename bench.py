@@ -275,18 +275,34 @@ def measure_streamed(f, tuning, minima, reps=7, slab=32):
     return out
 
 
-def measure_simplify(res, t, minima):
+def measure_simplify(res, t, minima, runs=3):
     """Graph simplification (host): arc bundling then persistence-directed
     cancellation at 5 % of the field's value range, as in the paper's
-    experiments."""
+    experiments.  ms_host is eg_simplify on the host copy of the graph (median
+    of `runs`); ms_gather the device gather of the critical values and the
+    copy of the graph to the host, once."""
+    import numpy as np
+    import torch
+
     from paper_2303_02724_amd import eg
 
     thr = 0.05 * float(t.max() - t.min())
+    flat = t.reshape(-1)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s = eg.simplify(res, t, threshold=thr, minima=minima)
-    ms = (time.perf_counter() - t0) * 1e3
+    host = (res.maxima.cpu().numpy(), flat[res.maxima.long()].cpu().numpy().astype(np.float64),
+            res.saddles.cpu().numpy(), flat[res.saddles.long()].cpu().numpy().astype(np.float64),
+            res.arc_offsets.cpu().numpy(), res.arc_maxima.cpu().numpy())
+    ms_gather = (time.perf_counter() - t0) * 1e3
+    ts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        s = eg.simplify_graph(*host, eg.SIMPLIFY_BUNDLE | eg.SIMPLIFY_CANCEL, thr, minima)
+        ts.append((time.perf_counter() - t0) * 1e3)
+    ms = sorted(ts)[len(ts) // 2]
     rows = s["arc_offsets"]
-    return {"ms_host": round(ms, 3), "threshold": thr, "cancellations": int(s["pair_saddle"].size),
+    return {"ms_host": round(ms, 3), "ms_gather": round(ms_gather, 3), "host_threads": os.cpu_count(),
+            "threshold": thr, "cancellations": int(s["pair_saddle"].size),
             "maxima_left": int((s["max_rep"] == range(s["max_rep"].size)).sum()),
             "saddles_left": int((rows[1:] > rows[:-1]).sum()), "arcs_left": int(rows[-1]),
             "maxima_in": int(res.maxima.numel()), "saddles_in": int(res.saddles.numel()),

@@ -7,6 +7,7 @@ cores), plus the invariants every extremum graph has.
   autotuner chooses from (3D tile shape x links per label pass);
 * 32^5 Gaussian mixture (maxima): every pass length;
 * 16^6 Schwefel samples (maxima): every pass length;
+* the 512^3 field built from pinned host memory in 32-plane slabs;
 * the 256 batched fields, in one batch with exact-fit capacities as the
   benchmark runs them.
 """
@@ -102,6 +103,16 @@ def test_full_6d_16_schwefel_every_pass_length():
         g = _graph(eg.build(t, want_ptr=True, tuning=tu))
         assert_same(g, want, KEYS + ["ptr"], ctx)
     _invariants(f, g, False)
+
+
+def test_full_512_streamed():
+    """The streamed build of the 512^3 field from pinned host memory, in the
+    slab height the benchmark times (32 planes), equals the oracle."""
+    f = W.field_3d_grf(512, seed=1)
+    host = torch.from_numpy(f).pin_memory()
+    want = O.extremum_graph(f)
+    g = _graph(eg.build_streamed(host, 32, want_ptr=True))
+    assert_same(g, want, KEYS + ["ptr"], "512^3 streamed, 32-plane slabs")
 
 
 def test_full_batched_256_fields():
