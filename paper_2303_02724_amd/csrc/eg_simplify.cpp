@@ -78,6 +78,45 @@ void parallel_parts(int T, F&& f)
     for (auto& x : th) x.join();
 }
 
+// Sort with the comparator `before`: chunks in parallel, then merged pairwise
+// in parallel rounds.
+template <class E, class Cmp>
+void parallel_sort(std::vector<E>& v, Cmp before)
+{
+    const int64_t n = (int64_t)v.size();
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int T = n < 65536 ? 1 : (int)std::max(1u, std::min(hw, 16u));
+    if (T == 1) {
+        std::sort(v.begin(), v.end(), before);
+        return;
+    }
+    std::vector<int64_t> cut((size_t)T + 1);
+    for (int t = 0; t <= T; ++t) cut[(size_t)t] = n * t / T;
+    {
+        std::vector<std::thread> th;
+        for (int t = 0; t < T; ++t)
+            th.emplace_back([&, t] { std::sort(v.begin() + cut[(size_t)t], v.begin() + cut[(size_t)t + 1], before); });
+        for (auto& x : th) x.join();
+    }
+    std::vector<E> tmp((size_t)n);
+    std::vector<E>* src = &v;
+    std::vector<E>* dst = &tmp;
+    for (int width = 1; width < T; width *= 2) {
+        std::vector<std::thread> th;
+        for (int t = 0; t < T; t += 2 * width) {
+            const int64_t a = cut[(size_t)t], m = cut[(size_t)std::min(t + width, T)],
+                          b = cut[(size_t)std::min(t + 2 * width, T)];
+            th.emplace_back([=, &before] {
+                std::merge(src->begin() + a, src->begin() + m, src->begin() + m, src->begin() + b, dst->begin() + a,
+                           before);
+            });
+        }
+        for (auto& x : th) x.join();
+        std::swap(src, dst);
+    }
+    if (src != &v) v.swap(*src);
+}
+
 struct Node {
     double h;  // height in the graph's direction
     int32_t id;
@@ -115,11 +154,16 @@ bool load(const eg_graph_host* g, Graph* G)
         G->mx[(size_t)j] = Node{sgn * (double)g->max_values[j], g->maxima[j]};
     }
     G->sd.resize((size_t)g->nsad);
-    for (int64_t i = 0; i < g->nsad; ++i) G->sd[(size_t)i] = Node{sgn * (double)g->sad_values[i], g->saddles[i]};
     G->off = g->arc_offsets;
     if (g->arc_offsets[0] != 0) return false;
-    for (int64_t i = 0; i < g->nsad; ++i)
-        if (g->arc_offsets[i + 1] < g->arc_offsets[i]) return false;
+    std::atomic<bool> bad{false};
+    parallel_for(g->nsad, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+            G->sd[(size_t)i] = Node{sgn * (double)g->sad_values[i], g->saddles[i]};
+            if (g->arc_offsets[i + 1] < g->arc_offsets[i]) bad.store(true, std::memory_order_relaxed);
+        }
+    });
+    if (bad.load()) return false;
     const int64_t narc = g->arc_offsets[g->nsad];
     if (narc > 0 && !g->arc_maxima) return false;
     const size_t nmax = G->mx.size();
@@ -131,7 +175,7 @@ bool load(const eg_graph_host* g, Graph* G)
         std::vector<Key> k(nmax);
         for (size_t j = 0; j < nmax; ++j) k[j] = Key{G->mx[j], (int32_t)j};
         const bool minima = G->minima;
-        std::sort(k.begin(), k.end(), [minima](const Key& a, const Key& b) { return higher(b.n, a.n, minima); });
+        parallel_sort(k, [minima](const Key& a, const Key& b) { return higher(b.n, a.n, minima); });
         G->inv.resize(nmax);
         for (size_t r = 0; r < nmax; ++r) G->inv[r] = k[r].j;
     }
@@ -142,11 +186,23 @@ bool load(const eg_graph_host* g, Graph* G)
         G->hr[r] = G->mx[(size_t)G->inv[r]].h;
     }
     G->arc.resize((size_t)narc);
-    std::atomic<bool> bad{false};
+    // arc endpoints to ranks: a bucket table over the top bits of the ids
+    // narrows each binary search to the maxima of one bucket
+    const int32_t top = nmax ? g->maxima[nmax - 1] : 0;
+    int shift = 0;
+    while (shift < 31 && (int64_t(top) >> shift) >= 65536) ++shift;
+    const int64_t nb = (int64_t(top) >> shift) + 2;
+    std::vector<int32_t> first((size_t)nb, (int32_t)nmax);
+    for (int64_t j = (int64_t)nmax - 1; j >= 0; --j) first[(size_t)(g->maxima[j] >> shift)] = (int32_t)j;
+    for (int64_t b = nb - 2; b >= 0; --b) first[(size_t)b] = std::min(first[(size_t)b], first[(size_t)b + 1]);
     parallel_for(narc, [&](int64_t k0, int64_t k1) {
         for (int64_t k = k0; k < k1; ++k) {
-            const int32_t* p = std::lower_bound(g->maxima, g->maxima + g->nmax, g->arc_maxima[k]);
-            if (p == g->maxima + g->nmax || *p != g->arc_maxima[k]) {  // not a maximum
+            const int32_t id = g->arc_maxima[k];
+            const int64_t b = id >= 0 && id <= top ? (int64_t(id) >> shift) : -1;
+            const int32_t* lo = g->maxima + (b >= 0 ? first[(size_t)b] : 0);
+            const int32_t* hi = g->maxima + (b >= 0 ? first[(size_t)b + 1] : 0);
+            const int32_t* p = std::lower_bound(lo, hi, id);
+            if (b < 0 || p == hi || *p != id) {  // not a maximum
                 bad.store(true, std::memory_order_relaxed);
                 return;
             }
@@ -261,45 +317,6 @@ struct Entry {
     int32_t sad;
     int32_t m0, m1;
 };
-
-// Sort a run with the comparator `before`: chunks in parallel, then merged
-// pairwise in parallel rounds.
-template <class Cmp>
-void parallel_sort(std::vector<Entry>& v, Cmp before)
-{
-    const int64_t n = (int64_t)v.size();
-    const unsigned hw = std::thread::hardware_concurrency();
-    const int T = n < 65536 ? 1 : (int)std::max(1u, std::min(hw, 16u));
-    if (T == 1) {
-        std::sort(v.begin(), v.end(), before);
-        return;
-    }
-    std::vector<int64_t> cut((size_t)T + 1);
-    for (int t = 0; t <= T; ++t) cut[(size_t)t] = n * t / T;
-    {
-        std::vector<std::thread> th;
-        for (int t = 0; t < T; ++t)
-            th.emplace_back([&, t] { std::sort(v.begin() + cut[(size_t)t], v.begin() + cut[(size_t)t + 1], before); });
-        for (auto& x : th) x.join();
-    }
-    std::vector<Entry> tmp((size_t)n);
-    std::vector<Entry>* src = &v;
-    std::vector<Entry>* dst = &tmp;
-    for (int width = 1; width < T; width *= 2) {
-        std::vector<std::thread> th;
-        for (int t = 0; t < T; t += 2 * width) {
-            const int64_t a = cut[(size_t)t], m = cut[(size_t)std::min(t + width, T)],
-                          b = cut[(size_t)std::min(t + 2 * width, T)];
-            th.emplace_back([=, &before] {
-                std::merge(src->begin() + a, src->begin() + m, src->begin() + m, src->begin() + b, dst->begin() + a,
-                           before);
-            });
-        }
-        for (auto& x : th) x.join();
-        std::swap(src, dst);
-    }
-    if (src != &v) v.swap(*src);
-}
 
 }  // namespace
 
