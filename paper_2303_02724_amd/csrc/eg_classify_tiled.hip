@@ -86,7 +86,9 @@ __device__ __forceinline__ void double_tile_chains(int (&cur)[VPT], int32_t* s_n
     bool pending = false;
 #pragma unroll
     for (int k = 0; k < VPT; ++k) pending |= (unsigned)cur[k] < (unsigned)TILE;
-    while (__ballot(pending) != 0) {
+    if (__ballot(pending) == 0) return;
+    // the test at the bottom keeps every cur[k] in one register across rounds
+    do {
         pending = false;
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
@@ -98,7 +100,7 @@ __device__ __forceinline__ void double_tile_chains(int (&cur)[VPT], int32_t* s_n
                 pending |= (unsigned)m < (unsigned)TILE;
             }
         }
-    }
+    } while (__ballot(pending) != 0);
 }
 
 // Every vertex whose steepest step leaves the tile gets its own entry of the
@@ -673,12 +675,10 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
 #pragma unroll
         for (int lz = 0; lz < TZ; ++lz) s_nxt[(lz * TY + wv + 4 * c) * TX + lx] = nxt[c * TZ + lz];
     __syncthreads();
-    // follow every chain inside the tile: entries >= 0 are tile-local
-    // successors (a maximum is its own successor), entries < 0 are
-    // -(id + 1) of the first vertex outside the tile
     // global offset of every tile row (lz, ly) from the tile's first vertex,
     // so that a tile index becomes a vertex id with one LDS read instead of
-    // two quarter-rate multiplies
+    // two quarter-rate multiplies; then every chain inside the tile is
+    // followed to its end (double_tile_chains names the three kinds of entry)
     __shared__ int s_rowoff[TY * TZ];
     if (tid < TY * TZ) s_rowoff[tid] = (tid / TY) * SZ + (tid % TY) * SY;
     double_tile_chains<VPT, TILE>(nxt, s_nxt, [&](int k) { return ((k % TZ) * TY + wv + 4 * (k / TZ)) * TX + lx; });
