@@ -518,6 +518,10 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
         // positions outside the grid get the sentinel key 0
         constexpr int ROWS = HY * HZ;
         constexpr int RPW = (ROWS + 3) / 4;
+        // every row index a wave takes exists when the rows split evenly
+        // (all the tile shapes here): the test then folds away instead of
+        // leaving a lane mask per row alive until the stores
+        constexpr bool EVEN = ROWS % 4 == 0;
         constexpr int EDGES = 2 * ROWS;
         static_assert(EDGES <= 256, "one edge value per thread");
         static_assert(RPW <= 32, "row flags fit a word");
@@ -533,9 +537,11 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
             const int row = wv + 4 * i;
             const int hy = row % HY, hz = row / HY;
             const int gy = y0 + hy - 1, gz = z0 + hz - 1;
-            const bool rin = row < ROWS && (unsigned)gy < (unsigned)Y && (unsigned)gz < (unsigned)Z;
-            rin_bits |= (rin ? 1u : 0u) << i;
-            const char* rowp = reinterpret_cast<const char*>(fb + (rin ? (int64_t)gz * SZ + (int64_t)gy * SY : 0));
+            rin_bits |= ((EVEN || row < ROWS) && (unsigned)gy < (unsigned)Y && (unsigned)gz < (unsigned)Z ? 1u : 0u) << i;
+            // rows outside the grid read a clamped row (their keys are
+            // replaced below): the address needs no per-row condition
+            const int gyc = min(max(gy, 0), Y - 1), gzc = min(max(gz, 0), Z - 1);
+            const char* rowp = reinterpret_cast<const char*>(fb + ((int64_t)gzc * SZ + (int64_t)gyc * SY));
             vals[i] = *reinterpret_cast<const uint32_t*>(rowp + lane_boff);
         }
         rin_bits = __builtin_amdgcn_readfirstlane(rin_bits);
@@ -554,7 +560,7 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
         for (int i = 0; i < RPW; ++i) {
             const int row = wv + 4 * i;
             const bool ok = ((rin_bits >> i) & 1u) && (FULL || xin);
-            if (row < ROWS) s_u[row * HX + lx + 1] = ok ? bits_key<MINMODE>(vals[i]) : 0u;
+            if (EVEN || row < ROWS) s_u[row * HX + lx + 1] = ok ? bits_key<MINMODE>(vals[i]) : 0u;
         }
         if (tid < EDGES) s_u[erow * HX + ((tid & 1) ? HX - 1 : 0)] = ein ? bits_key<MINMODE>(eval) : 0u;
     }
