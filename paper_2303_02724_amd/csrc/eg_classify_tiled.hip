@@ -398,23 +398,31 @@ __device__ __forceinline__ void store_row(int32_t* row, uint32_t lane_b, int32_t
     *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(row) + lane_b) = v;
 }
 
-// mode_key on the bit pattern: -0 folded into +0 by an integer test, the same
-// order-preserving flip and clamp (every vertex key is at least 1, so the
-// key 0 of positions outside the grid stays below all of them, NaN included:
-// no pointer can leave the grid).
 __device__ __forceinline__ uint32_t max3u(uint32_t a, uint32_t b, uint32_t c) { return max(max(a, b), c); }
 
+// An order-preserving key of the bit pattern, in four instructions: negative
+// values map to -b, the others to b | 2^31, so -0 and +0 meet at 2^31 and the
+// order of the numbers is kept (keys of the same value are equal, the index
+// decides); the top is clamped, so every vertex key lies in [1, 0xFFFFFFFE]
+// and the key 0 of positions outside the grid stays below all of them, NaN
+// included: no pointer can leave the grid.  The minimum graph takes the
+// complement.
 template <bool MINMODE>
 __device__ __forceinline__ uint32_t bits_key(uint32_t b)
 {
-    b = b == 0x80000000u ? 0u : b;
-    const uint32_t k = min(max(b ^ ((uint32_t)((int32_t)b >> 31) | 0x80000000u), 1u), 0xFFFFFFFEu);
+    const uint32_t m = (uint32_t)((int32_t)b >> 31);
+    const uint32_t k = min((b ^ (m | 0x80000000u)) - m, 0xFFFFFFFEu);
     return MINMODE ? ~k : k;
 }
 
-// Keys of numbers lie in [0x007FFFFF, 0xFF800000] in both graphs (-inf and
-// +inf at the ends); keys outside come from NaN patterns.
-__device__ __forceinline__ bool nan_key(uint32_t k) { return k < 0x007FFFFFu || k > 0xFF800000u; }
+// Keys of numbers lie in [0x00800000, 0xFF800000] (-inf and +inf at the
+// ends), complemented in the minimum graph; keys outside come from NaN
+// patterns.
+template <bool MINMODE>
+__device__ __forceinline__ bool nan_key(uint32_t k)
+{
+    return MINMODE ? (k < 0x007FFFFFu || k >= 0xFF800000u) : (k < 0x00800000u || k > 0xFF800000u);
+}
 
 // The key with its last four bits replaced by st (one instruction).
 template <int ST>
@@ -560,7 +568,8 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
         for (int i = 0; i < RPW; ++i) {
             const int row = wv + 4 * i;
             const bool ok = ((rin_bits >> i) & 1u) && (FULL || xin);
-            if (EVEN || row < ROWS) s_u[row * HX + lx + 1] = ok ? bits_key<MINMODE>(vals[i]) : 0u;
+            // one base address, the rows at immediate offsets from it
+            if (EVEN || row < ROWS) (s_u + wv * HX + lx + 1)[4 * i * HX] = ok ? bits_key<MINMODE>(vals[i]) : 0u;
         }
         if (tid < EDGES) s_u[erow * HX + ((tid & 1) ? HX - 1 : 0)] = ein ? bits_key<MINMODE>(eval) : 0u;
     }
@@ -601,7 +610,7 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
             const int gz = z0 + lz;
             const bool in = FULL || (gx < X && gy < Y && gz < Z);
             const uint32_t uv = win[(lz + 1) % 3][3];
-            nan |= in && nan_key(uv);
+            nan |= in && nan_key<MINMODE>(uv);
             // upper-link mask in two 7-row halves (bit constants stay inline)
             // upper-link mask: row 13 first, so that row j ends in bit j; each
             // row's comparison is the carry of an add that doubles the mask
