@@ -24,17 +24,18 @@
 //
 // Cost: bundling is linear in the number of (saddle, pair of maxima) records
 // (bucketed by the lower maximum, no comparison sort).  The queue holds the
-// initial entries as one sorted run plus a binary heap of reinserted entries;
-// a saddle with at most two maxima whose initial cost is above the threshold
-// is never queued, since merges only raise such a saddle's maxima and its
-// cost cannot fall back (dropping entries above the threshold never changes a
-// decision about an entry at or below it).  An entry carries the saddle's
-// height and, for a saddle with two maxima (the common case), both maxima, so
-// the dependent loop reads neither the saddle table nor the arc rows for it:
-// only the union-find roots of its two maxima.  Every phase but that loop
-// (arc look-up, bundling, initial costs, the sort of the run, the output
-// rows) splits its items over the host's hardware threads; results do not
-// depend on the split.
+// initial entries as one sorted run (a sample sort over the host's threads)
+// plus a binary heap of reinserted entries; a saddle with at most two maxima
+// whose initial cost is above the threshold is never queued, since merges
+// only raise such a saddle's maxima and its cost cannot fall back (dropping
+// entries above the threshold never changes a decision about an entry at or
+// below it).  An entry carries the saddle's height and, for a saddle with two
+// maxima (the common case), both maxima, so the dependent loop reads neither
+// the saddle table nor the arc rows for it: only the union-find roots of its
+// two maxima; a saddle with more than two needs only its two highest roots
+// unless it is cancelled.  Every phase but that loop (arc look-up, bundling,
+// initial costs, the sort of the run, the output rows) splits its items over
+// the host's hardware threads; results do not depend on the split.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -78,6 +79,34 @@ void parallel_parts(int T, F&& f)
     for (auto& x : th) x.join();
 }
 
+// Large working arrays are allocated without value-initialisation: their
+// first touch happens in the parallel loops that fill them, not in one
+// thread zeroing pages that are overwritten anyway.
+template <class T>
+struct NoInit : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = NoInit<U>;
+    };
+    NoInit() = default;
+    template <class U>
+    NoInit(const NoInit<U>&) noexcept
+    {
+    }
+    template <class U>
+    void construct(U* p) noexcept
+    {
+        ::new ((void*)p) U;
+    }
+    template <class U, class... A>
+    void construct(U* p, A&&... a)
+    {
+        ::new ((void*)p) U(std::forward<A>(a)...);
+    }
+};
+template <class T>
+using Buf = std::vector<T, NoInit<T>>;
+
 // Sort with the comparator `before`: chunks in parallel, then merged pairwise
 // in parallel rounds.
 template <class E, class Cmp>
@@ -117,6 +146,75 @@ void parallel_sort(std::vector<E>& v, Cmp before)
     if (src != &v) v.swap(*src);
 }
 
+// The entries of all parts as one run sorted by `before`, a strict total
+// order (so the run does not depend on how the parts were cut): a sample
+// sort.  Splitters come from regular samples of every part; each part's
+// thread finds every entry's bucket and then scatters its entries to their
+// bucket's range; each bucket is then sorted by a thread of its own.  The
+// parts are released on the way.
+template <class E, class Cmp>
+Buf<E> sorted_run(std::vector<std::vector<E>>& parts, Cmp before)
+{
+    const int T = (int)parts.size();
+    size_t total = 0;
+    for (auto& p : parts) total += p.size();
+    Buf<E> run(total);
+    if (T == 1 || total < 65536) {
+        size_t o = 0;
+        for (auto& p : parts) {
+            std::copy(p.begin(), p.end(), run.begin() + (int64_t)o);
+            o += p.size();
+            std::vector<E>().swap(p);
+        }
+        std::sort(run.begin(), run.end(), before);
+        return run;
+    }
+    constexpr int kSamples = 64;  // per part
+    std::vector<E> smp;
+    for (auto& p : parts)
+        for (int k = 0; k < kSamples && !p.empty(); ++k) smp.push_back(p[p.size() * (size_t)k / kSamples]);
+    std::sort(smp.begin(), smp.end(), before);
+    const int B = T;  // buckets (at most 16: one byte holds a bucket number)
+    std::vector<E> split;
+    for (int b = 1; b < B; ++b) split.push_back(smp[smp.size() * (size_t)b / (size_t)B]);
+    std::vector<std::vector<uint8_t>> bk((size_t)T);
+    std::vector<int64_t> cnt((size_t)T * (size_t)B, 0);
+    parallel_parts(T, [&](int t) {
+        const std::vector<E>& p = parts[(size_t)t];
+        std::vector<uint8_t>& k = bk[(size_t)t];
+        k.resize(p.size());
+        std::vector<int64_t> c((size_t)B, 0);
+        for (size_t r = 0; r < p.size(); ++r) {
+            const int b = (int)(std::upper_bound(split.begin(), split.end(), p[r], before) - split.begin());
+            k[r] = (uint8_t)b;
+            ++c[(size_t)b];
+        }
+        std::copy(c.begin(), c.end(), cnt.begin() + (int64_t)t * B);
+    });
+    // bucket b holds the entries of part 0, then part 1, ... that fall in it
+    std::vector<int64_t> at((size_t)T * (size_t)B), edge((size_t)B + 1);
+    int64_t o = 0;
+    for (int b = 0; b < B; ++b) {
+        edge[(size_t)b] = o;
+        for (int t = 0; t < T; ++t) {
+            at[(size_t)t * B + b] = o;
+            o += cnt[(size_t)t * B + b];
+        }
+    }
+    edge[(size_t)B] = o;
+    parallel_parts(T, [&](int t) {
+        std::vector<E>& p = parts[(size_t)t];
+        const std::vector<uint8_t>& k = bk[(size_t)t];
+        int64_t* a = &at[(size_t)t * B];
+        for (size_t r = 0; r < p.size(); ++r) run[(size_t)a[k[r]]++] = p[r];
+        std::vector<E>().swap(p);
+    });
+    parallel_parts(B, [&](int b) {
+        std::sort(run.begin() + edge[(size_t)b], run.begin() + edge[(size_t)b + 1], before);
+    });
+    return run;
+}
+
 struct Node {
     double h;  // height in the graph's direction
     int32_t id;
@@ -134,11 +232,12 @@ inline bool higher(const Node& a, const Node& b, bool minima)
 // indices.
 struct Graph {
     bool minima;
-    std::vector<Node> mx, sd;
+    std::vector<Node> mx;
+    Buf<Node> sd;
     std::vector<int32_t> rank, inv;
     std::vector<double> hr;  // height by rank
     const int32_t* off;
-    std::vector<int32_t> arc;  // maxima ranks
+    Buf<int32_t> arc;  // maxima ranks
 };
 
 bool load(const eg_graph_host* g, Graph* G)
@@ -224,59 +323,63 @@ int distinct(int32_t* ms, int n)
     return k;
 }
 
-// Saddles that survive bundling (flags per saddle).
+// Saddles that survive bundling (flags per saddle).  Every (lower maximum,
+// higher maximum, saddle) record goes to the part of the maxima range its
+// lower maximum falls in; each part is then grouped by lower maximum (a
+// counting sort) and, per lower maximum, the highest saddle of each higher
+// partner is kept.  No step shares a counter between threads.
 std::vector<char> bundle(const Graph& G)
 {
     const int64_t nsad = (int64_t)G.sd.size(), nmax = (int64_t)G.mx.size();
     std::vector<char> keep((size_t)nsad, 0);
-    // pass 1: pairs per lower maximum index; saddles no pair shares are kept
-    std::vector<std::atomic<int64_t>> count((size_t)nmax + 1);
-    for (auto& c : count) c.store(0, std::memory_order_relaxed);
-    parallel_for(nsad, [&](int64_t i0, int64_t i1) {
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int T = nsad < 32768 ? 1 : (int)std::max(1u, std::min(hw, 16u));
+    struct Rec {
+        int32_t a, b, s;  // lower and higher maximum (ranks), saddle
+    };
+    // part j holds the lower maxima a with j <= a T / nmax < j + 1
+    auto part_of = [&](int32_t a) { return (int)((int64_t)a * T / nmax); };
+    auto part_lo = [&](int j) { return (int32_t)(((int64_t)j * nmax + T - 1) / T); };
+    // records[t][j]: thread t's records of part j, in saddle order
+    std::vector<std::vector<std::vector<Rec>>> records((size_t)T, std::vector<std::vector<Rec>>((size_t)T));
+    parallel_parts(T, [&](int t) {
         std::vector<int32_t> row;
-        for (int64_t i = i0; i < i1; ++i) {
+        std::vector<std::vector<Rec>>& out = records[(size_t)t];
+        for (int64_t i = nsad * t / T; i < nsad * (t + 1) / T; ++i) {
             row.assign(G.arc.begin() + G.off[i], G.arc.begin() + G.off[i + 1]);
             const int k = distinct(row.data(), (int)row.size());
-            if (k < 2) keep[(size_t)i] = 1;
-            for (int a = 0; a < k; ++a)
-                for (int b = 0; b < k; ++b)
-                    if (row[(size_t)a] < row[(size_t)b])
-                        count[(size_t)row[(size_t)a] + 1].fetch_add(1, std::memory_order_relaxed);
+            if (k < 2) keep[(size_t)i] = 1;  // no pair shares it
+            for (int x = 0; x < k; ++x)
+                for (int y = 0; y < k; ++y)
+                    if (row[(size_t)x] < row[(size_t)y])
+                        out[(size_t)part_of(row[(size_t)x])].push_back(Rec{row[(size_t)x], row[(size_t)y], (int32_t)i});
         }
     });
-    std::vector<int64_t> start((size_t)nmax + 1, 0);
-    for (int64_t j = 0; j < nmax; ++j) start[(size_t)j + 1] = start[(size_t)j] + count[(size_t)j + 1].load();
-    // pass 2: (higher maximum, saddle) records bucketed by the lower maximum
-    // (the order inside a bucket does not matter: pass 3 takes a maximum)
-    std::vector<int32_t> other((size_t)start[(size_t)nmax]), sad((size_t)start[(size_t)nmax]);
-    std::vector<std::atomic<int64_t>> fill((size_t)nmax);
-    for (int64_t j = 0; j < nmax; ++j) fill[(size_t)j].store(start[(size_t)j], std::memory_order_relaxed);
-    parallel_for(nsad, [&](int64_t i0, int64_t i1) {
-        std::vector<int32_t> row;
-        for (int64_t i = i0; i < i1; ++i) {
-            row.assign(G.arc.begin() + G.off[i], G.arc.begin() + G.off[i + 1]);
-            const int k = distinct(row.data(), (int)row.size());
-            for (int a = 0; a < k; ++a)
-                for (int b = 0; b < k; ++b)
-                    if (row[(size_t)a] < row[(size_t)b]) {
-                        const int64_t at = fill[(size_t)row[(size_t)a]].fetch_add(1, std::memory_order_relaxed);
-                        other[(size_t)at] = row[(size_t)b];
-                        sad[(size_t)at] = (int32_t)i;
-                    }
+    parallel_parts(T, [&](int j) {
+        const int32_t lo = part_lo(j), hi = part_lo(j + 1);
+        // group the part's records by lower maximum
+        std::vector<int64_t> start((size_t)(hi - lo) + 1, 0);
+        for (int t = 0; t < T; ++t)
+            for (const Rec& r : records[(size_t)t][(size_t)j]) ++start[(size_t)(r.a - lo) + 1];
+        for (int32_t a = lo; a < hi; ++a) start[(size_t)(a - lo) + 1] += start[(size_t)(a - lo)];
+        std::vector<int64_t> fill(start.begin(), start.end() - 1);
+        std::vector<Rec> g((size_t)start.back());
+        for (int t = 0; t < T; ++t) {
+            std::vector<Rec>& v = records[(size_t)t][(size_t)j];
+            for (const Rec& r : v) g[(size_t)fill[(size_t)(r.a - lo)]++] = r;
+            std::vector<Rec>().swap(v);
         }
-    });
-    // pass 3: per lower maximum, the highest saddle of each higher partner
-    // (each thread its own scratch row over the partners)
-    parallel_for(nmax, [&](int64_t a0, int64_t a1) {
+        // per lower maximum, the highest saddle of each higher partner
         std::vector<int32_t> best((size_t)nmax, -1);
-        for (int64_t a = a0; a < a1; ++a) {
-            for (int64_t r = start[(size_t)a]; r < start[(size_t)a + 1]; ++r) {
-                int32_t& b = best[(size_t)other[(size_t)r]];
-                const int32_t s = sad[(size_t)r];
+        for (int32_t a = lo; a < hi; ++a) {
+            const int64_t r0 = start[(size_t)(a - lo)], r1 = start[(size_t)(a - lo) + 1];
+            for (int64_t r = r0; r < r1; ++r) {
+                int32_t& b = best[(size_t)g[(size_t)r].b];
+                const int32_t s = g[(size_t)r].s;
                 if (b < 0 || higher(G.sd[(size_t)s], G.sd[(size_t)b], G.minima)) b = s;
             }
-            for (int64_t r = start[(size_t)a]; r < start[(size_t)a + 1]; ++r) {
-                int32_t& b = best[(size_t)other[(size_t)r]];
+            for (int64_t r = r0; r < r1; ++r) {
+                int32_t& b = best[(size_t)g[(size_t)r].b];
                 if (b >= 0) __atomic_store_n(&keep[(size_t)b], (char)1, __ATOMIC_RELAXED);
                 b = -1;
             }
@@ -373,33 +476,35 @@ extern "C" eg_status eg_simplify(const eg_graph_host* g, uint32_t ops, double th
                 }
             }
         });
-        std::vector<Entry> run;
-        {
-            size_t total = 0;
-            for (auto& p : parts) total += p.size();
-            run.reserve(total);
-            for (auto& p : parts) {
-                run.insert(run.end(), p.begin(), p.end());
-                std::vector<Entry>().swap(p);
-            }
-        }
-        parallel_sort(run, before);
+        Buf<Entry> run = sorted_run(parts, before);
         // maxima of the saddles with more than two, copied in run order: the
         // loop then reads them front to back (m0 becomes the offset)
-        std::vector<int32_t> many;
+        Buf<int32_t> many;
         {
-            std::vector<int64_t> at(run.size() + 1, 0);
-            for (size_t r = 0; r < run.size(); ++r) at[r + 1] = at[r] + (run[r].m1 < 0 ? -run[r].m1 : 0);
-            many.resize((size_t)at[run.size()]);
-            parallel_for((int64_t)run.size(), [&](int64_t r0, int64_t r1) {
+            // each thread's chunk of the run: its share of the rows, then
+            // the rows at the chunk's offset
+            const int64_t nr = (int64_t)run.size();
+            const int TR = nr < 32768 ? 1 : T;
+            std::vector<int64_t> base((size_t)TR + 1, 0);
+            parallel_parts(TR, [&](int t) {
+                int64_t c = 0;
+                for (int64_t r = nr * t / TR; r < nr * (t + 1) / TR; ++r)
+                    c += run[(size_t)r].m1 < 0 ? -run[(size_t)r].m1 : 0;
+                base[(size_t)t + 1] = c;
+            });
+            for (int t = 0; t < TR; ++t) base[(size_t)t + 1] += base[(size_t)t];
+            many.resize((size_t)base[(size_t)TR]);
+            parallel_parts(TR, [&](int t) {
                 std::vector<int32_t> ms;
-                for (int64_t r = r0; r < r1; ++r) {
+                int64_t o = base[(size_t)t];
+                for (int64_t r = nr * t / TR; r < nr * (t + 1) / TR; ++r) {
                     Entry& e = run[(size_t)r];
                     if (e.m1 >= 0) continue;
                     ms.assign(G.arc.begin() + G.off[e.sad], G.arc.begin() + G.off[e.sad + 1]);
                     const int n = distinct(ms.data(), (int)ms.size());
-                    std::copy(ms.begin(), ms.begin() + n, many.begin() + at[(size_t)r]);
-                    e.m0 = (int32_t)at[(size_t)r];
+                    std::copy(ms.begin(), ms.begin() + n, many.begin() + o);
+                    e.m0 = (int32_t)o;
+                    o += n;
                 }
             });
         }
@@ -436,7 +541,7 @@ extern "C" eg_status eg_simplify(const eg_graph_host* g, uint32_t ops, double th
                     __builtin_prefetch(&U.parent[(size_t)f.m0]);
                     __builtin_prefetch(&U.parent[(size_t)f.m1]);
                 } else {
-                    __builtin_prefetch(&U.parent[(size_t)many[(size_t)f.m0]]);
+                    for (int k = 0; k < -f.m1; ++k) __builtin_prefetch(&U.parent[(size_t)many[(size_t)f.m0 + k]]);
                 }
             }
             Entry e = pop();
@@ -458,20 +563,33 @@ extern "C" eg_status eg_simplify(const eg_graph_host* g, uint32_t ops, double th
                 live[(size_t)i] = 0;  // the cancelled saddle leaves the graph
                 continue;
             }
-            // more than two maxima: their current roots, distinct, highest first
-            ms.clear();
-            for (int k = 0; k < -e.m1; ++k) ms.push_back(U.root(many[(size_t)e.m0 + (size_t)k]));
-            const int n = distinct(ms.data(), (int)ms.size());
-            ms.resize((size_t)n);
-            std::sort(ms.begin(), ms.end(), [](int32_t a, int32_t b) { return a > b; });
-            if (n < 2) continue;  // joins a single maximum now: no cost
-            const double cost = G.hr[(size_t)ms[1]] - e.sh;
+            // more than two maxima: the cost needs only the two highest of
+            // their current roots
+            const int32_t* mm = many.data() + e.m0;
+            int32_t r0 = -1, r1 = -1;
+            for (int k = 0; k < -e.m1; ++k) {
+                const int32_t r = U.root(mm[k]);
+                if (r > r0) {
+                    r1 = r0;
+                    r0 = r;
+                } else if (r < r0 && r > r1) {
+                    r1 = r;
+                }
+            }
+            if (r1 < 0) continue;  // joins a single maximum now: no cost
+            const double cost = G.hr[(size_t)r1] - e.sh;
             if (cost > threshold) continue;  // discarded
             if (!empty() && cost > top().cost) {  // the queue holds cheaper saddles
                 e.cost = cost;
                 heap.push(e);
                 continue;
             }
+            // cancelled: the distinct roots, highest first
+            ms.clear();
+            for (int k = 0; k < -e.m1; ++k) ms.push_back(U.root(mm[k]));
+            const int n = distinct(ms.data(), (int)ms.size());
+            ms.resize((size_t)n);
+            std::sort(ms.begin(), ms.end(), [](int32_t a, int32_t b) { return a > b; });
             for (int k = 1; k < n; ++k) {  // all but the highest merge into it
                 U.parent[(size_t)ms[(size_t)k]] = ms[0];
                 record(i, ms[(size_t)k], cost);
