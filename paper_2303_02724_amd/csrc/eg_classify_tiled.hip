@@ -69,10 +69,12 @@ struct Pack {
 // negative entries.
 
 // Resolve the tile's successor array by pointer jumping.  cur[k] holds the
-// successor of this thread's k-th vertex (s_idx(k) is its tile index): in
-// [0, TILE) a tile index, >= TILE a tile-local maximum (TILE + its own index),
-// < 0 the tile-local code of the exit by which the path leaves the tile; the
-// last two end a chain.  Each round replaces every tile index by that
+// successor of this thread's k-th vertex (s_idx(k) is its tile index), scaled
+// by UNIT (1: tile indices; 4: byte offsets into s_nxt, which spares the
+// address shift in every round): below UNIT TILE a vertex of the tile, at or
+// above it a tile-local maximum (UNIT (TILE + its own index)), < 0 the
+// tile-local code of the exit by which the path leaves the tile; the last two
+// end a chain.  Each round replaces every successor inside the tile by that
 // vertex's successor, in place.  Only the owning wave writes an entry, and
 // every value written is a vertex further along the same path (or its end),
 // so any value a wave reads, old or new, is a valid successor that moves its
@@ -80,24 +82,49 @@ struct Pack {
 // have ended, with no barrier (a wave that finishes early leaves final
 // entries behind); log2 of the longest in-tile path bounds the rounds.  Call
 // after a barrier that follows the last store to s_nxt.
-template <int VPT, int TILE, class Idx>
+template <int VPT, int TILE, int UNIT, class Idx>
 __device__ __forceinline__ void double_tile_chains(int (&cur)[VPT], int32_t* s_nxt, Idx s_idx)
 {
+    static_assert(UNIT == 1 || UNIT == 4, "tile indices or byte offsets");
+    constexpr unsigned END = (unsigned)TILE * UNIT;
     bool pending = false;
 #pragma unroll
-    for (int k = 0; k < VPT; ++k) pending |= (unsigned)cur[k] < (unsigned)TILE;
+    for (int k = 0; k < VPT; ++k) pending |= (unsigned)cur[k] < END;
     if (__ballot(pending) == 0) return;
+    if constexpr (UNIT == 4) {
+        // every round issues all its reads before it writes, with no branch:
+        // an entry that has ended reads its own slot, which holds its current
+        // value
+        do {
+            int m[VPT];
+#pragma unroll
+            for (int k = 0; k < VPT; ++k) {
+                const int n = cur[k];
+                const int at = (unsigned)n < END ? n : 4 * s_idx(k);
+                m[k] = *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(s_nxt) + at);
+            }
+            uint32_t lo = ~0u;
+#pragma unroll
+            for (int k = 0; k < VPT; ++k) {
+                cur[k] = m[k];
+                s_nxt[s_idx(k)] = m[k];
+                lo = min(lo, (uint32_t)m[k]);
+            }
+            pending = lo < END;
+        } while (__ballot(pending) != 0);
+        return;
+    }
     // the test at the bottom keeps every cur[k] in one register across rounds
     do {
         pending = false;
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
             const int n = cur[k];
-            if ((unsigned)n < (unsigned)TILE) {
+            if ((unsigned)n < END) {
                 const int m = s_nxt[n];
                 cur[k] = m;
                 s_nxt[s_idx(k)] = m;
-                pending |= (unsigned)m < (unsigned)TILE;
+                pending |= (unsigned)m < END;
             }
         }
     } while (__ballot(pending) != 0);
@@ -358,7 +385,7 @@ __device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u,
     // read per vertex instead of quarter-rate multiplies)
     __shared__ int s_rowoff[TY * TZ];
     if (tid < TY * TZ) s_rowoff[tid] = (tid / TY) * SZ + (tid % TY) * SY;
-    double_tile_chains<VPT, TILE>(nxt, s_nxt, s_idx);
+    double_tile_chains<VPT, TILE, 1>(nxt, s_nxt, s_idx);
     uint32_t base;
     const bool fit = place_exits(nexit, claim, s_u, s_tmp, a.exits, a.cap_exit, base);
     const int xoff = exit_offset<VPT>(nxt, fit, base, s_u, N);
@@ -386,9 +413,11 @@ __device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u,
 // the steepest candidate:
 //   bits 0..5   faces of the tile the step crosses if the vertex lies on them
 //               (x-, x+, y-, y+, z-, z+)
-//   bits 6..31  tile-local index offset (signed)
-// The vertex itself (a maximum) has no faces and the offset TILE, which turns
-// its own tile index into the chain end TILE + index.
+//   bits 6..31  tile-local offset in bytes of the chain array (signed)
+// The vertex itself (a maximum) has no faces and the offset 4 TILE, which
+// turns its own byte offset into the chain end 4 (TILE + index).  The 3D
+// chains hold byte offsets, so a doubling round reads its successor's entry
+// without an address shift.
 
 // Store to lane lx of a row whose first element sits at the uniform address
 // `row`: the address stays scalar and only the lane's byte offset lives in a
@@ -446,13 +475,24 @@ __device__ __forceinline__ uint32_t push_above(uint32_t up, uint32_t u, uint32_t
         asm("v_cmp_gt_u32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, %3, %3, vcc" : "=v"(r) : "v"(u), "v"(c), "v"(up) : "vcc");
     return r;
 }
+// The first row's comparison as the mask's lowest bit (no zero to double).
+template <bool WINS_TIE>
+__device__ __forceinline__ uint32_t first_above(uint32_t u, uint32_t c)
+{
+    uint32_t r;
+    if constexpr (WINS_TIE)
+        asm("v_cmp_ge_u32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, 0, 0, vcc" : "=v"(r) : "v"(u), "v"(c) : "vcc");
+    else
+        asm("v_cmp_gt_u32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, 0, 0, vcc" : "=v"(r) : "v"(u), "v"(c) : "vcc");
+    return r;
+}
 template <int TY, int HY, int HX>
 __device__ __forceinline__ constexpr uint32_t succ_pack(int dz, int dy, int dx)
 {
     const int loff = (dz * TY + dy) * 64 + dx;
     const uint32_t em = (dx < 0 ? 1u : 0u) | (dx > 0 ? 2u : 0u) | (dy < 0 ? 4u : 0u) | (dy > 0 ? 8u : 0u) |
                         (dz < 0 ? 16u : 0u) | (dz > 0 ? 32u : 0u);
-    return em | (uint32_t(loff) << 6);
+    return em | (uint32_t(4 * loff) << 6);
 }
 
 template <int NDIM_, int J>
@@ -502,7 +542,7 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
     if (tid <= K) {
         // entry st: the candidate visited at step st (the vertex itself at K / 2)
         const int pos = MINMODE ? K - tid : tid;
-        uint32_t pk = (uint32_t)TILE << 6;
+        uint32_t pk = (uint32_t)(4 * TILE) << 6;
         int gd = 0, ho = 0;
         if (pos != K / 2) {
             const int j = pos < K / 2 ? pos : pos - 1;
@@ -593,14 +633,19 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
         // window[p][q]: plane hz = lz + p, position q
         uint32_t win[3][7];
         auto load_plane = [&](uint32_t* w, int hz) {
-            const int base = (hz * HY + ly + 1) * HX + lx + 1;
-            w[0] = s_u[base - HX - 1];
-            w[1] = s_u[base - HX];
-            w[2] = s_u[base - 1];
-            w[3] = s_u[base];
-            w[4] = s_u[base + 1];
-            w[5] = s_u[base + HX];
-            w[6] = s_u[base + HX + 1];
+            // one opaque address per plane, at position (-1, -1): the seven
+            // reads lie within 2 HX + 2 words of it and pair into ds_read2
+            // without an address of their own
+            uint32_t boff = 4u * (uint32_t)((hz * HY + ly) * HX) + lane_b;
+            asm("" : "+v"(boff));
+            const uint32_t* p = reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(s_u) + boff);
+            w[0] = p[0];
+            w[1] = p[1];
+            w[2] = p[HX];
+            w[3] = p[HX + 1];
+            w[4] = p[HX + 2];
+            w[5] = p[2 * HX + 1];
+            w[6] = p[2 * HX + 2];
         };
         load_plane(win[0], 0);
         load_plane(win[1], 1);
@@ -611,7 +656,6 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
             const bool in = FULL || (gx < X && gy < Y && gz < Z);
             const uint32_t uv = win[(lz + 1) % 3][3];
             nan |= in && nan_key<MINMODE>(uv);
-            // upper-link mask in two 7-row halves (bit constants stay inline)
             // upper-link mask: row 13 first, so that row j ends in bit j; each
             // row's comparison is the carry of an add that doubles the mask
             uint32_t up = 0;
@@ -619,7 +663,10 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
                 constexpr int j = K - 1 - decltype(step)::value;
                 using WJ = Win<3, j>;
                 constexpr bool wins_tie = (j >= K / 2) != MINMODE;
-                up = push_above<wins_tie>(up, win[(lz + WJ::plane) % 3][WJ::pos], uv);
+                if constexpr (j == K - 1)
+                    up = first_above<wins_tie>(win[(lz + WJ::plane) % 3][WJ::pos], uv);
+                else
+                    up = push_above<wins_tie>(up, win[(lz + WJ::plane) % 3][WJ::pos], uv);
             });
             // steepest candidate: the maximum of (key with its last four bits
             // replaced by the visiting step), so that equal keys go to the
@@ -664,11 +711,11 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
             const uint32_t best_p = s_pack[best_st];
             const int row0 = gz * SZ + gy * SY + x0;  // uniform
             const int pv = row0 + lx + s_gdel[best_st];
-            const int li = (lz * TY + ly) * TX + lx;
+            const int li4 = 4 * ((lz * TY + ly) * TX) + (int)lane_b;  // byte offset in the chain array
             // leaves the tile iff it steps across a face the vertex lies on
             const uint32_t faces = bb_xy | (lz == 0 ? 16u : 0u) | (lz == TZ - 1 ? 32u : 0u);
-            int n = (faces & best_p & 63u) ? -(pv + 1) : li + ((int)best_p >> 6);
-            if constexpr (!FULL) n = in ? n : TILE + li;  // a vertex outside the grid ends its own chain
+            int n = (faces & best_p & 63u) ? -(pv + 1) : li4 + ((int)best_p >> 6);
+            if constexpr (!FULL) n = in ? n : 4 * TILE + li4;  // a vertex outside the grid ends its own chain
             if constexpr (PTR)
                 if (in) store_row(ptr + row0, lane_b, pv);
             nxt[c * TZ + lz] = n;
@@ -696,7 +743,8 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
     // followed to its end (double_tile_chains names the three kinds of entry)
     __shared__ int s_rowoff[TY * TZ];
     if (tid < TY * TZ) s_rowoff[tid] = (tid / TY) * SZ + (tid % TY) * SY;
-    double_tile_chains<VPT, TILE>(nxt, s_nxt, [&](int k) { return ((k % TZ) * TY + wv + 4 * (k / TZ)) * TX + lx; });
+    double_tile_chains<VPT, TILE, 4>(nxt, s_nxt,
+                                     [&](int k) { return ((k % TZ) * TY + wv + 4 * (k / TZ)) * TX + lx; });
     uint32_t base;
     const bool fit = place_exits(nexit, claim, s_u + TILE, s_tmp, a.exits, a.cap_exit, base);
     const int xoff = exit_offset<VPT>(nxt, fit, base, s_u + TILE, X * Y * Z);
@@ -711,9 +759,9 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
             const int n = nxt[c * TZ + lz];
             // the row offset is read for every vertex (masked into range), so
             // that the label is a select rather than a branch
-            const int ro = s_rowoff[((uint32_t)(n - TILE) >> 6) & (TY * TZ - 1)];
+            const int ro = s_rowoff[((uint32_t)(n - 4 * TILE) >> 8) & (TY * TZ - 1)];
             if (FULL || (gx < X && gy < Y && gz < Z))
-                store_row(lab + (gz * SZ + gy * SY + x0), lane_b, n >= 0 ? tile0 + ro + (n & 63) : n - xoff);
+                store_row(lab + (gz * SZ + gy * SY + x0), lane_b, n >= 0 ? tile0 + ro + ((n >> 2) & 63) : n - xoff);
         }
     }
 }
