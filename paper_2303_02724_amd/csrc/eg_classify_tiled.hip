@@ -580,17 +580,43 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
         const uint32_t lane_boff = 4u * (uint32_t)gxc;
         uint32_t vals[RPW];
         uint32_t rin_bits = 0;  // rows of this wave inside the grid (bit i)
+        // a tile whose halo rows all lie in the grid (most of them) steps
+        // through its rows by byte offsets from the halo's first row, four
+        // rows at a time, on the scalar unit: no per-row division, clamp,
+        // test or 64-bit address
+        const bool interior = EVEN && y0 >= 1 && z0 >= 1 && y0 + TY < Y && z0 + TZ < Z &&
+                              (int64_t)(TZ + 1) * SZ + (int64_t)(TY + 1) * SY + X < (int64_t(1) << 29);
+        if (interior) {
+            // a raw buffer at the halo's first row: the lane's byte offset in
+            // a vector register, the row's in a scalar one (offsets stay
+            // below 2^31 bytes, checked above)
+            const uint32_t* org = fb + ((int64_t)(z0 - 1) * SZ + (int64_t)(y0 - 1) * SY);
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(org), (short)0, 0x7fffffff, 0x00020000);
+            int hy = wv;
+            uint32_t off = 4u * (uint32_t)(wv * SY);
 #pragma unroll
-        for (int i = 0; i < RPW; ++i) {
-            const int row = wv + 4 * i;
-            const int hy = row % HY, hz = row / HY;
-            const int gy = y0 + hy - 1, gz = z0 + hz - 1;
-            rin_bits |= ((EVEN || row < ROWS) && (unsigned)gy < (unsigned)Y && (unsigned)gz < (unsigned)Z ? 1u : 0u) << i;
-            // rows outside the grid read a clamped row (their keys are
-            // replaced below): the address needs no per-row condition
-            const int gyc = min(max(gy, 0), Y - 1), gzc = min(max(gz, 0), Z - 1);
-            const char* rowp = reinterpret_cast<const char*>(fb + ((int64_t)gzc * SZ + (int64_t)gyc * SY));
-            vals[i] = *reinterpret_cast<const uint32_t*>(rowp + lane_boff);
+            for (int i = 0; i < RPW; ++i) {
+                vals[i] = __builtin_amdgcn_raw_buffer_load_b32(rs, lane_boff, off, 0);
+                const bool wrap = hy + 4 >= HY;
+                off += wrap ? 4u * (uint32_t)(SZ + (4 - HY) * SY) : 4u * (uint32_t)(4 * SY);
+                hy += wrap ? 4 - HY : 4;
+            }
+            rin_bits = RPW == 32 ? ~0u : (1u << RPW) - 1u;
+        } else {
+#pragma unroll
+            for (int i = 0; i < RPW; ++i) {
+                const int row = wv + 4 * i;
+                const int hy = row % HY, hz = row / HY;
+                const int gy = y0 + hy - 1, gz = z0 + hz - 1;
+                rin_bits |= ((EVEN || row < ROWS) && (unsigned)gy < (unsigned)Y && (unsigned)gz < (unsigned)Z ? 1u : 0u)
+                            << i;
+                // rows outside the grid read a clamped row (their keys are
+                // replaced below): the address needs no per-row condition
+                const int gyc = min(max(gy, 0), Y - 1), gzc = min(max(gz, 0), Z - 1);
+                const char* rowp = reinterpret_cast<const char*>(fb + ((int64_t)gzc * SZ + (int64_t)gyc * SY));
+                vals[i] = *reinterpret_cast<const uint32_t*>(rowp + lane_boff);
+            }
         }
         rin_bits = __builtin_amdgcn_readfirstlane(rin_bits);
         // edge value of this thread: row tid >> 1, left (x0 - 1) or right (x0 + 64)
