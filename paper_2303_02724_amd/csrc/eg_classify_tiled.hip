@@ -267,7 +267,41 @@ __device__ __forceinline__ void tile_nd(const TileArgs& a, int b, uint32_t* s_u,
     if constexpr (NDIM == 3)
         for (int i = tid; i < 512; i += 256) s_conn[i] = c_conn3.w[i];
     bool nan = false;
-    {
+    if constexpr (NDIM == 2) {
+        // rows of 64 aligned values, one per lane, from a uniform row address
+        // (rows outside the grid read a clamped row and are replaced), then
+        // the two edge columns of every row (one value per thread); all loads
+        // are issued before the first is used
+        constexpr int RPW = (HY + 3) / 4;
+        constexpr int EDGES = 2 * HY;
+        static_assert(EDGES <= 256, "one edge value per thread");
+        const int gx = x0 + lx;
+        const bool xin = gx < X;
+        const int gxc = xin ? gx : X - 1;
+        float vals[RPW];
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+            const int gy = y0 + wv + 4 * i - 1;
+            const int gyc = min(max(gy, 0), Y - 1);
+            vals[i] = f[(int64_t)gyc * SY + gxc];
+        }
+        const int erow = tid >> 1;
+        const int egx = (tid & 1) ? x0 + TX : x0 - 1;
+        const int egy = y0 + erow - 1;
+        const bool ein = tid < EDGES && (unsigned)egx < (unsigned)X && (unsigned)egy < (unsigned)Y;
+        const float eval = f[ein ? (int64_t)egy * SY + egx : 0];
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+            const int hy = wv + 4 * i;  // uniform
+            if (hy < HY) {
+                const int gy = y0 + hy - 1;
+                const bool ok = xin && (unsigned)gy < (unsigned)Y;
+                nan |= ok && hy >= 1 && hy <= TY && vals[i] != vals[i];
+                s_u[hy * HX + lx + 1] = ok ? mode_key<MINMODE>(vals[i]) : 0u;
+            }
+        }
+        if (tid < EDGES) s_u[erow * HX + ((tid & 1) ? HX - 1 : 0)] = ein ? mode_key<MINMODE>(eval) : 0u;
+    } else {
         constexpr int PER = (HALO + 255) / 256;
         float vals[PER];
         bool vin[PER];
@@ -589,7 +623,9 @@ __device__ __forceinline__ void tile3d_body(const TileArgs& a, int b, uint32_t* 
         if (interior) {
             // a raw buffer at the halo's first row: the lane's byte offset in
             // a vector register, the row's in a scalar one (offsets stay
-            // below 2^31 bytes, checked above)
+            // below 2^31 bytes, checked above, so the record limit 2^31 - 1
+            // never clips a load); the last descriptor word selects 32-bit
+            // data, as for any raw dword access on this architecture
             const uint32_t* org = fb + ((int64_t)(z0 - 1) * SZ + (int64_t)(y0 - 1) * SY);
             const __amdgpu_buffer_rsrc_t rs =
                 __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(org), (short)0, 0x7fffffff, 0x00020000);
