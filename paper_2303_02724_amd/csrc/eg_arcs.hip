@@ -581,8 +581,15 @@ __device__ __forceinline__ void arc_write_body(const ArcArgs& A, uint32_t blk, u
     }
 }
 
+// Four waves per SIMD for the 5D rows (the compiler's own choice, 133 and 143
+// registers, leaves three and stalls on the gathers; the few spilled values
+// cost less); 6D keeps its registers, since there the spills cost more.
+template <int NDIM>
+constexpr int kArcWaves = NDIM == 5 ? 4 : 1;
+
 template <int NDIM, bool MINMODE>
-__global__ __launch_bounds__(256) void k_arc_count(OneField sel)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kArcWaves<NDIM>, 8))) void k_arc_count(
+    OneField sel)
 {
     __shared__ Mask<NDIM> s_adj[Rows<NDIM>::K];
     __shared__ uint32_t tmp[4];
@@ -592,7 +599,8 @@ __global__ __launch_bounds__(256) void k_arc_count(OneField sel)
 }
 
 template <int NDIM, bool MINMODE>
-__global__ __launch_bounds__(256) void k_arc_write(OneField sel)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kArcWaves<NDIM>, 8))) void k_arc_write(
+    OneField sel)
 {
     __shared__ Mask<NDIM> s_adj[Rows<NDIM>::K];
     __shared__ uint32_t tmp[4];
@@ -639,7 +647,7 @@ __device__ __forceinline__ uint32_t key_of(const ArcArgs& A, int x)
 // pointers) ends the walk and returns false, so no input can make it leave
 // the grid or loop.
 template <bool MINMODE, class V>
-__device__ __forceinline__ bool walk(const ArcArgs& A, const EG_GPTR(const int32_t) ptr, int r, V&& visit)
+__device__ __forceinline__ bool walk(const ArcArgs& A, EG_GPTR(const int32_t) const ptr, int r, V&& visit)
 {
     visit(r);
     uint32_t ur = key_of<MINMODE>(A, r);
