@@ -581,9 +581,10 @@ __device__ __forceinline__ void arc_write_body(const ArcArgs& A, uint32_t blk, u
     }
 }
 
-// Four waves per SIMD for the 5D rows (the compiler's own choice, 133 and 143
-// registers, leaves three and stalls on the gathers; the few spilled values
-// cost less); 6D keeps its registers, since there the spills cost more.
+// Four waves per SIMD for the 5D rows, in the arc and the path kernels alike
+// (the compiler's own choice, 133 to 150 registers, leaves three and stalls
+// on the gathers; the few spilled values cost less); 6D keeps its registers,
+// since there the spills cost more.
 template <int NDIM>
 constexpr int kArcWaves = NDIM == 5 ? 4 : 1;
 
@@ -671,7 +672,8 @@ __global__ void k_path_reset(OneField sel)
 // Paths and path vertices of every saddle of the block's chunk (kept for the
 // write pass in the workspace), block sums into rows 0 and 1.
 template <int NDIM, bool MINMODE>
-__global__ __launch_bounds__(256) void k_path_count(OneField sel, PathArgs P)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kArcWaves<NDIM>, 8))) void k_path_count(
+    OneField sel, PathArgs P)
 {
     __shared__ Mask<NDIM> s_adj[Rows<NDIM>::K];
     __shared__ uint32_t tmp[4];
@@ -710,7 +712,8 @@ __global__ __launch_bounds__(256) void k_path_count(OneField sel, PathArgs P)
 }
 
 template <int NDIM, bool MINMODE>
-__global__ __launch_bounds__(256) void k_path_write(OneField sel, PathArgs P)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kArcWaves<NDIM>, 8))) void k_path_write(
+    OneField sel, PathArgs P)
 {
     __shared__ Mask<NDIM> s_adj[Rows<NDIM>::K];
     __shared__ uint32_t tmp[4];
