@@ -337,15 +337,24 @@ __global__ __launch_bounds__(256) void k_classify_slab(const uint32_t* __restric
             };
             // the upper-link mask, and the highest key of the closed
             // neighbourhood (rows outside the grid hold key 0 < uv)
-            Mask<NDIM> up = 0;
+            // 32 rows per word, pushed from the highest row down so that row
+            // j ends in bit j % 32 of word j / 32 (two instructions a row)
+            constexpr int NW = (K + 31) / 32;
+            uint32_t wd[NW];
             uint32_t top = uv;
-#pragma unroll
-            for (int j = 0; j < K; ++j) {
+            static_for<0, K>([&](auto step) {
+                constexpr int j = K - 1 - decltype(step)::value;
+                constexpr bool wins = (j >= K / 2) != MINMODE;
                 const uint32_t u = key(j);
-                const bool above = row_wins_tie<MINMODE>(j, K) ? (u >= uv) : (u > uv);
-                up |= Mask<NDIM>(above) << j;
+                if constexpr (j == K - 1 || j % 32 == 31)
+                    wd[j / 32] = first_above<wins>(u, uv);
+                else
+                    wd[j / 32] = push_above<wins>(wd[j / 32], u, uv);
                 top = max(top, u);
-            }
+            });
+            Mask<NDIM> up = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) up |= Mask<NDIM>(wd[w]) << (32 * w);
             // the steepest target: the last vertex holding `top` in the order
             // in which later vertices win ties (v itself between the halves)
             int best_j = -1;

@@ -45,15 +45,6 @@ struct Row {
     static constexpr int dx = R.d[J][NDIM - 1];
 };
 
-template <int I, int N, class F>
-__device__ __forceinline__ void static_for(F&& f)
-{
-    if constexpr (I < N) {
-        f(std::integral_constant<int, I>{});
-        static_for<I + 1, N>(f);
-    }
-}
-
 template <int NDIM>
 struct Pack {
     static_assert(NDIM <= 3, "two bits per row must fit 32 bits");
@@ -496,30 +487,6 @@ __device__ __forceinline__ uint32_t bucket_step(uint32_t u)
     return r;
 }
 
-// up = 2 up + (u above c): the comparison's lane mask is the carry of an add
-// that doubles the mask, two instructions per row; a neighbour that wins ties
-// is above at equal keys.
-template <bool WINS_TIE>
-__device__ __forceinline__ uint32_t push_above(uint32_t up, uint32_t u, uint32_t c)
-{
-    uint32_t r;
-    if constexpr (WINS_TIE)
-        asm("v_cmp_ge_u32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, %3, %3, vcc" : "=v"(r) : "v"(u), "v"(c), "v"(up) : "vcc");
-    else
-        asm("v_cmp_gt_u32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, %3, %3, vcc" : "=v"(r) : "v"(u), "v"(c), "v"(up) : "vcc");
-    return r;
-}
-// The first row's comparison as the mask's lowest bit (no zero to double).
-template <bool WINS_TIE>
-__device__ __forceinline__ uint32_t first_above(uint32_t u, uint32_t c)
-{
-    uint32_t r;
-    if constexpr (WINS_TIE)
-        asm("v_cmp_ge_u32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, 0, 0, vcc" : "=v"(r) : "v"(u), "v"(c) : "vcc");
-    else
-        asm("v_cmp_gt_u32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, 0, 0, vcc" : "=v"(r) : "v"(u), "v"(c) : "vcc");
-    return r;
-}
 template <int TY, int HY, int HX>
 __device__ __forceinline__ constexpr uint32_t succ_pack(int dz, int dy, int dx)
 {

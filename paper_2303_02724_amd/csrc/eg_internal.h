@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 #include "eg.h"
 
 namespace eg {
@@ -255,6 +257,42 @@ template <bool MINMODE>
 __device__ __forceinline__ bool row_wins_tie(int j, int k)
 {
     return (j >= k / 2) != MINMODE;
+}
+
+// f(std::integral_constant<int, i>) for i in [I, N): compile-time row indices.
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+// Upper-link masks, one 32-bit word per 32 rows, built from the highest row
+// down: up = 2 up + (u above c), where the comparison's lane mask is the carry
+// of an add that doubles the word (two instructions per row); a row that wins
+// ties is above at equal keys.
+template <bool WINS_TIE>
+__device__ __forceinline__ uint32_t push_above(uint32_t up, uint32_t u, uint32_t c)
+{
+    uint32_t r;
+    if constexpr (WINS_TIE)
+        asm("v_cmp_ge_u32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, %3, %3, vcc" : "=v"(r) : "v"(u), "v"(c), "v"(up) : "vcc");
+    else
+        asm("v_cmp_gt_u32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, %3, %3, vcc" : "=v"(r) : "v"(u), "v"(c), "v"(up) : "vcc");
+    return r;
+}
+// The first row's comparison as the mask's lowest bit (no zero to double).
+template <bool WINS_TIE>
+__device__ __forceinline__ uint32_t first_above(uint32_t u, uint32_t c)
+{
+    uint32_t r;
+    if constexpr (WINS_TIE)
+        asm("v_cmp_ge_u32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, 0, 0, vcc" : "=v"(r) : "v"(u), "v"(c) : "vcc");
+    else
+        asm("v_cmp_gt_u32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, 0, 0, vcc" : "=v"(r) : "v"(u), "v"(c) : "vcc");
+    return r;
 }
 
 // ------------------------------------------------------------------ launchers
