@@ -48,6 +48,20 @@ def test_library_simplify_equals_reference(shape, kind):
                 _compare(g, ops, t, minima, f"{shape} {kind} minima={minima} ops={ops} t={t}")
 
 
+def test_library_simplify_equals_reference_threaded():
+    # 82 k saddles and 26 k maxima: enough that every phase but the
+    # dependent loop splits over threads (bundling by maxima ranges, the
+    # sample sort of the queue's run, the rows of multi-saddles)
+    f = W.random_field((72, 72, 72), 5, "uniform")
+    for minima in (False, True):
+        g = _graph(f, minima)
+        assert len(g[2]) > 65536
+        costs = [c for _, _, c in S.cancel(*g, np.inf, minima)[3]]
+        for ops in (eg.SIMPLIFY_CANCEL, eg.SIMPLIFY_BUNDLE | eg.SIMPLIFY_CANCEL):
+            for t in (float(np.quantile(costs, 0.3)), np.inf):
+                _compare(g, ops, t, minima, f"72^3 minima={minima} ops={ops} t={t}")
+
+
 def test_library_simplify_rejects_bad_graphs():
     g = _graph(W.random_field((20, 20), 3), False)
     maxima, mv, sad, sv, offs, arcs = g
