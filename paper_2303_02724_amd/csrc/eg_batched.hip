@@ -36,13 +36,33 @@ __global__ __launch_bounds__(256) void k_binit(const BatchPlan* __restrict__ pla
 
 // ------------------------------------------------------------------ labels
 
+// Both exit-list kernels take four consecutive entries per thread when the
+// field's list and results are 16-byte aligned (one 16-byte access, four
+// independent gathers or chains in flight), as the single-field kernels do.
+__device__ __forceinline__ bool aligned16(const void* a, const void* b)
+{
+    return ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15u) == 0;
+}
+
 __global__ __launch_bounds__(256) void k_bexit_init(const BatchPlan* __restrict__ plan)
 {
     const BatchField F = plan->fields[blockIdx.y];  // a copy: loop loads cannot alias it
     const uint32_t req = rd(&F.ta.ctr[C_NEXIT]);
     const uint32_t n = req < F.ta.cap_exit ? req : F.ta.cap_exit;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        F.exres[i] = F.ta.lab[F.ta.exits[i]];
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+    const int32_t* lab = F.ta.lab;
+    uint32_t done = 0;
+    if (aligned16(F.ta.exits, F.exres)) {
+        const uint32_t nq = n >> 2;
+        const uint4* e4 = reinterpret_cast<const uint4*>(F.ta.exits);
+        int4* r4 = reinterpret_cast<int4*>(F.exres);
+        for (uint32_t q = t; q < nq; q += stride) {
+            const uint4 e = e4[q];
+            r4[q] = make_int4(lab[e.x], lab[e.y], lab[e.z], lab[e.w]);
+        }
+        done = nq << 2;
+    }
+    for (uint32_t i = done + t; i < n; i += stride) F.exres[i] = lab[F.ta.exits[i]];
 }
 
 __global__ __launch_bounds__(256) void k_bexit_jump(const BatchPlan* __restrict__ plan, int pass)
@@ -55,8 +75,28 @@ __global__ __launch_bounds__(256) void k_bexit_jump(const BatchPlan* __restrict_
     const int32_t* lab = F.ta.lab;
     int32_t* res = F.exres;
     const int hops = plan->tuning.hops;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
     bool notdone = false;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    uint32_t done = 0;
+    if (aligned16(F.ta.exits, res)) {
+        const uint32_t nq = n >> 2;
+        int4* r4 = reinterpret_cast<int4*>(res);
+        for (uint32_t q = t; q < nq; q += stride) {
+            const int4 x = r4[q];
+            if ((x.x | x.y | x.z | x.w) >= 0) continue;  // all four final
+            int y0 = x.x, y1 = x.y, y2 = x.z, y3 = x.w;
+            for (int h = 0; (y0 < 0 || y1 < 0 || y2 < 0 || y3 < 0) && h < hops; ++h) {
+                if (y0 < 0) y0 = next_link_b(lab, res, N, y0);
+                if (y1 < 0) y1 = next_link_b(lab, res, N, y1);
+                if (y2 < 0) y2 = next_link_b(lab, res, N, y2);
+                if (y3 < 0) y3 = next_link_b(lab, res, N, y3);
+            }
+            r4[q] = make_int4(y0, y1, y2, y3);
+            notdone |= (y0 < 0) | (y1 < 0) | (y2 < 0) | (y3 < 0);
+        }
+        done = nq << 2;
+    }
+    for (uint32_t i = done + t; i < n; i += stride) {
         int x = res[i];
         if (x >= 0) continue;
         int h = 0;
