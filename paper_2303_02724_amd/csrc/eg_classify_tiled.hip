@@ -852,13 +852,15 @@ __device__ __forceinline__ void final_tile(const TileArgs& a, int b, const int32
     bool notdone = false;
     int vid[VPT], x[VPT];
     // every load of the thread first, then the exit-list look-ups, then the
-    // stores: loads and stores of the same array would otherwise serialise
+    // stores: loads and stores of the same array would otherwise serialise;
+    // the codes and labels stream through once, so both bypass the caches'
+    // normal retention (the exit list stays cached for the look-ups)
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
         const int gy = ty * TY + wv + 4 * (k / TZ), gz = tz * TZ + (k % TZ);
         const bool in = gx < X && gy < Y && gz < Z;
         vid[k] = in ? gz * SZ + gy * SY + gx : -1;
-        x[k] = in ? lab[vid[k]] : 0;
+        x[k] = in ? __builtin_nontemporal_load(&lab[vid[k]]) : 0;
     }
 #pragma unroll
     for (int k = 0; k < VPT; ++k)
@@ -874,7 +876,7 @@ __device__ __forceinline__ void final_tile(const TileArgs& a, int b, const int32
     }
 #pragma unroll
     for (int k = 0; k < VPT; ++k)
-        if (vid[k] >= 0) lab[vid[k]] = x[k];
+        if (vid[k] >= 0) __builtin_nontemporal_store(x[k], &lab[vid[k]]);
     if (__ballot(notdone) != 0 && __lane_id() == 0) atomicOr(flag, 1u);
 }
 
